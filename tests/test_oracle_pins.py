@@ -1,0 +1,519 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+known-answer values, closed forms derived from the paper's equations,
+brute-force enumeration on tiny inputs, invariants and textbook limits.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from helpers import min_image_brute, oracle_from_workload, random_frozen_system
+from oracle import OracleSystem, Reaction
+from oracle.dybond import OracleError, resolve_rates
+from oracle.philox import box_muller3, philox4x32_10, reaction_order, u53
+from paper_2609_21204_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ Philox
+def test_philox_known_answers():
+    """Philox4x32-10 against the published known-answer vectors (Salmon et al. 2011)."""
+    rows = 0
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(t, 16) for t in line.split()]
+        out = philox4x32_10(*w[0:4], *w[4:6])
+        assert [int(o) for o in out] == w[6:10]
+        rows += 1
+    assert rows == 3
+
+
+def test_uniform_and_gaussian_conversions():
+    c = np.arange(200000, dtype=np.uint64)
+    w = philox4x32_10(7, 0, c, 0, 123, 456)
+    u = u53(w[0], w[1])
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert abs(u.mean() - 0.5) < 4 * math.sqrt(1 / 12 / len(u))
+    assert stats.kstest(u, "uniform").pvalue > 1e-4
+    g = np.concatenate(box_muller3(*w))
+    assert abs(g.mean()) < 4 / math.sqrt(len(g))
+    assert abs(g.var() - 1.0) < 4 * math.sqrt(2 / len(g))
+    assert stats.kstest(g, "norm").pvalue > 1e-4
+
+
+def test_reaction_order_is_uniform_permutation():
+    counts = {}
+    for s in range(1, 6001):
+        o = tuple(reaction_order(99, s, 3))
+        assert sorted(o) == [0, 1, 2]
+        counts[o] = counts.get(o, 0) + 1
+    assert len(counts) == 6
+    chi2 = sum((v - 1000.0) ** 2 / 1000.0 for v in counts.values())
+    assert chi2 < stats.chi2.ppf(1 - 1e-4, 5)
+    assert reaction_order(1, 5, 1) == [0]
+
+
+# ---------------------------------------------------------- neighbour search
+def test_pair_search_matches_brute_force():
+    rng = np.random.default_rng(3)
+    L = 4.0
+    for trial in range(5):
+        n = 70
+        x = rng.uniform(-L / 2, L / 2, (n, 3)).astype(np.float32).astype(np.float64)
+        # push a few particles onto the faces so that pairs straddle the boundary
+        x[:6, trial % 3] = np.float32(L / 2 - 1e-3)
+        x[6:12, trial % 3] = np.float32(-L / 2)
+        o = OracleSystem(n, 1, L, 1)
+        for cut in (0.9, 1.3, 1.9):
+            i, j, _, r = o.pairs_within(x, cut)
+            got = {(int(a), int(b)) for a, b in zip(i, j)}
+            want = set()
+            for a in range(n):
+                for b in range(a + 1, n):
+                    if min_image_brute(x[a], x[b], L) <= cut:
+                        want.add((a, b))
+            # exact ties at the cutoff are measure-zero for random inputs
+            assert got == want
+            for a, b, rr in zip(i, j, r):
+                assert abs(rr - min_image_brute(x[a], x[b], L)) < 1e-12
+
+
+# ------------------------------------------------------------------ forces
+def _two_body(L, xi, xj, sig=(1.0, 1.0), static=None, bond=None):
+    o = OracleSystem(2, 2, L, 1)
+    o.set_type(0, 0, sig[0], 1.0, 1.0)
+    o.set_type(1, 0, sig[1], 1.0, 1.0)
+    if bond is not None:
+        o.add_bond_type(*bond)
+    o.set_particles([xi, xj], np.zeros((2, 3)), [0, 1])
+    if static:
+        o.add_static_bonds([(0, 1)], [0])
+    o.commit()
+    return o
+
+
+def test_wca_closed_form_values():
+    o = _two_body(10.0, (0, 0, 0), (1.0, 0, 0))
+    F, U = o.forces(o.x)
+    assert abs(U - 1.0) < 1e-14                         # 4(1-1)+1
+    assert abs(F[0, 0] + 24.0) < 1e-12 and abs(F[1, 0] - 24.0) < 1e-12
+    o = _two_body(10.0, (0, 0, 0), (0.5, 0, 0), sig=(0.5, 0.5))
+    F, U = o.forces(o.x)
+    assert abs(abs(F[0, 0]) - 48.0) < 1e-12          # 24 eps / sigma at r = sigma
+    o = _two_body(10.0, (0, 0, 0), (2 ** (1 / 6) + 1e-9, 0, 0))
+    F, U = o.forces(o.x)
+    assert np.all(F == 0) and U == 0.0
+    o = _two_body(10.0, (0, 0, 0), (2 ** (1 / 6) - 1e-7, 0, 0))
+    F, U = o.forces(o.x)
+    assert 0 < abs(F[0, 0]) < 1e-4
+    # mixed sigma: (1 + 0.5)/2 = 0.75 contact
+    o = _two_body(10.0, (0, 0, 0), (0.75, 0, 0), sig=(1.0, 0.5))
+    F, U = o.forces(o.x)
+    assert abs(abs(F[0, 0]) - 32.0) < 1e-12 and abs(U - 1.0) < 1e-14
+
+
+def test_wca_across_periodic_boundary():
+    L = 6.0
+    a = _two_body(L, (L / 2 - 0.3, 0.1, -0.2), (-L / 2 + 0.6, 0.1, -0.2))
+    b = _two_body(L, (0.0, 0.1, -0.2), (0.9, 0.1, -0.2))
+    Fa, Ua = a.forces(a.x)
+    Fb, Ub = b.forces(b.x)
+    assert np.allclose(Fa, Fb, rtol=1e-12, atol=1e-12) and abs(Ua - Ub) < 1e-12
+
+
+def test_bond_closed_forms():
+    o = _two_body(10.0, (0, 0, 0), (1.2, 0, 0), sig=(0.0, 0.0), static=True,
+                  bond=(0, 100.0, 1.0))
+    F, U = o.forces(o.x)
+    assert abs(F[0, 0] - 20.0) < 1e-12 and abs(U - 2.0) < 1e-12    # -k(r-r0) toward partner
+    o = _two_body(10.0, (0, 0, 0), (1.0, 0, 0), sig=(0.0, 0.0), static=True,
+                  bond=(1, 30.0, 1.5))
+    F, U = o.forces(o.x)
+    assert abs(F[0, 0] - 30.0 / (1 - 1 / 2.25)) < 1e-12
+    assert abs(U - (-0.5 * 30 * 2.25 * math.log(1 - 1 / 2.25))) < 1e-12
+    with pytest.raises(OracleError):
+        _two_body(10.0, (0, 0, 0), (1.5, 0, 0), sig=(0.0, 0.0), static=True,
+                  bond=(1, 30.0, 1.5))
+
+
+def _mixed_system(seed=11):
+    """Dense small system: mixed sigma, FENE chains and harmonic dynamic bonds."""
+    rng = np.random.default_rng(seed)
+    w = inputs.telechelic(seed=seed, n_chains=6, chain_len=5, n_cross=8, density=0.3)
+    o = oracle_from_workload(w)
+    # add dynamic bonds between chain ends and crosslinkers that are close
+    ends = np.where(w.type_id == 0)[0]
+    cross = np.where(w.type_id == 2)[0]
+    pairs = []
+    used = set()
+    for e in ends:
+        for c in cross:
+            r = float(o.norm(o.delta(o.x[e], o.x[c])))
+            if r < 1.4 and c not in used:
+                pairs.append((e, c))
+                used.add(c)
+                break
+    o.set_state(0, w.pos, w.vel, pairs, [1] * len(pairs))
+    return o, rng
+
+
+def test_force_is_minus_gradient_of_energy():
+    o, rng = _mixed_system()
+    F, U = o.forces(o.x)
+    h = 1e-6
+    for i in rng.choice(o.n, 12, replace=False):
+        for c in range(3):
+            xp = o.x.copy()
+            xp[i, c] += h
+            xm = o.x.copy()
+            xm[i, c] -= h
+            num = -(o.forces(xp)[1] - o.forces(xm)[1]) / (2 * h)
+            assert abs(num - F[i, c]) <= 1e-5 * max(1.0, abs(F[i, c]))
+    assert np.abs(F.sum(axis=0)).max() < 1e-9          # Newton's third law
+
+
+# ------------------------------------------------------------------ sweep
+def _brute_propose(o, a, occ0):
+    """Plain per-site loop of the proposal rule (Sec. 2.3)."""
+    rx = o.reactions[a]
+    r0 = o.bond_kinds[rx.bond_type][2]
+    props = {}
+    for i in range(o.n):
+        ti = int(o.types[i])
+        if ti == rx.type_a:
+            want = rx.type_b
+        elif ti == rx.type_b:
+            want = rx.type_a
+        else:
+            continue
+        if occ0[i] >= o.valence[ti]:
+            continue
+        best = None
+        for j in range(o.n):
+            tj = int(o.types[j])
+            if j == i or tj != want or occ0[j] >= o.valence[tj]:
+                continue
+            if o.bonded(i, j):
+                continue
+            if rx.self_avoid and o.mol[i] == o.mol[j]:
+                continue
+            r = min_image_brute(o.x[i], o.x[j], o.L)
+            if r < rx.r_min or r > rx.r_max:
+                continue
+            cand = (abs(r - r0), j)
+            if best is None or cand < best:
+                best = cand
+        if best is not None:
+            props[i] = best[1]
+    return props
+
+
+def test_proposal_matches_brute_force():
+    rng = np.random.default_rng(21)
+    for trial in range(6):
+        chains = [(k, k + 1) for k in range(0, 20, 2)]
+        o = random_frozen_system(
+            rng, n=48, L=4.0, reactions=[(0, 1, 1.0, 0.7, trial % 2, 0.3, 1.4),
+                                         (1, 1, 0.5, 0.9, 1, 0.0, 1.2),
+                                         (0, 2, 0.0, 0.5, 0, 0.0, 1.6)],
+            static_pairs=chains, seed=trial)
+        for s in range(1, 4):             # create some occupancy first
+            o.sweep(s)
+        for a in range(3):
+            assert o.propose(a, o.occ.copy()) == _brute_propose(o, a, o.occ.copy())
+
+
+def test_matching_is_the_greedy_matching_in_key_order():
+    rng = np.random.default_rng(5)
+    o = random_frozen_system(rng, n=60, L=3.5, reactions=[(0, 1, 1.0, 1.0, 0, 0.0, 1.5),
+                                                          (1, 1, 1.0, 1.0, 0, 0.0, 1.5)])
+    for a in range(2):
+        for s in range(1, 30):
+            props = o.propose(a, o.occ.copy())
+            pairs = o.match(a, s, props)
+            used = [v for p in pairs for v in p]
+            assert len(used) == len(set(used))              # disjoint
+            keys = dict(zip(sorted(props), o.match_keys(a, s, sorted(props))))
+            chosen = {frozenset(p): keys[p[0]] for p in pairs}
+            for i, j in props.items():
+                if frozenset((i, j)) in chosen:
+                    continue
+                # a rejected proposal touches a claim made with a smaller key
+                blockers = [k for p, k in chosen.items() if (i in p or j in p)]
+                assert blockers and min(blockers) < keys[i]
+
+
+def _frozen(points, types, valence, reactions, L=8.0, seed=3, kT=1.0, bond_k=100.0,
+            r0=1.0, static=()):
+    n = len(points)
+    nt = max(types) + 1
+    o = OracleSystem(n, nt, L, seed)
+    for t in range(nt):
+        o.set_type(t, valence[t], 0.0, 0.0, 1.0)
+    o.set_particles(np.array(points, dtype=np.float64), np.zeros((n, 3)), types)
+    for _ in reactions:
+        o.add_bond_type(0, bond_k, r0)
+    if static:
+        fb = o.add_bond_type(1, 30.0, 50.0)
+        o.add_static_bonds(static, [fb] * len(static))
+    for k, (a, b, kw) in enumerate(reactions):
+        o.add_reaction(Reaction(a, b, k, kw.pop("r_min", 0.0), kw.pop("r_max", 1.3),
+                                self_avoid=kw.pop("self_avoid", 0), **kw))
+    o.set_integrator(0.005, kT, 1.0, 10)
+    o.commit()
+    return o
+
+
+def test_frozen_dimer_two_state_chain():
+    """One pair at fixed r: forming with p = P0_on e^{-U/kT}, breaking with q = P0_off."""
+    r = 1.1
+    o = _frozen([(0, 0, 0), (r, 0, 0)], [0, 1], [1, 1],
+                [(0, 1, dict(epsilon=0.3, p_on0=0.8))])
+    p = 0.8 * math.exp(-0.5 * 100.0 * (r - 1.0) ** 2)
+    q = 0.8 * math.exp(-0.3)
+    n_sw = 8000
+    state = []
+    for s in range(1, n_sw + 1):
+        was = len(o.dyn)
+        o.sweep(s)
+        state.append((was, len(o.dyn)))
+    st = np.array(state)
+    from_u = st[st[:, 0] == 0]
+    from_b = st[st[:, 0] == 1]
+    pf = from_u[:, 1].mean()
+    qb = 1 - from_b[:, 1].mean()
+    assert abs(pf - p) < 4 * math.sqrt(p * (1 - p) / len(from_u))
+    assert abs(qb - q) < 4 * math.sqrt(q * (1 - q) / len(from_b))
+    # stationary bonded fraction of the two-state chain
+    pb = st[:, 1].mean()
+    tau = (2 - p - q) / (p + q)
+    assert abs(pb - p / (p + q)) < 4 * math.sqrt(p * q / (p + q) ** 2 * tau / n_sw)
+
+
+def test_competition_ln4():
+    """A competes for B and C; a fourfold smaller k_off gives fourfold occupancy
+    (k_B T ln 4 free-energy difference, Sec. 2.6)."""
+    o = _frozen([(0, 0, 0), (1, 0, 0), (0, 1, 0)], [0, 1, 2], [1, 1, 1],
+                [(0, 1, dict(k_on=6.0, k_off=0.5)), (0, 2, dict(k_on=6.0, k_off=2.0))])
+    counts = np.zeros(3)
+    n_sw = 9000
+    for s in range(1, n_sw + 1):
+        o.sweep(s)
+        st = 0
+        for (_, _), a in o.dyn.items():
+            st = 1 + a
+        counts[st] += 1
+    P = counts / n_sw
+    K_ab, K_ac = 12.0, 3.0
+    Z = 1 + K_ab + K_ac
+    assert abs(P[1] - K_ab / Z) < 0.02 and abs(P[2] - K_ac / Z) < 0.02
+    assert abs(P[1] / P[2] - 4.0) < 0.6
+
+
+@pytest.mark.slow
+def test_four_reaction_square_partition_function():
+    """Frozen square with A-B, A-C, D-B, D-C at the rest length (App. A, Eq. Z)."""
+    eps = {"AB": 1.0, "AC": 0.5, "DB": 0.0, "DC": 1.5}
+    A, B, C, D = 0, 1, 2, 3
+    o = _frozen([(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0)], [A, B, C, D], [1] * 4,
+                [(A, B, dict(epsilon=eps["AB"], p_on0=0.5)),
+                 (A, C, dict(epsilon=eps["AC"], p_on0=0.5)),
+                 (D, B, dict(epsilon=eps["DB"], p_on0=0.5)),
+                 (D, C, dict(epsilon=eps["DC"], p_on0=0.5))])
+    K = {k: math.exp(v) for k, v in eps.items()}
+    Z = 1 + sum(K.values()) + K["AB"] * K["DC"] + K["AC"] * K["DB"]
+    want = [K["AB"] * (1 + K["DC"]) / Z, K["AC"] * (1 + K["DB"]) / Z,
+            K["DB"] * (1 + K["AC"]) / Z, K["DC"] * (1 + K["AB"]) / Z]
+    assert abs(Z - 24.6799074009) < 1e-9
+    counts = np.zeros(4)
+    n_sw = 16000
+    for s in range(1, n_sw + 1):
+        o.sweep(s)
+        occ = np.zeros(4, dtype=int)
+        for (i, j), a in o.dyn.items():
+            counts[a] += 1
+            occ[i] += 1
+            occ[j] += 1
+        assert occ.max() <= 1
+    assert np.max(np.abs(counts / n_sw - np.array(want))) < 0.02
+
+
+def test_valence_and_no_reform_invariants_under_turnover():
+    rng = np.random.default_rng(8)
+    o = random_frozen_system(rng, n=120, L=3.2, valence=(2, 4, 1),
+                             reactions=[(0, 1, 0.5, 0.9, 0, 0.0, 1.4),
+                                        (0, 2, 0.2, 0.9, 0, 0.0, 1.4),
+                                        (1, 1, 0.0, 0.8, 0, 0.0, 1.3)])
+    o.events = []
+    for s in range(1, 150):
+        start = dict(o.dyn)
+        o.events.clear()
+        o.sweep(s)
+        deg = np.zeros(o.n, dtype=int)
+        for (i, j), a in o.dyn.items():
+            deg[i] += 1
+            deg[j] += 1
+            rx = o.reactions[a]
+            assert {int(o.types[i]), int(o.types[j])} == {rx.type_a, rx.type_b}
+        assert np.array_equal(deg, o.occ)
+        assert np.all(o.occ <= o.valence[o.types])
+        broken = {(e[1], e[3], e[4]) for e in o.events if e[2] == "break"}
+        formed = [(e[1], e[3], e[4]) for e in o.events if e[2] == "form"]
+        assert len(formed) == len(set(formed))
+        for f in formed:
+            assert f not in broken                # a reaction never re-forms what it broke
+            assert f[1:] not in start             # never proposes an existing pair
+        for e in o.events:
+            if e[2] == "form":
+                assert e[5] <= o.reactions[e[1]].r_max
+        # turnover: reshuffle positions between sweeps
+        o.x = rng.uniform(-o.L / 2, o.L / 2, (o.n, 3))
+
+
+def test_molecule_exclusion_both_directions_with_control():
+    # molecule 1: A(0) - M(1) - B(2) with A and B at the rest length
+    # control pair: A(3) and B(4) in separate molecules, also at the rest length
+    pts = [(0, 0, 0), (0.5, 0.8, 0), (1.0, 0, 0), (4, 0, 0), (5, 0, 0)]
+    types = [0, 2, 1, 0, 1]
+    for self_avoid, expect_intra in ((1, False), (0, True)):
+        o = _frozen(pts, types, [1, 1, 0], [(0, 1, dict(epsilon=2.0, p_on0=1.0,
+                                                        self_avoid=self_avoid))],
+                    static=[(0, 1), (1, 2)])
+        o.sweep(10)
+        assert ((0, 2) in o.dyn) == expect_intra
+        assert (3, 4) in o.dyn
+
+
+def test_unbinding_by_bond_type():
+    """Two reactions on the same endpoint types break by their own P0_off."""
+    n_pairs = 300
+    pts, types, pairs, btypes = [], [], [], []
+    for k in range(n_pairs):
+        pts += [(k * 3.0 - 450.0, 0, 0), (k * 3.0 - 450.0, 1.6, 0)]   # beyond r_max: no re-forming
+        types += [0, 1]
+        pairs.append((2 * k, 2 * k + 1))
+        btypes.append(k % 2)
+    o = _frozen(pts, types, [1, 1], [(0, 1, dict(epsilon=1.0, p_on0=0.1)),
+                                     (0, 1, dict(epsilon=3.0, p_on0=0.1))], L=905.0)
+    o.set_state(0, pts, np.zeros((len(pts), 3)), pairs, btypes)
+    q = [0.1 * math.exp(-1.0), 0.1 * math.exp(-3.0)]
+    survive = np.zeros(2)
+    n_sw = 40
+    for s in range(1, n_sw + 1):
+        o.sweep(s)
+    for (i, j), a in o.dyn.items():
+        survive[a] += 1
+    for a in range(2):
+        expect = (n_pairs / 2) * (1 - q[a]) ** n_sw
+        assert abs(survive[a] - expect) < 4 * math.sqrt(expect) + 1
+
+
+def test_zero_temperature_limit():
+    for r, formed in ((1.0, True), (1.1, False)):
+        o = _frozen([(0, 0, 0), (r, 0, 0)], [0, 1], [1, 1],
+                    [(0, 1, dict(epsilon=2.0, p_on0=1.0))], kT=0.0)
+        o.sweep(10)
+        assert (len(o.dyn) == 1) == formed
+    o = _frozen([(0, 0, 0), (1.2, 0, 0)], [0, 1], [1, 1],
+                [(0, 1, dict(epsilon=2.0, p_on0=1.0))], kT=1e-300)
+    assert o.acceptance_probability(1.0, 2.0, 1e-300) == 0.0
+    assert o.acceptance_probability(1.0, 0.0, 0.0) == 1.0
+    o.sweep(10)
+    assert len(o.dyn) == 0
+
+
+# ------------------------------------------------------------- rate closure
+def test_rate_closure():
+    k_on, k_off, eps, p_on, p_off = resolve_rates(math.nan, math.nan, 5.0, 1.0, 0.005, 10)
+    assert p_on == 1.0 and abs(p_off - math.exp(-5.0)) < 1e-15
+    assert abs(k_on - 20.0) < 1e-12 and abs(k_on / k_off - math.exp(5.0)) < 1e-9
+    k_on, k_off, eps, p_on, p_off = resolve_rates(2.0, 0.5, math.nan, math.nan, 0.001, 100)
+    assert abs(eps - math.log(4.0)) < 1e-15 and abs(p_on - 0.2) < 1e-15
+    with pytest.raises(OracleError) as e:
+        resolve_rates(2.0, math.nan, math.nan, math.nan, 0.001, 100)
+    assert e.value.code == "EINVAL"
+    with pytest.raises(OracleError) as e:
+        resolve_rates(300.0, 1.0, math.nan, math.nan, 0.005, 10)
+    assert e.value.code == "ERANGE"
+    with pytest.raises(OracleError):
+        resolve_rates(2.0, 0.5, 3.0, math.nan, 0.001, 100)     # inconsistent
+    resolve_rates(2.0, 0.5, math.log(4.0), 0.2, 0.001, 100)    # consistent over-specification
+
+
+def test_self_avoid_has_no_default():
+    with pytest.raises(OracleError) as e:
+        _frozen([(0, 0, 0), (1, 0, 0)], [0, 1], [1, 1],
+                [(0, 1, dict(epsilon=2.0, p_on0=1.0, self_avoid=None))])
+    assert e.value.code == "EINVAL"
+
+
+# --------------------------------------------------------------- integrator
+def _ideal_gas(n=400, L=12.0, gamma=1.0, seed=4):
+    rng = np.random.default_rng(seed)
+    o = OracleSystem(n, 1, L, seed)
+    o.set_type(0, 0, 0.0, 0.0, 1.0)
+    o.set_particles(rng.uniform(-L / 2, L / 2, (n, 3)), rng.standard_normal((n, 3)), np.zeros(n))
+    o.set_integrator(0.005, 1.0, gamma, 10)
+    o.commit()
+    return o
+
+
+def test_langevin_equipartition_and_velocity_decorrelation():
+    o = _ideal_gas()
+    v0 = o.v.copy()
+    o.step(100)                                  # t = 0.5 tau
+    c = np.sum(v0 * o.v) / np.sum(v0 * v0)
+    assert abs(c - math.exp(-0.5)) < 0.04
+    ke = []
+    for _ in range(30):
+        o.step(20)
+        ke.append(o.observables()["T_kin"])
+    assert abs(np.mean(ke) - 1.0) < 0.03
+
+
+def test_free_diffusion_msd():
+    o = _ideal_gas(n=400)
+    o.step(1000)
+    u0 = o.x + o.img * o.L
+    o.step(2000)                                 # t = 10 tau
+    u1 = o.x + o.img * o.L
+    msd = np.mean(np.sum((u1 - u0) ** 2, axis=1))
+    t = 10.0
+    expect = 6 * (t - (1 - math.exp(-t)))        # OU position variance, D = kT/(m gamma) = 1
+    assert abs(msd / expect - 1.0) < 0.1
+
+
+def test_energy_conservation_without_thermostat():
+    """gamma = 0 turns BAOAB into velocity Verlet: energy is conserved."""
+    o, _ = _mixed_system(seed=2)
+    o.gamma = 0.0
+    o.dt = 0.001
+    o.period = 10 ** 9
+    o.set_state(0, o.x, o.v * 0.5, [(i, j) for (i, j) in o.dyn], [1] * len(o.dyn))
+    e0 = o.observables()
+    E0 = e0["KE"] + e0["PE"]
+    o.step(400)
+    e1 = o.observables()
+    E1 = e1["KE"] + e1["PE"]
+    assert abs(E1 - E0) / o.n < 2e-3
+
+
+# --------------------------------------------------- equilibrium statistics
+@pytest.mark.slow
+def test_forms_balance_breaks_at_equilibrium():
+    w = inputs.small(seed=2, n=512, density=0.3, eps_bond=2.0)
+    o = oracle_from_workload(w)
+    o.step(1500)
+    c0 = o.counters.copy()
+    o.step(3000)
+    F = o.counters[0, 1] - c0[0, 1]
+    B = o.counters[0, 2] - c0[0, 2]
+    assert F + B > 200
+    assert abs(F - B) <= 4 * math.sqrt(F + B)
