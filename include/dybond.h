@@ -1,0 +1,224 @@
+/*
+ * dybond.h -- C ABI of the MI355X dynamic-bonding Langevin MD library.
+ *
+ * One time step (db_step) of a periodic, cubic, coarse-grained particle system:
+ *   - Langevin integration (BAOAB) of positions and velocities;
+ *   - a cell-list neighbour structure rebuilt every step;
+ *   - WCA pair forces on all pairs plus harmonic / FENE bond forces;
+ *   - every `sweep_period` steps, a bonding sweep that forms and breaks
+ *     dynamic bonds between partner species under per-site valence caps,
+ *     consistent with the equilibrium constant K = k_on / k_off = e^eps of
+ *     each reaction (paper Sec. 2.1, Eq. epsilon; sweep Sec. 2.3; acceptance
+ *     Eq. pon; per-sweep probabilities Eq. probs).
+ *
+ * Conventions for every entry point
+ *   - Host arrays passed in are borrowed for the duration of the call and
+ *     copied; the library keeps no pointer to them.
+ *   - Per-particle arrays are in TAG order: tag = index into the arrays given
+ *     to db_set_particles.  The library may keep particles in a different
+ *     order internally; no result depends on that order.
+ *   - Outputs go to caller-allocated host buffers.  A buffer that is too small
+ *     yields DB_ETRUNC with the required size in the count argument.
+ *   - No exception and no abort crosses the ABI.  Every call returns a
+ *     db_status; db_last_error() gives a message for the last failure.
+ *   - A HIP runtime error makes the handle unusable (sticky DB_EDEVICE).
+ *   - Results are a pure function of (initial state, parameters, seed, step).
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Set-up calls (db_create ... db_validate) touch no GPU.  The device is
+ *     first used by db_commit.
+ *
+ * Limits: n < 2^24 particles, at most 8 particle types, 8 bond types,
+ * 8 reactions, valence <= 8 per type, <= 8 static bonds per particle.
+ */
+#ifndef DYBOND_H
+#define DYBOND_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define DB_API __attribute__((visibility("default")))
+#else
+#define DB_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct db_system db_system;   /* opaque; created by db_create, freed by db_destroy */
+
+typedef enum {
+    DB_OK = 0,
+    DB_EINVAL = 1,     /* invalid argument or configuration */
+    DB_ENOMEM = 2,     /* host or device allocation failed */
+    DB_EDEVICE = 3,    /* HIP runtime error (sticky) or no usable device */
+    DB_ESTATE = 4,     /* call not valid in the current state (e.g. before commit) */
+    DB_ERANGE = 5,     /* a per-sweep probability k n dt exceeds 1 (Eq. probs) */
+    DB_EBOND = 6,      /* a FENE bond reached r >= R0, or a force left the representable range */
+    DB_ETRUNC = 7,     /* output buffer too small; required size returned */
+    DB_EOVERFLOW = 8   /* more particles in one cell than the cell capacity */
+} db_status;
+
+enum { DB_BOND_HARMONIC = 0,   /* U = k/2 (r - r0)^2 */
+       DB_BOND_FENE = 1 };     /* U = -k R0^2/2 ln(1 - r^2/R0^2), r0 argument = R0 */
+
+enum { DB_KT_SETPOINT = 0,     /* acceptance uses the thermostat set point kT */
+       DB_KT_KINETIC = 1 };    /* acceptance uses the instantaneous kinetic temperature
+                                  sum(m v^2) / (3N) at the sweep (Sec. 2.2) */
+
+#define DB_MAX_REACTIONS 8
+
+/* One reaction channel alpha (Sec. 2.1, registered per type pair as in Sec. 2.6).
+ * Sites of type_a bond to sites of type_b (type_a == type_b allowed) with the
+ * harmonic bond type `bond_type`, whose r0 is the rest length used by the
+ * proposal rule; each reaction must own a distinct bond type (bonds break by
+ * their own bond type, App. A).  Candidate pairs lie in [r_min, r_max].
+ * Rates: give any two of k_on, k_off, epsilon, p_on0 (NaN = not given;
+ * k_on and p_on0 carry the same information since P0_on = k_on n dt).
+ * self_avoid: 1 = sites of one molecule (static-bond component) never bond to
+ * each other, 0 = they may; any other value is DB_EINVAL (no default, Sec. 2.4). */
+typedef struct {
+    uint32_t type_a, type_b, bond_type;
+    double r_min, r_max;
+    double k_on, k_off, epsilon, p_on0;
+    int32_t self_avoid;
+} db_reaction_desc;
+
+typedef struct {
+    uint64_t step;
+    uint32_t n_reactions;
+    uint32_t pad;
+    uint64_t n_bonds[DB_MAX_REACTIONS];     /* dynamic bonds currently formed by each reaction */
+    uint64_t attempts[DB_MAX_REACTIONS];    /* cumulative acceptance trials (claimed pairs) */
+    uint64_t forms[DB_MAX_REACTIONS];       /* cumulative bonds formed */
+    uint64_t breaks[DB_MAX_REACTIONS];      /* cumulative bonds broken */
+    double bonded_fraction[DB_MAX_REACTIONS]; /* n_bonds / min(valence sum of type_a, of type_b);
+                                                 homotypic: n_bonds / (valence sum / 2) */
+    double largest_cluster_fraction;        /* largest component of static + dynamic bonds / N */
+    double pe;                              /* potential energy (pairs + bonds) */
+    double ke;                              /* kinetic energy, sum m v^2 / 2 */
+    double t_kin;                           /* 2 KE / (3N) */
+} db_observables;
+
+/* Create an empty system of n particles and n_types types in a cube of side
+ * box_L (positions in [-L/2, L/2)).  `seed` keys every random stream (Sec. 2.5).
+ * `device` is the HIP device index used from db_commit on.  *out receives the
+ * handle (caller frees with db_destroy).  No GPU work. */
+DB_API db_status db_create(uint32_t n, uint32_t n_types, double box_L, uint32_t seed, int device,
+                    db_system** out);
+
+/* Free the handle and all its host and device memory.  NULL is ignored. */
+DB_API void db_destroy(db_system* sys);
+
+/* Per-type parameters: valence (maximum number of dynamic bonds of a site of
+ * this type; 0 = not reactive), WCA sigma and epsilon (sigma_ij is the
+ * arithmetic mean, eps_ij the geometric mean; sigma 0 switches WCA off for
+ * the type), and mass (> 0).  Defaults: valence 0, sigma 1, eps 1, mass 1. */
+DB_API db_status db_set_type(db_system* sys, uint32_t type, uint32_t valence, double wca_sigma,
+                      double wca_eps, double mass);
+
+/* Initial state in tag order: pos3[3n] in [-L/2, L/2), vel3[3n], type[n] < n_types.
+ * All three pointers are required. */
+DB_API db_status db_set_particles(db_system* sys, const float* pos3, const float* vel3,
+                           const uint32_t* type);
+
+/* Register a bond type (kind DB_BOND_HARMONIC or DB_BOND_FENE, stiffness k,
+ * rest length r0 or FENE maximum extension R0); *id receives its index. */
+DB_API db_status db_add_bond_type(db_system* sys, int kind, double k, double r0, uint32_t* id);
+
+/* Add m static (never-breaking) bonds: tag_pairs[2m] and bond_types[m].
+ * Static bonds define the molecules used by self_avoid (Sec. 2.4). */
+DB_API db_status db_add_static_bonds(db_system* sys, const uint32_t* tag_pairs,
+                              const uint32_t* bond_types, uint64_t m);
+
+/* Register a reaction (copied); *id receives its index (processing order is
+ * redrawn at random every sweep, Sec. 2.3). */
+DB_API db_status db_add_reaction(db_system* sys, const db_reaction_desc* desc, uint32_t* id);
+
+/* Integrator: time step dt > 0, thermostat kT >= 0, friction gamma >= 0,
+ * sweep period n >= 1 (the n of Eq. probs), temperature source for the
+ * acceptance factor (DB_KT_SETPOINT or DB_KT_KINETIC).  Defaults 0.005, 1, 1, 10. */
+DB_API db_status db_set_integrator(db_system* sys, double dt, double kT, double gamma,
+                            uint32_t sweep_period, int kt_source);
+
+/* Validate the configuration and close the rate parameters of every reaction
+ * (Eq. epsilon, Eq. probs) without touching a GPU.  Errors: DB_EINVAL (bad
+ * or missing parameter, under-determined or inconsistent rates, box smaller
+ * than 3 cells of side max(WCA cutoff, r_max)), DB_ERANGE (P0 > 1). */
+DB_API db_status db_validate(db_system* sys);
+
+/* Resolved parameters of reaction `id` after a successful db_validate:
+ * resolved->k_on/k_off/epsilon filled in, *p_on0 and *p_off0 receive the
+ * per-sweep probabilities P0 = k n dt.  Host only. */
+DB_API db_status db_get_reaction(const db_system* sys, uint32_t id, db_reaction_desc* resolved,
+                          double* p_on0, double* p_off0);
+
+/* db_validate, then allocate device memory, upload the state and compute the
+ * initial forces.  Errors as db_validate, plus DB_EDEVICE/DB_ENOMEM, DB_EBOND
+ * (FENE bond already overstretched). */
+DB_API db_status db_commit(db_system* sys);
+
+/* Advance n_steps time steps (sweeps included at every step s with
+ * s % sweep_period == 0, after the position update and before the forces).
+ * Synchronous: returns when the GPU work is done.  DB_EBOND / DB_EOVERFLOW
+ * leave the state invalid (DB_ESTATE) until db_set_state. */
+DB_API db_status db_step(db_system* sys, uint64_t n_steps);
+
+/* One bonding sweep at the current positions with step key `step_key`
+ * (random streams keyed as for a sweep at that step); particles do not move,
+ * velocities are unchanged, the step counter is unchanged. */
+DB_API db_status db_sweep_frozen(db_system* sys, uint64_t step_key);
+
+/* Replace the dynamic state: step counter, pos3[3n], vel3[3n] (tag order) and
+ * the m dynamic bonds dyn_tag_pairs[2m] with their bond types (each must be
+ * the bond type of a reaction whose type pair matches the two sites; valences
+ * must hold).  Static bonds and parameters are unchanged. */
+DB_API db_status db_set_state(db_system* sys, uint64_t step, const float* pos3, const float* vel3,
+                       const uint32_t* dyn_tag_pairs, const uint32_t* dyn_bond_types,
+                       uint64_t m);
+
+/* Positions pos3[3n] in [-L/2, L/2) (tag order); image3[3n] (may be NULL)
+ * receives the periodic image counters. */
+DB_API db_status db_read_positions(db_system* sys, float* pos3, int32_t* image3);
+
+/* Full-step velocities vel3[3n] (tag order). */
+DB_API db_status db_read_velocities(db_system* sys, float* vel3);
+
+/* Forces force3[3n] at the current positions and bonds (tag order). */
+DB_API db_status db_read_forces(db_system* sys, float* force3);
+
+/* Dynamic bonds, sorted by (tag_lo, tag_hi, bond_type): tag_pairs[2*cap]
+ * (tag_lo < tag_hi) and bond_types[cap].  *count receives the number of bonds
+ * (also on DB_ETRUNC). */
+DB_API db_status db_read_bonds(db_system* sys, uint32_t* tag_pairs, uint32_t* bond_types,
+                        uint64_t cap, uint64_t* count);
+
+/* Observables of the current state (computed on the device). */
+DB_API db_status db_read_observables(db_system* sys, db_observables* out);
+
+/* Current step counter (host mirror). */
+DB_API uint64_t db_get_step(const db_system* sys);
+
+/* Message of the last failed call on this handle ("" if none); NULL handle
+ * gives the message of the last failed db_create.  Owned by the library. */
+DB_API const char* db_last_error(const db_system* sys);
+
+/* Launch the library's kernels on `hip_stream` (a hipStream_t created by the
+ * caller at default priority; NULL = the library's own stream). */
+DB_API db_status db_set_stream(db_system* sys, void* hip_stream);
+
+/* Enable (1) or disable (0) HIP-event timing of every kernel launch; the
+ * timing is taken on the stream the kernels are launched on and disables
+ * graph replay while on. */
+DB_API db_status db_kernel_timing(db_system* sys, int enable);
+
+/* Number of timed launches and their total duration in ms of the kernel
+ * named `kernel` (e.g. "k_step") since timing was enabled. */
+DB_API db_status db_read_kernel_time(db_system* sys, const char* kernel, uint64_t* launches,
+                              double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DYBOND_H */

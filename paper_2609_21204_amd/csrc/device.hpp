@@ -1,0 +1,187 @@
+// Device-side building blocks of the dynamic-bonding MD step (gfx950).
+//
+// Counter-based random numbers (Philox4x32-10, Salmon et al. SC'11), the
+// FP64 geometry that every bond decision is taken with, and the parameter
+// and state blocks passed to every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dyb {
+
+constexpr int kMaxTypes = 8;
+constexpr int kMaxRx = 8;
+constexpr int kMaxBondTypes = 8;
+constexpr int kMaxValence = 8;
+constexpr int kMaxStatic = 8;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;       // empty bond slot
+constexpr uint32_t kIdxMask = 0x00FFFFFFu;     // partner index bits of a slot word
+constexpr uint32_t kNewBit = 0x80000000u;      // dynamic bond formed in the running sweep
+constexpr uint64_t kNoKey = ~0ull;
+constexpr float kFixScale = 4294967296.0f;     // 2^32: fixed-point force / energy scale
+constexpr double kFixInv = 1.0 / 4294967296.0;
+
+// Random stream kinds: one stream per purpose, reaction and replica.
+enum : uint32_t { kThermo = 1, kOrder = 2, kMatch = 3, kOn = 4, kOff = 5 };
+
+// Edge states of the matching phase.
+enum : uint8_t { kEdgeNone = 0, kEdgeLive = 1, kEdgeMatched = 2, kEdgeDead = 3 };
+
+// Device error flags (sticky until the host clears them).
+enum : uint32_t { kErrOverflow = 1u, kErrFene = 2u, kErrForce = 4u };
+
+// ---------------------------------------------------------------- Philox
+struct Word4 { uint32_t w0, w1, w2, w3; };
+
+// Philox4x32 with 10 rounds.  A round multiplies counter words 0 and 2 by
+// the two round constants, swaps the halves into the other two words xor-ed
+// with the key, and bumps the key by the Weyl increments.
+__host__ __device__ inline Word4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Word4{c0, c1, c2, c3};
+}
+
+__host__ __device__ inline uint32_t stream_k1(uint32_t kind, uint32_t rx, uint32_t replica) {
+    return (kind << 24) | (rx << 16) | (replica & 0xFFFFu);
+}
+
+// 53-bit uniform double in [0, 1).
+__host__ __device__ inline double u53(uint32_t w0, uint32_t w1) {
+    const uint64_t bits = ((uint64_t)w0 << 21) | (uint64_t)(w1 >> 11);
+    return (double)bits * 0x1.0p-53;
+}
+
+// Random processing order of the reactions of the sweep at step s: Fisher-
+// Yates from the last slot down, slot k swapped with floor(w (k+1) / 2^32),
+// words taken in order from Philox blocks (s, 0, block) of the ORDER stream.
+// Returns the reaction processed in slot `slot`.
+__host__ __device__ inline int reaction_at(uint32_t seed, uint64_t s, int nrx, int slot) {
+    int order[kMaxRx];
+    for (int k = 0; k < nrx; ++k) order[k] = k;
+    if (nrx > 1) {
+        const uint32_t k1 = stream_k1(kOrder, 0, 0);
+        Word4 blk{};
+        int used = 4;
+        uint32_t block = 0;
+        for (int k = nrx - 1; k >= 1; --k) {
+            if (used == 4) {
+                blk = philox((uint32_t)s, (uint32_t)(s >> 32), 0u, block++, seed, k1);
+                used = 0;
+            }
+            const uint32_t w = used == 0 ? blk.w0 : used == 1 ? blk.w1 : used == 2 ? blk.w2 : blk.w3;
+            ++used;
+            const int j = (int)(((uint64_t)w * (uint64_t)(k + 1)) >> 32);
+            const int t = order[k];
+            order[k] = order[j];
+            order[j] = t;
+        }
+    }
+    return order[slot];
+}
+
+// ---------------------------------------------------------------- geometry
+// Minimum-image separation x_j - x_i in FP64 from FP32 coordinates.  The
+// evaluation order is fixed and never contracted into FMAs, so that every
+// bond decision sees exactly the same r on every device and on the host.
+__device__ __forceinline__ double mi_delta(float xi, float xj, double L, double invL) {
+#pragma clang fp contract(off)
+    const double d = (double)xj - (double)xi;
+    const double k = rint(d * invL);
+    return d - k * L;
+}
+
+__device__ __forceinline__ double norm3(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    return sqrt(r2);
+}
+
+// ---------------------------------------------------------------- blocks
+struct Params {
+    uint32_t n, ntypes, nrx, cap_max;
+    uint32_t stat_max, nc, ncell, cellcap;
+    uint32_t seed, period, kt_kinetic, any_self_avoid;
+    double L, invL;
+    float Lf, halfLf, cell_scale, h;   // h = dt / 2
+    float c1;                          // exp(-gamma dt)
+    float pad0;
+    double kT;
+    float inv_mass[kMaxTypes];
+    float noise_sd[kMaxTypes];         // sqrt(1 - c1^2) sqrt(kT / m)
+    float mass[kMaxTypes];
+    uint32_t cap[kMaxTypes];
+    float sig2[kMaxTypes * kMaxTypes];
+    float eps4[kMaxTypes * kMaxTypes];  // 4 eps_ij (0: no WCA)
+    float rc2[kMaxTypes * kMaxTypes];   // (2^(1/6) sigma_ij)^2
+    uint32_t bkind[kMaxBondTypes];
+    float bk[kMaxBondTypes], br0[kMaxBondTypes], bR02[kMaxBondTypes];
+    uint32_t ra[kMaxRx], rb[kMaxRx], rbt[kMaxRx], rself[kMaxRx];
+    double rmin[kMaxRx], rmax[kMaxRx], r0[kMaxRx], hk[kMaxRx], pon[kMaxRx], poff[kMaxRx];
+};
+
+struct Dev {
+    float4* x[2];          // positions (xyz) + type bits (w), double-buffered
+    float4* u;             // velocity before the closing half kick of the last step
+    int32_t* img;          // image counters, 3 x n
+    uint32_t* tag;         // tag of the particle at each index
+    uint32_t* rtag;        // index of each tag
+    uint8_t* occ;          // dynamic-bond count per site
+    uint32_t* dyn;         // cap_max x n dynamic slots: partner | rx << 24 | new bit
+    uint32_t* stat;        // stat_max x n static slots: partner | bond type << 24
+    uint32_t* mol;         // molecule id (static-bond component)
+    uint32_t* ccount[3];   // per-cell counts of three rotating cell lists
+    uint32_t* cmem[3];     // per-cell members (cellcap slots per cell)
+    int32_t* prop;         // proposed partner index (-1 none)
+    unsigned long long* key;        // matching priority of each proposal
+    unsigned long long* best[3];    // per-site minimum key of live incident proposals (3 rotating)
+    uint8_t* estate;       // proposal state
+    uint8_t* claimed;      // site claimed in the running reaction
+    uint32_t* live;        // compacted live proposals handed to the finishing pass
+    uint32_t* live_count;  // [0] = length of `live`
+    unsigned long long* counters;   // nrx x 3: attempts, forms, breaks
+    unsigned long long* stepv;      // two step slots (parity of the step)
+    unsigned long long* ke_fix;     // sum m v^2 in 2^-32 fixed point (kinetic kT)
+    uint32_t* err;         // [0] flags, [1], [2] tags of the offending pair
+    float4* f4;            // forces + per-particle energy (evaluation kernels)
+    unsigned long long* red;        // reduction scratch (observables)
+    uint32_t* scan;        // scan scratch (bond read-out)
+    uint32_t* parent;      // union-find parents (cluster observable)
+};
+
+__device__ __forceinline__ uint32_t type_of(const float4& p) { return __float_as_uint(p.w); }
+
+__device__ __forceinline__ int cell_coord(float x, const Params& P) {
+    int c = (int)floorf((x + P.halfLf) * P.cell_scale);
+    c = c < 0 ? 0 : c;
+    return c >= (int)P.nc ? (int)P.nc - 1 : c;
+}
+
+__device__ __forceinline__ int wrapc(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
+
+__device__ __forceinline__ long long to_fix(float f) {
+    return (long long)rint((double)f * 4294967296.0);
+}
+
+// Wave-aggregated atomic add of a per-lane count to a 64-bit counter.
+__device__ __forceinline__ void wave_add(unsigned long long* dst, uint32_t v) {
+    unsigned long long sum = v;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if (__lane_id() == 0 && sum) atomicAdd(dst, sum);
+}
+
+}  // namespace dyb

@@ -1,0 +1,959 @@
+// Host side of the C ABI declared in include/dybond.h: configuration,
+// validation and rate closure (Eqs. epsilon and probs), device memory, kernel
+// launches of one time step and of the bonding sweep, graph replay of whole
+// sweep periods, and the read-out paths.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/dybond.h"
+#include "kernels.hpp"
+
+using namespace dyb;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMatchRounds = 3;        // full-grid matching rounds before the one-workgroup finish
+constexpr uint32_t kCellCap = 16;      // particle slots per cell
+thread_local std::string g_create_error;
+
+struct TypeCfg { uint32_t valence = 0; double sigma = 1.0, eps = 1.0, mass = 1.0; };
+struct BondCfg { int kind; double k, r0; };
+struct RxRes { double k_on, k_off, eps, p_on, p_off; };
+
+struct Timing {
+    bool on = false;
+    struct Pending { std::string name; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<uint64_t, double>> acc;
+};
+
+}  // namespace
+
+struct db_system {
+    // configuration (host)
+    uint32_t n = 0, ntypes = 0;
+    double L = 0.0;
+    uint32_t seed = 0;
+    int device = 0;
+    std::vector<TypeCfg> types;
+    std::vector<BondCfg> bonds;
+    std::vector<db_reaction_desc> rx;
+    std::vector<RxRes> res;
+    std::vector<float> pos, vel;
+    std::vector<uint32_t> type;
+    bool have_particles = false;
+    std::vector<uint32_t> stat_pairs, stat_bt;
+    double dt = 0.005, kT = 1.0, gamma = 1.0;
+    uint32_t period = 10;
+    int kt_source = DB_KT_SETPOINT;
+    bool validated = false, committed = false, invalid = false, dead = false;
+    std::string err;
+    // device state
+    Params P{};
+    Dev D{};
+    std::vector<void*> allocs;
+    hipStream_t stream = nullptr, own_stream = nullptr;
+    uint32_t* bsum = nullptr;       // block sums for the bond read-out (nb + 1)
+    float4* stage = nullptr;        // tag-ordered staging buffer
+    uint32_t* flag = nullptr;       // device flag for iterative kernels
+    uint64_t step = 0;
+    int cur_x = 0, cur_list = 0;
+    std::vector<uint32_t> tag_h, rtag_h;   // host mirrors of tag / rtag
+    Timing timing;
+    std::map<int, hipGraphExec_t> graphs;  // keyed by (cur_x, cur_list)
+    bool use_graphs = true;
+};
+
+namespace {
+
+db_status fail(db_system* s, db_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (s) s->err = buf;
+    else g_create_error = buf;
+    return st;
+}
+
+#define HIPCHK(sys, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            (sys)->dead = true;                                                                  \
+            return fail((sys), DB_EDEVICE, "HIP error %s at %s:%d", hipGetErrorString(e_),      \
+                        __FILE__, __LINE__);                                                     \
+        }                                                                                        \
+    } while (0)
+
+inline unsigned grid_of(uint32_t n) { return (n + kBlock - 1) / kBlock; }
+
+struct TimerScope {
+    db_system* s;
+    const char* name;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimerScope(db_system* sys, const char* nm) : s(sys), name(nm) {
+        if (!s->timing.on) return;
+        auto take = [&]() {
+            hipEvent_t e;
+            if (!s->timing.pool.empty()) { e = s->timing.pool.back(); s->timing.pool.pop_back(); }
+            else (void)hipEventCreate(&e);
+            return e;
+        };
+        a = take();
+        b = take();
+        (void)hipEventRecord(a, s->stream);
+    }
+    ~TimerScope() {
+        if (!a) return;
+        (void)hipEventRecord(b, s->stream);
+        s->timing.pending.push_back({name, a, b});
+    }
+};
+
+#define LAUNCH(sys, kern, grid, block, ...)                                                      \
+    do {                                                                                         \
+        TimerScope ts_((sys), #kern);                                                            \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (sys)->stream, __VA_ARGS__);       \
+    } while (0)
+
+void flush_timing(db_system* s) {
+    if (s->timing.pending.empty()) return;
+    (void)hipStreamSynchronize(s->stream);
+    for (auto& p : s->timing.pending) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p.a, p.b);
+        auto& acc = s->timing.acc[p.name];
+        acc.first += 1;
+        acc.second += ms;
+        s->timing.pool.push_back(p.a);
+        s->timing.pool.push_back(p.b);
+    }
+    s->timing.pending.clear();
+}
+
+bool isnan_(double v) { return std::isnan(v); }
+
+// Rate closure of one reaction (Eq. epsilon: K = k_on/k_off = e^eps; Eq. probs:
+// P0 = k n dt).  Same order of evaluation as documented in the header.
+db_status close_rates(db_system* s, const db_reaction_desc& d, RxRes& out) {
+    double k_on = d.k_on, k_off = d.k_off, eps = d.epsilon, p_on0 = d.p_on0;
+    const double ndt = (double)s->period * s->dt;
+    if (!isnan_(p_on0)) {
+        if (!isnan_(k_on)) {
+            if (std::fabs(p_on0 - k_on * ndt) > 1e-9 * std::max(1.0, std::fabs(p_on0)))
+                return fail(s, DB_EINVAL, "reaction: k_on and p_on0 disagree");
+        } else {
+            k_on = p_on0 / ndt;
+        }
+    }
+    const int known = !isnan_(k_on) + !isnan_(k_off) + !isnan_(eps);
+    if (known < 2) return fail(s, DB_EINVAL, "reaction: rates under-determined (give two of k_on/p_on0, k_off, epsilon)");
+    if (!isnan_(k_on) && !isnan_(k_off)) {
+        if (!isnan_(eps)) {
+            if (k_off <= 0.0 || k_on <= 0.0 ||
+                std::fabs(eps - std::log(k_on / k_off)) > 1e-9 * std::max(1.0, std::fabs(eps)))
+                return fail(s, DB_EINVAL, "reaction: k_on, k_off and epsilon disagree");
+        } else if (k_on > 0.0 && k_off > 0.0) {
+            eps = std::log(k_on / k_off);
+        }
+    } else if (!isnan_(k_on)) {
+        k_off = k_on * std::exp(-eps);
+    } else {
+        k_on = k_off * std::exp(eps);
+    }
+    const double p_on = !isnan_(p_on0) ? p_on0 : k_on * ndt;
+    const double p_off = k_off * ndt;
+    for (double v : {k_on, k_off, p_on, p_off})
+        if (!std::isfinite(v) || v < 0.0) return fail(s, DB_ERANGE, "reaction: negative or non-finite rate");
+    if (p_on > 1.0 || p_off > 1.0)
+        return fail(s, DB_ERANGE, "reaction: per-sweep probability k n dt exceeds 1 (P0_on=%g, P0_off=%g)", p_on, p_off);
+    out = RxRes{k_on, k_off, eps, p_on, p_off};
+    return DB_OK;
+}
+
+double wca_cut(double sig) { return std::pow(2.0, 1.0 / 6.0) * sig; }
+
+db_status validate(db_system* s) {
+    s->validated = false;
+    if (!s->have_particles) return fail(s, DB_ESTATE, "particles not set");
+    if (!(s->dt > 0.0) || !(s->kT >= 0.0) || !(s->gamma >= 0.0) || s->period < 1)
+        return fail(s, DB_EINVAL, "integrator parameters out of range");
+    if (s->rx.size() > (size_t)kMaxRx) return fail(s, DB_EINVAL, "too many reactions");
+    s->res.assign(s->rx.size(), RxRes{});
+    std::vector<int> bt_owner(s->bonds.size(), -1);
+    double rmax_all = 0.0;
+    for (size_t a = 0; a < s->rx.size(); ++a) {
+        const auto& d = s->rx[a];
+        if (d.self_avoid != 0 && d.self_avoid != 1)
+            return fail(s, DB_EINVAL, "reaction %zu: self_avoid must be stated as 0 or 1", a);
+        if (d.type_a >= s->ntypes || d.type_b >= s->ntypes)
+            return fail(s, DB_EINVAL, "reaction %zu: type out of range", a);
+        if (d.bond_type >= s->bonds.size() || s->bonds[d.bond_type].kind != DB_BOND_HARMONIC)
+            return fail(s, DB_EINVAL, "reaction %zu: bond type must be a harmonic bond type", a);
+        if (bt_owner[d.bond_type] >= 0)
+            return fail(s, DB_EINVAL, "reaction %zu: bond type already owned by reaction %d", a, bt_owner[d.bond_type]);
+        bt_owner[d.bond_type] = (int)a;
+        if (!(d.r_min >= 0.0) || !(d.r_max > d.r_min) || !std::isfinite(d.r_max))
+            return fail(s, DB_EINVAL, "reaction %zu: window must satisfy 0 <= r_min < r_max", a);
+        rmax_all = std::max(rmax_all, d.r_max);
+        db_status st = close_rates(s, d, s->res[a]);
+        if (st != DB_OK) return st;
+    }
+    for (const auto& b : s->bonds)
+        if (!(b.k >= 0.0) || !(b.r0 > 0.0 || (b.kind == DB_BOND_HARMONIC && b.r0 >= 0.0)))
+            return fail(s, DB_EINVAL, "bond type parameters out of range");
+    double rc = 0.0;
+    for (uint32_t a = 0; a < s->ntypes; ++a)
+        for (uint32_t b = 0; b < s->ntypes; ++b) {
+            const double sig = 0.5 * (s->types[a].sigma + s->types[b].sigma);
+            const double eps = std::sqrt(s->types[a].eps * s->types[b].eps);
+            if (sig > 0.0 && eps > 0.0) rc = std::max(rc, wca_cut(sig));
+        }
+    const double rsearch = std::max(rc, rmax_all);
+    if (!(rsearch > 0.0)) return fail(s, DB_EINVAL, "no interaction range (all sigma 0 and no reaction)");
+    const double nc = std::floor(s->L / (rsearch * (1.0 + 1e-5)));
+    if (nc < 3.0)
+        return fail(s, DB_EINVAL, "box L=%g holds fewer than 3 cells of side %g", s->L, rsearch);
+    if (nc * nc * nc > 2.0e9) return fail(s, DB_EINVAL, "too many cells");
+    // static bonds: per particle degree, FENE range
+    std::vector<uint32_t> deg(s->n, 0);
+    for (size_t k = 0; k < s->stat_bt.size(); ++k) {
+        const uint32_t i = s->stat_pairs[2 * k], j = s->stat_pairs[2 * k + 1];
+        if (i >= s->n || j >= s->n || i == j || s->stat_bt[k] >= s->bonds.size())
+            return fail(s, DB_EINVAL, "static bond %zu invalid", k);
+        if (++deg[i] > (uint32_t)kMaxStatic || ++deg[j] > (uint32_t)kMaxStatic)
+            return fail(s, DB_EINVAL, "more than %d static bonds on one particle", kMaxStatic);
+    }
+    s->validated = true;
+    return DB_OK;
+}
+
+void union_find_mol(db_system* s, std::vector<uint32_t>& mol) {
+    mol.resize(s->n);
+    std::iota(mol.begin(), mol.end(), 0u);
+    auto find = [&](uint32_t v) {
+        while (mol[v] != v) { mol[v] = mol[mol[v]]; v = mol[v]; }
+        return v;
+    };
+    for (size_t k = 0; k < s->stat_bt.size(); ++k) {
+        uint32_t a = find(s->stat_pairs[2 * k]), b = find(s->stat_pairs[2 * k + 1]);
+        if (a != b) mol[std::max(a, b)] = std::min(a, b);
+    }
+    for (uint32_t v = 0; v < s->n; ++v) mol[v] = find(v);
+}
+
+template <class T>
+db_status dalloc(db_system* s, T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(s, DB_ENOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+    }
+    s->allocs.push_back(q);
+    *p = (T*)q;
+    return DB_OK;
+}
+
+#define DALLOC(sys, ptr, count)                       \
+    do {                                              \
+        db_status st_ = dalloc((sys), &(ptr), (count)); \
+        if (st_ != DB_OK) return st_;                 \
+    } while (0)
+
+void fill_params(db_system* s) {
+    Params& P = s->P;
+    P = Params{};
+    P.n = s->n;
+    P.ntypes = s->ntypes;
+    P.nrx = (uint32_t)s->rx.size();
+    P.seed = s->seed;
+    P.period = s->period;
+    P.kt_kinetic = s->kt_source == DB_KT_KINETIC;
+    P.L = s->L;
+    P.invL = 1.0 / s->L;
+    P.Lf = (float)s->L;
+    P.halfLf = (float)(0.5 * s->L);
+    P.h = (float)(0.5 * s->dt);
+    const double c1 = std::exp(-s->gamma * s->dt);
+    P.c1 = (float)c1;
+    P.kT = s->kT;
+    uint32_t capmax = 0;
+    for (uint32_t t = 0; t < s->ntypes; ++t) {
+        P.inv_mass[t] = (float)(1.0 / s->types[t].mass);
+        P.mass[t] = (float)s->types[t].mass;
+        P.noise_sd[t] = (float)(std::sqrt(std::max(0.0, 1.0 - c1 * c1)) * std::sqrt(s->kT / s->types[t].mass));
+        P.cap[t] = s->types[t].valence;
+        capmax = std::max(capmax, s->types[t].valence);
+    }
+    P.cap_max = std::max(capmax, 1u);
+    double rc = 0.0, rmax_all = 0.0;
+    for (uint32_t a = 0; a < s->ntypes; ++a)
+        for (uint32_t b = 0; b < s->ntypes; ++b) {
+            const double sig = 0.5 * (s->types[a].sigma + s->types[b].sigma);
+            const double eps = std::sqrt(s->types[a].eps * s->types[b].eps);
+            const int k = a * kMaxTypes + b;
+            if (sig > 0.0 && eps > 0.0) {
+                P.sig2[k] = (float)(sig * sig);
+                P.eps4[k] = (float)(4.0 * eps);
+                P.rc2[k] = (float)(wca_cut(sig) * wca_cut(sig));
+                rc = std::max(rc, wca_cut(sig));
+            }
+        }
+    for (size_t b = 0; b < s->bonds.size(); ++b) {
+        P.bkind[b] = (uint32_t)s->bonds[b].kind;
+        P.bk[b] = (float)s->bonds[b].k;
+        P.br0[b] = (float)s->bonds[b].r0;
+        P.bR02[b] = (float)(s->bonds[b].r0 * s->bonds[b].r0);
+    }
+    for (size_t a = 0; a < s->rx.size(); ++a) {
+        const auto& d = s->rx[a];
+        P.ra[a] = d.type_a;
+        P.rb[a] = d.type_b;
+        P.rbt[a] = d.bond_type;
+        P.rself[a] = (uint32_t)d.self_avoid;
+        P.any_self_avoid |= (uint32_t)d.self_avoid;
+        P.rmin[a] = d.r_min;
+        P.rmax[a] = d.r_max;
+        P.r0[a] = s->bonds[d.bond_type].r0;
+        P.hk[a] = 0.5 * s->bonds[d.bond_type].k;
+        P.pon[a] = s->res[a].p_on;
+        P.poff[a] = s->res[a].p_off;
+        rmax_all = std::max(rmax_all, d.r_max);
+    }
+    const double rsearch = std::max(rc, rmax_all);
+    P.nc = (uint32_t)std::floor(s->L / (rsearch * (1.0 + 1e-5)));
+    P.ncell = P.nc * P.nc * P.nc;
+    P.cellcap = kCellCap;
+    P.cell_scale = (float)((double)P.nc / s->L);
+    uint32_t smax = 0;
+    std::vector<uint32_t> deg(s->n, 0);
+    for (size_t k = 0; k < s->stat_bt.size(); ++k) {
+        smax = std::max(smax, ++deg[s->stat_pairs[2 * k]]);
+        smax = std::max(smax, ++deg[s->stat_pairs[2 * k + 1]]);
+    }
+    P.stat_max = smax;
+}
+
+// Upload positions/velocities (tag order) and dynamic bonds; rebuild derived
+// device state (cell list, u = v - h F/m).
+db_status upload_state(db_system* s, const float* pos3, const float* vel3, const uint32_t* pairs,
+                       const uint32_t* bts, uint64_t m) {
+    const uint32_t n = s->n;
+    const Params& P = s->P;
+    std::vector<float4> xs(n), vs(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t t = s->tag_h[i];
+        float tb;
+        const uint32_t ty = s->type[t];
+        std::memcpy(&tb, &ty, 4);
+        xs[i] = make_float4(pos3[3 * t], pos3[3 * t + 1], pos3[3 * t + 2], tb);
+        vs[i] = make_float4(vel3[3 * t], vel3[3 * t + 1], vel3[3 * t + 2], 0.f);
+    }
+    std::vector<uint32_t> dyn((size_t)P.cap_max * n, kEmpty);
+    std::vector<uint8_t> occ(n, 0);
+    std::vector<int> bt2rx(s->bonds.size(), -1);
+    for (size_t a = 0; a < s->rx.size(); ++a) bt2rx[s->rx[a].bond_type] = (int)a;
+    for (uint64_t k = 0; k < m; ++k) {
+        const uint32_t ta = pairs[2 * k], tb = pairs[2 * k + 1], bt = bts[k];
+        const int a = bt < bt2rx.size() ? bt2rx[bt] : -1;
+        const uint32_t ia = s->rtag_h[ta], ib = s->rtag_h[tb];
+        const uint32_t bits = ((uint32_t)a << 24);
+        auto put = [&](uint32_t i, uint32_t j) {
+            for (uint32_t q = 0; q < P.cap_max; ++q)
+                if (dyn[(size_t)q * n + i] == kEmpty) { dyn[(size_t)q * n + i] = j | bits; return; }
+        };
+        put(ia, ib);
+        put(ib, ia);
+        occ[ia]++;
+        occ[ib]++;
+    }
+    std::vector<int32_t> img(3 * (size_t)n, 0);
+    HIPCHK(s, hipMemcpyAsync(s->D.x[0], xs.data(), n * sizeof(float4), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->D.x[1], xs.data(), n * sizeof(float4), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->D.u, vs.data(), n * sizeof(float4), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->D.dyn, dyn.data(), dyn.size() * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->D.occ, occ.data(), n, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->D.img, img.data(), img.size() * 4, hipMemcpyHostToDevice, s->stream));
+    unsigned long long sv[2];
+    sv[s->step & 1] = s->step;
+    sv[(s->step & 1) ^ 1] = s->step;
+    HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv, sizeof sv, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemsetAsync(s->D.err, 0, 4 * sizeof(uint32_t), s->stream));
+    HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, sizeof(unsigned long long), s->stream));
+    s->cur_x = 0;
+    s->cur_list = 0;
+    for (int l = 0; l < 3; ++l) LAUNCH(s, k_clear_counts, std::min(grid_of(P.ncell), 65535u), kBlock, s->P, s->D, l);
+    LAUNCH(s, k_bin, grid_of(n), kBlock, s->P, s->D, 0, 0);
+    LAUNCH(s, k_eval, grid_of(n), kBlock, s->P, s->D, 0, 0, 0u);
+    LAUNCH(s, k_init_u, grid_of(n), kBlock, s->P, s->D, 0, 0u);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    uint32_t err[4];
+    HIPCHK(s, hipMemcpy(err, s->D.err, sizeof err, hipMemcpyDeviceToHost));
+    if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", kCellCap); }
+    if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "FENE bond %u-%u overstretched", err[1], err[2]); }
+    if (err[0] & kErrForce) { s->invalid = true; return fail(s, DB_EBOND, "force out of range"); }
+    s->invalid = false;
+    return DB_OK;
+}
+
+db_status check_errors(db_system* s) {
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    flush_timing(s);
+    uint32_t err[4];
+    HIPCHK(s, hipMemcpy(err, s->D.err, sizeof err, hipMemcpyDeviceToHost));
+    if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", kCellCap); }
+    if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "FENE bond %u-%u reached r >= R0", err[1], err[2]); }
+    if (err[0] & kErrForce) { s->invalid = true; return fail(s, DB_EBOND, "force out of the representable range"); }
+    return DB_OK;
+}
+
+// Sweep at the current positions: buffers xcur / cell list lst, step key in slot sp.
+void launch_sweep(db_system* s, int xcur, int lst, int sp) {
+    const Params& P = s->P;
+    const unsigned g = grid_of(P.n);
+    for (int slot = 0; slot < (int)P.nrx; ++slot) {
+        LAUNCH(s, k_propose, g, kBlock, P, s->D, slot, xcur, lst, sp);
+        LAUNCH(s, k_claim, g, kBlock, P, s->D, slot, 1, xcur, sp);
+        for (int q = 2; q <= kMatchRounds; ++q) {
+            LAUNCH(s, k_kill, g, kBlock, P, s->D, q, q == kMatchRounds ? 1 : 0);
+            LAUNCH(s, k_claim, g, kBlock, P, s->D, slot, q, xcur, sp);
+        }
+        LAUNCH(s, k_finish, 1, 1024, P, s->D, slot, (kMatchRounds + 1) % 3, xcur, sp);
+        LAUNCH(s, k_break, g, kBlock, P, s->D, slot, xcur, sp, slot == (int)P.nrx - 1 ? 1 : 0);
+    }
+}
+
+// One time step t -> t+1 (plus the sweep when (t+1) % period == 0).
+void launch_step(db_system* s) {
+    const Params& P = s->P;
+    const uint64_t t = s->step;
+    const int xin = s->cur_x, lcur = s->cur_list;
+    const int lnext = (lcur + 1) % 3, lclr = (lcur + 2) % 3;
+    const int sp = (int)(t & 1);
+    const bool sweep = P.nrx > 0 && ((t + 1) % P.period == 0);
+    LAUNCH(s, k_step, grid_of(P.n), kBlock, P, s->D, xin, lcur, lnext, lclr, sp,
+           (sweep && P.kt_kinetic) ? 1 : 0);
+    s->cur_x ^= 1;
+    s->cur_list = lnext;
+    s->step = t + 1;
+    if (sweep) launch_sweep(s, s->cur_x, s->cur_list, (int)((t + 1) & 1));
+}
+
+void destroy_graphs(db_system* s) {
+    for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
+    s->graphs.clear();
+}
+
+// Steps per graph: a whole number of sweep periods that also returns the
+// rotating buffers (x: 2, cell lists: 3, step slots: 2) to where they were.
+uint64_t graph_span(const db_system* s) {
+    uint64_t g = s->period;
+    while (g % 6 != 0) g += s->period;
+    while (g < 30) g *= 2;
+    return g;
+}
+
+db_status run_steps(db_system* s, uint64_t nsteps) {
+    const uint64_t span = graph_span(s);
+    uint64_t done = 0;
+    while (done < nsteps) {
+        const bool aligned = (s->step % s->period) == 0;
+        if (s->use_graphs && !s->timing.on && aligned && nsteps - done >= span) {
+            const int key = s->cur_x * 3 + s->cur_list;
+            auto it = s->graphs.find(key);
+            if (it == s->graphs.end()) {
+                const uint64_t step0 = s->step;
+                const int x0 = s->cur_x, l0 = s->cur_list;
+                hipGraph_t g;
+                HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+                for (uint64_t k = 0; k < span; ++k) launch_step(s);
+                HIPCHK(s, hipStreamEndCapture(s->stream, &g));
+                hipGraphExec_t ge;
+                HIPCHK(s, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+                HIPCHK(s, hipGraphDestroy(g));
+                s->step = step0;
+                s->cur_x = x0;
+                s->cur_list = l0;
+                it = s->graphs.emplace(key, ge).first;
+            }
+            HIPCHK(s, hipGraphLaunch(it->second, s->stream));
+            s->step += span;       // span is a multiple of 6: buffers return to (x0, l0)
+            done += span;
+        } else {
+            launch_step(s);
+            ++done;
+        }
+    }
+    return DB_OK;
+}
+
+db_status ready(db_system* s) {
+    if (!s) return DB_EINVAL;
+    if (s->dead) return fail(s, DB_EDEVICE, "device error earlier on this handle");
+    if (!s->committed) return fail(s, DB_ESTATE, "system not committed");
+    if (s->invalid) return fail(s, DB_ESTATE, "state invalid after an error; call db_set_state");
+    return DB_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+extern "C" {
+
+db_status db_create(uint32_t n, uint32_t n_types, double box_L, uint32_t seed, int device, db_system** out) {
+    if (!out) return fail(nullptr, DB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n == 0 || n >= (1u << 24)) return fail(nullptr, DB_EINVAL, "n must be in [1, 2^24)");
+    if (n_types == 0 || n_types > (uint32_t)kMaxTypes) return fail(nullptr, DB_EINVAL, "n_types must be in [1, 8]");
+    if (!(box_L > 0.0) || !std::isfinite(box_L)) return fail(nullptr, DB_EINVAL, "box_L must be positive");
+    db_system* s = new (std::nothrow) db_system();
+    if (!s) return fail(nullptr, DB_ENOMEM, "out of host memory");
+    s->n = n;
+    s->ntypes = n_types;
+    s->L = box_L;
+    s->seed = seed;
+    s->device = device;
+    s->types.assign(n_types, TypeCfg{});
+    s->tag_h.resize(n);
+    s->rtag_h.resize(n);
+    std::iota(s->tag_h.begin(), s->tag_h.end(), 0u);
+    std::iota(s->rtag_h.begin(), s->rtag_h.end(), 0u);
+    *out = s;
+    return DB_OK;
+}
+
+void db_destroy(db_system* s) {
+    if (!s) return;
+    if (s->committed) {
+        (void)hipSetDevice(s->device);
+        (void)hipStreamSynchronize(s->stream);
+        destroy_graphs(s);
+        for (auto& p : s->timing.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+        for (auto e : s->timing.pool) (void)hipEventDestroy(e);
+        for (void* p : s->allocs) (void)hipFree(p);
+        if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+    }
+    delete s;
+}
+
+db_status db_set_type(db_system* s, uint32_t type, uint32_t valence, double sigma, double eps, double mass) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "parameters are fixed after commit");
+    if (type >= s->ntypes) return fail(s, DB_EINVAL, "type out of range");
+    if (valence > (uint32_t)kMaxValence) return fail(s, DB_EINVAL, "valence above %d", kMaxValence);
+    if (!(sigma >= 0.0) || !(eps >= 0.0) || !(mass > 0.0) || !std::isfinite(sigma) || !std::isfinite(mass))
+        return fail(s, DB_EINVAL, "sigma, eps must be >= 0 and mass > 0");
+    s->types[type] = TypeCfg{valence, sigma, eps, mass};
+    s->validated = false;
+    return DB_OK;
+}
+
+db_status db_set_particles(db_system* s, const float* pos3, const float* vel3, const uint32_t* type) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "use db_set_state after commit");
+    if (!pos3 || !vel3 || !type) return fail(s, DB_EINVAL, "pos3, vel3 and type are required");
+    const float half = (float)(0.5 * s->L);
+    for (size_t k = 0; k < 3 * (size_t)s->n; ++k)
+        if (!(pos3[k] >= -half && pos3[k] < half)) return fail(s, DB_EINVAL, "position %zu outside [-L/2, L/2)", k / 3);
+    for (uint32_t i = 0; i < s->n; ++i)
+        if (type[i] >= s->ntypes) return fail(s, DB_EINVAL, "type of particle %u out of range", i);
+    s->pos.assign(pos3, pos3 + 3 * (size_t)s->n);
+    s->vel.assign(vel3, vel3 + 3 * (size_t)s->n);
+    s->type.assign(type, type + s->n);
+    s->have_particles = true;
+    s->validated = false;
+    return DB_OK;
+}
+
+db_status db_add_bond_type(db_system* s, int kind, double k, double r0, uint32_t* id) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "parameters are fixed after commit");
+    if (kind != DB_BOND_HARMONIC && kind != DB_BOND_FENE) return fail(s, DB_EINVAL, "unknown bond kind");
+    if (s->bonds.size() >= (size_t)kMaxBondTypes) return fail(s, DB_EINVAL, "too many bond types");
+    if (!(k >= 0.0) || !(r0 >= 0.0) || !std::isfinite(k) || !std::isfinite(r0) || (kind == DB_BOND_FENE && !(r0 > 0.0)))
+        return fail(s, DB_EINVAL, "bond parameters out of range");
+    s->bonds.push_back(BondCfg{kind, k, r0});
+    if (id) *id = (uint32_t)s->bonds.size() - 1;
+    s->validated = false;
+    return DB_OK;
+}
+
+db_status db_add_static_bonds(db_system* s, const uint32_t* pairs, const uint32_t* bt, uint64_t m) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "static bonds are fixed after commit");
+    if (m && (!pairs || !bt)) return fail(s, DB_EINVAL, "NULL arrays");
+    s->stat_pairs.insert(s->stat_pairs.end(), pairs, pairs + 2 * m);
+    s->stat_bt.insert(s->stat_bt.end(), bt, bt + m);
+    s->validated = false;
+    return DB_OK;
+}
+
+db_status db_add_reaction(db_system* s, const db_reaction_desc* d, uint32_t* id) {
+    if (!s || !d) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "reactions are fixed after commit");
+    if (s->rx.size() >= (size_t)kMaxRx) return fail(s, DB_EINVAL, "at most %d reactions", kMaxRx);
+    s->rx.push_back(*d);
+    if (id) *id = (uint32_t)s->rx.size() - 1;
+    s->validated = false;
+    return DB_OK;
+}
+
+db_status db_set_integrator(db_system* s, double dt, double kT, double gamma, uint32_t period, int kt_source) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "integrator is fixed after commit");
+    if (!(dt > 0.0) || !(kT >= 0.0) || !(gamma >= 0.0) || period < 1 || !std::isfinite(dt) ||
+        !std::isfinite(kT) || !std::isfinite(gamma))
+        return fail(s, DB_EINVAL, "dt > 0, kT >= 0, gamma >= 0, period >= 1 required");
+    if (kt_source != DB_KT_SETPOINT && kt_source != DB_KT_KINETIC) return fail(s, DB_EINVAL, "bad kt_source");
+    s->dt = dt;
+    s->kT = kT;
+    s->gamma = gamma;
+    s->period = period;
+    s->kt_source = kt_source;
+    s->validated = false;
+    return DB_OK;
+}
+
+db_status db_validate(db_system* s) {
+    if (!s) return DB_EINVAL;
+    return validate(s);
+}
+
+db_status db_get_reaction(const db_system* s, uint32_t id, db_reaction_desc* out, double* p_on0, double* p_off0) {
+    if (!s || !out) return DB_EINVAL;
+    if (!s->validated) return DB_ESTATE;
+    if (id >= s->rx.size()) return DB_EINVAL;
+    *out = s->rx[id];
+    out->k_on = s->res[id].k_on;
+    out->k_off = s->res[id].k_off;
+    out->epsilon = s->res[id].eps;
+    out->p_on0 = s->res[id].p_on;
+    if (p_on0) *p_on0 = s->res[id].p_on;
+    if (p_off0) *p_off0 = s->res[id].p_off;
+    return DB_OK;
+}
+
+static db_status commit_impl(db_system* s);
+
+db_status db_commit(db_system* s) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "already committed");
+    const db_status st = commit_impl(s);
+    if (st != DB_OK && s->committed && st != DB_EBOND && st != DB_EOVERFLOW) s->dead = true;
+    return st;
+}
+
+static db_status commit_impl(db_system* s) {
+    if (s->committed) return fail(s, DB_ESTATE, "already committed");
+    db_status st = validate(s);
+    if (st != DB_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(s, DB_EDEVICE, "no HIP device available");
+    }
+    if (s->device < 0 || s->device >= ndev) return fail(s, DB_EDEVICE, "device %d not present", s->device);
+    HIPCHK(s, hipSetDevice(s->device));
+    fill_params(s);
+    const uint32_t n = s->n;
+    const Params& P = s->P;
+    Dev& D = s->D;
+    HIPCHK(s, hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
+    s->stream = s->own_stream;
+    s->committed = true;   // from here on db_destroy frees device memory
+    DALLOC(s, D.x[0], n);
+    DALLOC(s, D.x[1], n);
+    DALLOC(s, D.u, n);
+    DALLOC(s, D.img, 3 * (size_t)n);
+    DALLOC(s, D.tag, n);
+    DALLOC(s, D.rtag, n);
+    DALLOC(s, D.occ, n);
+    DALLOC(s, D.dyn, (size_t)P.cap_max * n);
+    DALLOC(s, D.stat, (size_t)std::max(P.stat_max, 1u) * n);
+    DALLOC(s, D.mol, n);
+    for (int l = 0; l < 3; ++l) {
+        DALLOC(s, D.ccount[l], P.ncell);
+        DALLOC(s, D.cmem[l], (size_t)P.ncell * P.cellcap);
+        DALLOC(s, D.best[l], n);
+    }
+    DALLOC(s, D.prop, n);
+    DALLOC(s, D.key, n);
+    DALLOC(s, D.estate, n);
+    DALLOC(s, D.claimed, n);
+    DALLOC(s, D.live, n);
+    DALLOC(s, D.live_count, 4);
+    DALLOC(s, D.counters, 3 * kMaxRx);
+    DALLOC(s, D.stepv, 2);
+    DALLOC(s, D.ke_fix, 1);
+    DALLOC(s, D.err, 4);
+    DALLOC(s, D.f4, 2 * (size_t)n);
+    DALLOC(s, D.red, 4 + kMaxRx);
+    DALLOC(s, D.scan, (size_t)n + 1);
+    DALLOC(s, D.parent, n);
+    DALLOC(s, s->bsum, grid_of(n) + 1);
+    DALLOC(s, s->stage, n);
+    DALLOC(s, s->flag, 1);
+    // static topology, molecule ids, tags
+    std::vector<uint32_t> stat((size_t)std::max(P.stat_max, 1u) * n, kEmpty), fillc(n, 0);
+    for (size_t k = 0; k < s->stat_bt.size(); ++k) {
+        const uint32_t i = s->stat_pairs[2 * k], j = s->stat_pairs[2 * k + 1], b = s->stat_bt[k];
+        stat[(size_t)fillc[i]++ * n + i] = j | (b << 24);
+        stat[(size_t)fillc[j]++ * n + j] = i | (b << 24);
+    }
+    std::vector<uint32_t> mol;
+    union_find_mol(s, mol);
+    HIPCHK(s, hipMemcpyAsync(D.stat, stat.data(), stat.size() * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(D.mol, mol.data(), n * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(D.tag, s->tag_h.data(), n * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(D.rtag, s->rtag_h.data(), n * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemsetAsync(D.counters, 0, 3 * kMaxRx * sizeof(unsigned long long), s->stream));
+    for (int l = 0; l < 3; ++l) HIPCHK(s, hipMemsetAsync(D.best[l], 0xFF, (size_t)n * 8, s->stream));
+    HIPCHK(s, hipMemsetAsync(D.estate, 0, n, s->stream));
+    HIPCHK(s, hipMemsetAsync(D.claimed, 0, n, s->stream));
+    HIPCHK(s, hipMemsetAsync(D.prop, 0xFF, (size_t)n * 4, s->stream));
+    HIPCHK(s, hipMemsetAsync(D.live_count, 0, 16, s->stream));
+    s->step = 0;
+    return upload_state(s, s->pos.data(), s->vel.data(), nullptr, nullptr, 0);
+}
+
+db_status db_step(db_system* s, uint64_t nsteps) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    HIPCHK(s, hipSetDevice(s->device));
+    st = run_steps(s, nsteps);
+    if (st != DB_OK) return st;
+    return check_errors(s);
+}
+
+db_status db_sweep_frozen(db_system* s, uint64_t step_key) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (s->P.nrx == 0) return DB_OK;
+    HIPCHK(s, hipSetDevice(s->device));
+    const unsigned g = grid_of(s->n);
+    const int xc = s->cur_x, lc = s->cur_list;
+    LAUNCH(s, k_eval, g, kBlock, s->P, s->D, xc, lc, 0u);
+    const unsigned long long sv[2] = {step_key, step_key};
+    const unsigned long long sv_back[2] = {s->step, s->step};
+    HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv, sizeof sv, hipMemcpyHostToDevice, s->stream));
+    if (s->P.kt_kinetic) {
+        HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, 8, s->stream));
+        LAUNCH(s, k_ke_accum, g, kBlock, s->P, s->D, xc);
+    }
+    launch_sweep(s, xc, lc, (int)(step_key & 1));
+    LAUNCH(s, k_eval, g, kBlock, s->P, s->D, xc, lc, s->n);
+    LAUNCH(s, k_fix_u, g, kBlock, s->P, s->D, xc);
+    HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv_back, sizeof sv_back, hipMemcpyHostToDevice, s->stream));
+    return check_errors(s);
+}
+
+db_status db_set_state(db_system* s, uint64_t step, const float* pos3, const float* vel3,
+                       const uint32_t* pairs, const uint32_t* bts, uint64_t m) {
+    if (!s) return DB_EINVAL;
+    if (s->dead) return fail(s, DB_EDEVICE, "device error earlier on this handle");
+    if (!s->committed) return fail(s, DB_ESTATE, "system not committed");
+    if (!pos3 || !vel3 || (m && (!pairs || !bts))) return fail(s, DB_EINVAL, "NULL arrays");
+    const float half = (float)(0.5 * s->L);
+    for (size_t k = 0; k < 3 * (size_t)s->n; ++k)
+        if (!(pos3[k] >= -half && pos3[k] < half)) return fail(s, DB_EINVAL, "position %zu outside [-L/2, L/2)", k / 3);
+    std::vector<int> bt2rx(s->bonds.size(), -1);
+    for (size_t a = 0; a < s->rx.size(); ++a) bt2rx[s->rx[a].bond_type] = (int)a;
+    std::vector<uint32_t> occ(s->n, 0);
+    std::vector<uint64_t> keys;
+    keys.reserve(m);
+    for (uint64_t k = 0; k < m; ++k) {
+        uint32_t a = pairs[2 * k], b = pairs[2 * k + 1];
+        if (a >= s->n || b >= s->n || a == b) return fail(s, DB_EINVAL, "dynamic bond %llu: bad tags", (unsigned long long)k);
+        if (bts[k] >= bt2rx.size() || bt2rx[bts[k]] < 0)
+            return fail(s, DB_EINVAL, "dynamic bond %llu: bond type is not a reaction's", (unsigned long long)k);
+        const auto& d = s->rx[bt2rx[bts[k]]];
+        const uint32_t ta = s->type[a], tb = s->type[b];
+        if (!((ta == d.type_a && tb == d.type_b) || (ta == d.type_b && tb == d.type_a)))
+            return fail(s, DB_EINVAL, "dynamic bond %llu: types do not match its reaction", (unsigned long long)k);
+        if (++occ[a] > s->types[ta].valence || ++occ[b] > s->types[tb].valence)
+            return fail(s, DB_EINVAL, "dynamic bond %llu exceeds a valence", (unsigned long long)k);
+        keys.push_back(((uint64_t)std::min(a, b) << 32) | std::max(a, b));
+    }
+    std::sort(keys.begin(), keys.end());
+    if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) return fail(s, DB_EINVAL, "duplicate dynamic bond");
+    HIPCHK(s, hipSetDevice(s->device));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->step = step;
+    return upload_state(s, pos3, vel3, pairs, bts, m);
+}
+
+db_status db_read_positions(db_system* s, float* pos3, int32_t* image3) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!pos3) return fail(s, DB_EINVAL, "pos3 is NULL");
+    HIPCHK(s, hipSetDevice(s->device));
+    LAUNCH(s, k_gather, grid_of(s->n), kBlock, s->P, s->D, s->stage, s->cur_x, 0);
+    std::vector<float4> h(s->n);
+    HIPCHK(s, hipMemcpyAsync(h.data(), s->stage, s->n * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
+    std::vector<int32_t> im;
+    if (image3) {
+        // the staging buffer (16 n bytes) is reused for 12 n bytes of image counters;
+        // the position copy above is ordered before this kernel on the stream
+        LAUNCH(s, k_gather_img, grid_of(s->n), kBlock, s->P, s->D, (int32_t*)s->stage);
+        im.resize(3 * (size_t)s->n);
+        HIPCHK(s, hipMemcpyAsync(im.data(), s->stage, im.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    }
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (uint32_t t = 0; t < s->n; ++t) {
+        pos3[3 * t] = h[t].x;
+        pos3[3 * t + 1] = h[t].y;
+        pos3[3 * t + 2] = h[t].z;
+    }
+    if (image3) std::memcpy(image3, im.data(), im.size() * 4);
+    return DB_OK;
+}
+
+static db_status read_vec(db_system* s, float* out3, int mode) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!out3) return fail(s, DB_EINVAL, "output is NULL");
+    HIPCHK(s, hipSetDevice(s->device));
+    LAUNCH(s, k_eval, grid_of(s->n), kBlock, s->P, s->D, s->cur_x, s->cur_list, 0u);
+    LAUNCH(s, k_gather, grid_of(s->n), kBlock, s->P, s->D, s->stage, s->cur_x, mode);
+    std::vector<float4> h(s->n);
+    HIPCHK(s, hipMemcpyAsync(h.data(), s->stage, s->n * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
+    st = check_errors(s);
+    if (st != DB_OK) return st;
+    for (uint32_t t = 0; t < s->n; ++t) {
+        out3[3 * t] = h[t].x;
+        out3[3 * t + 1] = h[t].y;
+        out3[3 * t + 2] = h[t].z;
+    }
+    return DB_OK;
+}
+
+db_status db_read_velocities(db_system* s, float* vel3) { return read_vec(s, vel3, 1); }
+db_status db_read_forces(db_system* s, float* force3) { return read_vec(s, force3, 2); }
+
+db_status db_read_bonds(db_system* s, uint32_t* pairs, uint32_t* bts, uint64_t cap, uint64_t* count) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!count) return fail(s, DB_EINVAL, "count is NULL");
+    HIPCHK(s, hipSetDevice(s->device));
+    const unsigned nb = grid_of(s->n);
+    LAUNCH(s, k_rows_count, nb, kBlock, s->P, s->D, s->cur_x, s->bsum);
+    LAUNCH(s, k_scan_bsum, 1, 1024, s->bsum, nb);
+    uint32_t total = 0;
+    HIPCHK(s, hipMemcpyAsync(&total, s->bsum + nb, 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *count = total;
+    if (total > cap) return fail(s, DB_ETRUNC, "%u bonds, capacity %llu", total, (unsigned long long)cap);
+    if (total == 0) return DB_OK;
+    if (!pairs || !bts) return fail(s, DB_EINVAL, "NULL output arrays");
+    uint32_t *dp = nullptr, *db = nullptr;
+    HIPCHK(s, hipMallocAsync((void**)&dp, (size_t)total * 8, s->stream));
+    HIPCHK(s, hipMallocAsync((void**)&db, (size_t)total * 4, s->stream));
+    LAUNCH(s, k_rows_emit, nb, kBlock, s->P, s->D, s->cur_x, s->bsum, dp, db);
+    HIPCHK(s, hipMemcpyAsync(pairs, dp, (size_t)total * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(bts, db, (size_t)total * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipFreeAsync(dp, s->stream));
+    HIPCHK(s, hipFreeAsync(db, s->stream));
+    return check_errors(s);
+}
+
+db_status db_read_observables(db_system* s, db_observables* out) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!out) return fail(s, DB_EINVAL, "out is NULL");
+    HIPCHK(s, hipSetDevice(s->device));
+    const unsigned g = grid_of(s->n);
+    const Params& P = s->P;
+    LAUNCH(s, k_eval, g, kBlock, P, s->D, s->cur_x, s->cur_list, 0u);
+    HIPCHK(s, hipMemsetAsync(s->D.red, 0, (4 + kMaxRx) * 8, s->stream));
+    LAUNCH(s, k_observe, g, kBlock, P, s->D, s->cur_x);
+    // largest cluster: union by minimum index until no hook changes a root
+    LAUNCH(s, k_cc_init, g, kBlock, P, s->D);
+    for (int it = 0; it < 64; ++it) {
+        uint32_t changed = 0;
+        HIPCHK(s, hipMemsetAsync(s->flag, 0, 4, s->stream));
+        LAUNCH(s, k_cc_hook, g, kBlock, P, s->D, s->flag, s->cur_x);
+        LAUNCH(s, k_cc_compress, g, kBlock, P, s->D);
+        HIPCHK(s, hipMemcpyAsync(&changed, s->flag, 4, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        if (!changed) break;
+        if (it == 63) return fail(s, DB_EDEVICE, "cluster labelling did not converge");
+    }
+    HIPCHK(s, hipMemsetAsync(s->D.scan, 0, (size_t)s->n * 4, s->stream));
+    LAUNCH(s, k_cc_size, g, kBlock, P, s->D);
+    LAUNCH(s, k_cc_max, g, kBlock, P, s->D);
+    unsigned long long red[4 + kMaxRx], ctr[3 * kMaxRx];
+    HIPCHK(s, hipMemcpyAsync(red, s->D.red, sizeof red, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(ctr, s->D.counters, sizeof ctr, hipMemcpyDeviceToHost, s->stream));
+    st = check_errors(s);
+    if (st != DB_OK) return st;
+    std::memset(out, 0, sizeof *out);
+    out->step = s->step;
+    out->n_reactions = P.nrx;
+    out->pe = (double)red[0] * kFixInv;
+    out->ke = (double)red[1] * kFixInv;
+    out->t_kin = 2.0 * out->ke / (3.0 * (double)s->n);
+    out->largest_cluster_fraction = (double)red[2 + kMaxRx] / (double)s->n;
+    for (uint32_t a = 0; a < P.nrx; ++a) {
+        out->n_bonds[a] = red[2 + a];
+        out->attempts[a] = ctr[3 * a];
+        out->forms[a] = ctr[3 * a + 1];
+        out->breaks[a] = ctr[3 * a + 2];
+        double cap_a = 0, cap_b = 0;
+        for (uint32_t i = 0; i < s->n; ++i) {
+            if (s->type[i] == s->rx[a].type_a) cap_a += s->types[s->type[i]].valence;
+            if (s->type[i] == s->rx[a].type_b) cap_b += s->types[s->type[i]].valence;
+        }
+        const double denom = s->rx[a].type_a == s->rx[a].type_b ? cap_a / 2.0 : std::min(cap_a, cap_b);
+        out->bonded_fraction[a] = denom > 0 ? (double)red[2 + a] / denom : 0.0;
+    }
+    return DB_OK;
+}
+
+uint64_t db_get_step(const db_system* s) { return s ? s->step : 0; }
+
+const char* db_last_error(const db_system* s) { return s ? s->err.c_str() : g_create_error.c_str(); }
+
+db_status db_set_stream(db_system* s, void* stream) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    destroy_graphs(s);
+    s->stream = stream ? (hipStream_t)stream : s->own_stream;
+    return DB_OK;
+}
+
+db_status db_kernel_timing(db_system* s, int enable) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    flush_timing(s);
+    s->timing.on = enable != 0;
+    if (enable) s->timing.acc.clear();
+    return DB_OK;
+}
+
+db_status db_read_kernel_time(db_system* s, const char* kernel, uint64_t* launches, double* total_ms) {
+    if (!s || !kernel) return DB_EINVAL;
+    flush_timing(s);
+    auto it = s->timing.acc.find(kernel);
+    if (launches) *launches = it == s->timing.acc.end() ? 0 : it->second.first;
+    if (total_ms) *total_ms = it == s->timing.acc.end() ? 0.0 : it->second.second;
+    return DB_OK;
+}
+
+}  // extern "C"

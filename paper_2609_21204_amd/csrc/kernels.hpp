@@ -1,0 +1,754 @@
+// HIP kernels of the dynamic-bonding Langevin MD step (gfx950, wave64).
+//
+// Step structure (one kernel per time step, plus the sweep every n steps):
+//
+//   k_step      forces at x_t (27-cell stencil of the cell list of x_t, WCA on
+//               every pair, static and dynamic bonds), closing half kick of the
+//               previous step, then B-A-O-A of BAOAB, wrap, and binning of
+//               x_{t+1} into the next cell list.  Forces are accumulated in
+//               64-bit fixed point, so the sum does not depend on the order in
+//               which neighbours are visited.
+//   sweep       per reaction (order redrawn every sweep, Sec. 2.3):
+//               k_propose -> (k_claim, k_kill)* -> k_finish -> k_break.
+//               The matching reproduces the sequential greedy matching in
+//               ascending priority key exactly: a proposal is claimed as soon
+//               as its key is the minimum over all live proposals touching
+//               either of its sites (local-minimum rounds); the last rounds run
+//               inside one workgroup.  Acceptance (Eq. pon) is evaluated by the
+//               thread that claims the pair and writes both sites' slots.
+#pragma once
+
+#include "device.hpp"
+
+namespace dyb {
+
+// ------------------------------------------------------------ force kernel
+struct Force3 { float x, y, z; };
+
+// Bond force on site i from partner position pj (slot word w, bond type bt).
+__device__ __forceinline__ void bond_force(const Params& P, const Dev& D, float4 pi, float4 pj,
+                                           uint32_t bt, uint32_t i, uint32_t j,
+                                           long long& fx, long long& fy, long long& fz,
+                                           double* e) {
+    const float dx = (float)mi_delta(pi.x, pj.x, P.L, P.invL);
+    const float dy = (float)mi_delta(pi.y, pj.y, P.L, P.invL);
+    const float dz = (float)mi_delta(pi.z, pj.z, P.L, P.invL);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    float f;
+    if (P.bkind[bt] == 1u) {                      // FENE: F_i = k / (1 - r^2/R0^2) d
+        const float g = 1.0f - r2 / P.bR02[bt];
+        if (!(g > 0.0f)) {
+            if (atomicOr(&D.err[0], kErrFene) == 0u) {
+                D.err[1] = D.tag[i];
+                D.err[2] = D.tag[j];
+            }
+            return;
+        }
+        f = P.bk[bt] / g;
+        if (e) *e += 0.5 * (-0.5 * (double)P.bk[bt] * (double)P.bR02[bt] * log((double)g));
+    } else {                                      // harmonic: F_i = k (r - r0) / r d
+        const float r = sqrtf(r2);
+        const float dr = r - P.br0[bt];
+        f = r > 0.0f ? P.bk[bt] * dr / r : 0.0f;
+        if (e) *e += 0.5 * (0.5 * (double)P.bk[bt] * (double)dr * (double)dr);
+    }
+    fx += to_fix(f * dx);
+    fy += to_fix(f * dy);
+    fz += to_fix(f * dz);
+}
+
+// Total force on particle i at positions X with cell list `lst`; optional
+// per-particle energy (half of each pair and bond energy).
+__device__ __forceinline__ Force3 force_on(const Params& P, const Dev& D, const float4* __restrict__ X,
+                                           int lst, uint32_t i, float4 pi, uint32_t ti,
+                                           double* e) {
+    long long fx = 0, fy = 0, fz = 0;
+    const uint32_t* __restrict__ cnt = D.ccount[lst];
+    const uint32_t* __restrict__ mem = D.cmem[lst];
+    const int nc = (int)P.nc;
+    const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
+    const int prow = (int)ti * kMaxTypes;
+    for (int oz = -1; oz <= 1; ++oz) {
+        const int z = wrapc(cz + oz, nc);
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int y = wrapc(cy + oy, nc);
+            const int rowbase = (z * nc + y) * nc;
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int c = rowbase + wrapc(cx + ox, nc);
+                uint32_t m = cnt[c];
+                m = m < P.cellcap ? m : P.cellcap;
+                const uint32_t base = (uint32_t)c * P.cellcap;
+                for (uint32_t k = 0; k < m; ++k) {
+                    const uint32_t j = mem[base + k];
+                    if (j == i) continue;
+                    const float4 pj = X[j];
+                    const int pt = prow + (int)type_of(pj);
+                    const float dx = (float)mi_delta(pi.x, pj.x, P.L, P.invL);
+                    const float dy = (float)mi_delta(pi.y, pj.y, P.L, P.invL);
+                    const float dz = (float)mi_delta(pi.z, pj.z, P.L, P.invL);
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 < P.rc2[pt]) {
+                        // F_i = -24 eps (sigma/r)^6 (2 (sigma/r)^6 - 1) / r^2 * d
+                        const float sr2 = P.sig2[pt] / r2;
+                        const float sr6 = sr2 * sr2 * sr2;
+                        const float f = 6.0f * P.eps4[pt] * sr6 * (2.0f * sr6 - 1.0f) / r2;
+                        fx -= to_fix(f * dx);
+                        fy -= to_fix(f * dy);
+                        fz -= to_fix(f * dz);
+                        if (e) *e += 0.5 * ((double)P.eps4[pt] * ((double)sr6 * sr6 - sr6) + 0.25 * P.eps4[pt]);
+                    }
+                }
+            }
+        }
+    }
+    for (uint32_t s = 0; s < P.stat_max; ++s) {
+        const uint32_t w = D.stat[(size_t)s * P.n + i];
+        if (w == kEmpty) break;
+        const uint32_t j = w & kIdxMask;
+        bond_force(P, D, pi, X[j], w >> 24, i, j, fx, fy, fz, e);
+    }
+    const uint32_t cap = P.cap[ti];
+    for (uint32_t s = 0; s < cap; ++s) {
+        const uint32_t w = D.dyn[(size_t)s * P.n + i];
+        if (w == kEmpty) continue;
+        const uint32_t j = w & kIdxMask;
+        bond_force(P, D, pi, X[j], P.rbt[(w >> 24) & 0x7Fu], i, j, fx, fy, fz, e);
+    }
+    const long long lim = 1ll << 61;
+    if (fx > lim || fx < -lim || fy > lim || fy < -lim || fz > lim || fz < -lim)
+        atomicOr(&D.err[0], kErrForce);
+    return Force3{(float)((double)fx * kFixInv), (float)((double)fy * kFixInv),
+                  (float)((double)fz * kFixInv)};
+}
+
+// Insert particle i (position p) into cell list `lst`.
+__device__ __forceinline__ void bin_particle(const Params& P, const Dev& D, int lst, uint32_t i, float4 p) {
+    const int c = (cell_coord(p.z, P) * (int)P.nc + cell_coord(p.y, P)) * (int)P.nc + cell_coord(p.x, P);
+    const uint32_t slot = atomicAdd(&D.ccount[lst][c], 1u);
+    if (slot < P.cellcap) D.cmem[lst][(size_t)c * P.cellcap + slot] = i;
+    else atomicOr(&D.err[0], kErrOverflow);
+}
+
+__global__ void k_clear_counts(const Params P, const Dev D, int lst) {
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell; c += gridDim.x * blockDim.x)
+        D.ccount[lst][c] = 0u;
+}
+
+__global__ void k_bin(const Params P, const Dev D, int xin, int lst) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) bin_particle(P, D, lst, i, D.x[xin][i]);
+}
+
+// Forces (and per-particle energies) at the current positions into f4[off + i].
+__global__ void k_eval(const Params P, const Dev D, int xin, int lst, uint32_t off) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const float4 pi = D.x[xin][i];
+    double e = 0.0;
+    const Force3 f = force_on(P, D, D.x[xin], lst, i, pi, type_of(pi), &e);
+    D.f4[off + i] = make_float4(f.x, f.y, f.z, (float)e);
+}
+
+// u = v - h F / m (turn full-step velocities into the stored form).
+__global__ void k_init_u(const Params P, const Dev D, int xin, uint32_t off) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const float hm = P.h * P.inv_mass[type_of(D.x[xin][i])];
+    const float4 f = D.f4[off + i];
+    float4 u = D.u[i];
+    u.x -= hm * f.x;
+    u.y -= hm * f.y;
+    u.z -= hm * f.z;
+    D.u[i] = u;
+}
+
+// After a frozen sweep changed the bonds: keep v = u + h F/m unchanged.
+__global__ void k_fix_u(const Params P, const Dev D, int xin) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const float hm = P.h * P.inv_mass[type_of(D.x[xin][i])];
+    const float4 fo = D.f4[i];
+    const float4 fn = D.f4[P.n + i];
+    float4 u = D.u[i];
+    u.x += hm * fo.x - hm * fn.x;
+    u.y += hm * fo.y - hm * fn.y;
+    u.z += hm * fo.z - hm * fn.z;
+    D.u[i] = u;
+}
+
+// sum m v^2 of the full-step velocities (v = u + h F/m, F in f4) into ke_fix.
+__global__ __launch_bounds__(256) void k_ke_accum(const Params P, const Dev D, int xin) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long ke = 0ull;
+    if (i < P.n) {
+        const uint32_t ti = type_of(D.x[xin][i]);
+        const float hm = P.h * P.inv_mass[ti];
+        const float4 u = D.u[i], f = D.f4[i];
+        const float vx = u.x + hm * f.x, vy = u.y + hm * f.y, vz = u.z + hm * f.z;
+        const double v2 = ((double)vx * vx + (double)vy * vy) + (double)vz * vz;
+        ke = (unsigned long long)rint((double)P.mass[ti] * v2 * 4294967296.0);
+    }
+    for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
+    if (__lane_id() == 0 && ke) atomicAdd(D.ke_fix, ke);
+}
+
+// One BAOAB step t -> s = t + 1 for every particle.
+//   xin/xout = position buffers, lcur = cell list of x_t, lnext = list that
+//   receives x_s, lclr = list cleared for the step after, sp = slot holding t.
+__global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int xin, int lcur,
+                                              int lnext, int lclr, int sp, int accum_ke) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long t = D.stepv[sp];
+    const unsigned long long s = t + 1ull;
+    if (i == 0) D.stepv[sp ^ 1] = s;
+    for (uint32_t c = i; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
+    unsigned long long ke = 0ull;
+    if (i < P.n) {
+        const float4* __restrict__ X = D.x[xin];
+        const float4 pi = X[i];
+        const uint32_t ti = type_of(pi);
+        const Force3 F = force_on(P, D, X, lcur, i, pi, ti, nullptr);
+        const float4 u = D.u[i];
+        const float hm = P.h * P.inv_mass[ti];
+        // closing half kick of step t-1 (B), then the opening half kick of step t (B)
+        float vx = u.x + hm * F.x, vy = u.y + hm * F.y, vz = u.z + hm * F.z;
+        vx += hm * F.x;
+        vy += hm * F.y;
+        vz += hm * F.z;
+        float x = pi.x + P.h * vx, y = pi.y + P.h * vy, z = pi.z + P.h * vz;          // A
+        const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), D.tag[i], 0u, P.seed,
+                               stream_k1(kThermo, 0, 0));
+        // Box-Muller: u1 in (0, 1], u2 in [0, 1)
+        const float u1a = ((float)w.w0 + 1.0f) * 0x1.0p-32f;
+        const float u1b = ((float)w.w2 + 1.0f) * 0x1.0p-32f;
+        const float ra = sqrtf(-2.0f * logf(u1a));
+        const float rb = sqrtf(-2.0f * logf(u1b));
+        float sa, ca, sb, cb;
+        sincospif(2.0f * ((float)w.w1 * 0x1.0p-32f), &sa, &ca);
+        sincospif(2.0f * ((float)w.w3 * 0x1.0p-32f), &sb, &cb);
+        const float sd = P.noise_sd[ti];
+        vx = P.c1 * vx + sd * (ra * ca);                                              // O
+        vy = P.c1 * vy + sd * (ra * sa);
+        vz = P.c1 * vz + sd * (rb * cb);
+        x += P.h * vx;                                                                // A
+        y += P.h * vy;
+        z += P.h * vz;
+        int ix = 0, iy = 0, iz = 0;
+        if (x < -P.halfLf) { x += P.Lf; --ix; }
+        if (x >= P.halfLf) { x -= P.Lf; ++ix; }
+        if (y < -P.halfLf) { y += P.Lf; --iy; }
+        if (y >= P.halfLf) { y -= P.Lf; ++iy; }
+        if (z < -P.halfLf) { z += P.Lf; --iz; }
+        if (z >= P.halfLf) { z -= P.Lf; ++iz; }
+        if (ix | iy | iz) {
+            D.img[i] += ix;
+            D.img[P.n + i] += iy;
+            D.img[2 * P.n + i] += iz;
+        }
+        const float4 po = make_float4(x, y, z, pi.w);
+        D.x[xin ^ 1][i] = po;
+        D.u[i] = make_float4(vx, vy, vz, 0.0f);
+        bin_particle(P, D, lnext, i, po);
+        if (accum_ke) {
+            const double m = (double)P.mass[ti];
+            const double v2 = ((double)vx * vx + (double)vy * vy) + (double)vz * vz;
+            ke = (unsigned long long)rint(m * v2 * 4294967296.0);
+        }
+    }
+    if (accum_ke) {
+        unsigned long long sum = ke;
+        for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
+        if (__lane_id() == 0 && sum) atomicAdd(D.ke_fix, sum);
+    }
+}
+
+// ------------------------------------------------------------ sweep kernels
+__device__ __forceinline__ int sweep_reaction(const Params& P, unsigned long long s, int slot) {
+    __shared__ int alpha;
+    if (threadIdx.x == 0) alpha = reaction_at(P.seed, s, (int)P.nrx, slot);
+    __syncthreads();
+    return alpha;
+}
+
+// Proposal phase (Sec. 2.3, Fig. sweep a) fused with the first matching round.
+__global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur,
+                                                 int lst, int sp) {
+    const unsigned long long s = D.stepv[sp];
+    const int a = sweep_reaction(P, s, slot);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) D.live_count[0] = 0u;
+    if (i >= P.n) return;
+    D.best[2][i] = kNoKey;
+    D.claimed[i] = 0;
+    D.estate[i] = kEdgeNone;
+    D.prop[i] = -1;
+    const float4* __restrict__ X = D.x[xcur];
+    const float4 pi = X[i];
+    const uint32_t ti = type_of(pi);
+    const uint32_t ta = P.ra[a], tb = P.rb[a];
+    if (ti != ta && ti != tb) return;
+    if ((uint32_t)D.occ[i] >= P.cap[ti]) return;
+    const uint32_t want = ti == ta ? tb : ta;
+    // partners already bonded to i (any bond) are excluded
+    uint32_t mine[kMaxValence + kMaxStatic];
+#pragma unroll
+    for (int k = 0; k < kMaxValence; ++k)
+        mine[k] = (uint32_t)k < P.cap[ti] ? (D.dyn[(size_t)k * P.n + i] & kIdxMask) : kIdxMask;
+#pragma unroll
+    for (int k = 0; k < kMaxStatic; ++k)
+        mine[kMaxValence + k] = (uint32_t)k < P.stat_max ? (D.stat[(size_t)k * P.n + i] & kIdxMask) : kIdxMask;
+    const bool avoid = P.rself[a] != 0u;
+    const uint32_t mol_i = avoid ? D.mol[i] : 0u;
+    const double rmin = P.rmin[a], rmax = P.rmax[a], r0 = P.r0[a];
+    double best_score = 0.0;
+    uint32_t best_tag = 0xFFFFFFFFu;
+    int best_j = -1;
+    const uint32_t* __restrict__ cnt = D.ccount[lst];
+    const uint32_t* __restrict__ mem = D.cmem[lst];
+    const int nc = (int)P.nc;
+    const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
+    for (int oz = -1; oz <= 1; ++oz) {
+        const int z = wrapc(cz + oz, nc);
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int y = wrapc(cy + oy, nc);
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int c = (z * nc + y) * nc + wrapc(cx + ox, nc);
+                uint32_t m = cnt[c];
+                m = m < P.cellcap ? m : P.cellcap;
+                for (uint32_t k = 0; k < m; ++k) {
+                    const uint32_t j = mem[(size_t)c * P.cellcap + k];
+                    if (j == i) continue;
+                    const float4 pj = X[j];
+                    const uint32_t tj = type_of(pj);
+                    if (tj != want) continue;
+                    if ((uint32_t)D.occ[j] >= P.cap[tj]) continue;
+                    bool bonded = false;
+#pragma unroll
+                    for (int q = 0; q < kMaxValence + kMaxStatic; ++q) bonded |= mine[q] == j;
+                    if (bonded) continue;
+                    if (avoid && D.mol[j] == mol_i) continue;
+                    const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
+                    const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
+                    const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
+                    const double r = norm3(dx, dy, dz);
+                    if (!(r >= rmin && r <= rmax)) continue;
+                    const double score = fabs(r - r0);
+                    const uint32_t tgj = D.tag[j];
+                    if (best_j < 0 || score < best_score || (score == best_score && tgj < best_tag)) {
+                        best_score = score;
+                        best_tag = tgj;
+                        best_j = (int)j;
+                    }
+                }
+            }
+        }
+    }
+    if (best_j < 0) return;
+    const uint32_t tgi = D.tag[i];
+    const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), tgi, 0u, P.seed, stream_k1(kMatch, a, 0));
+    const uint64_t key = ((uint64_t)w.w0 << 32) | tgi;
+    D.prop[i] = best_j;
+    D.key[i] = key;
+    D.estate[i] = kEdgeLive;
+    atomicMin(&D.best[1][i], (unsigned long long)key);
+    atomicMin(&D.best[1][best_j], (unsigned long long)key);
+}
+
+// Acceptance of a claimed pair (Eq. pon): returns true when the bond forms,
+// in which case both sites get the bond in their first free slot.
+__device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a, unsigned long long s,
+                                            const float4* __restrict__ X, uint32_t i, uint32_t j) {
+    const float4 pi = X[i], pj = X[j];
+    const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
+    const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
+    const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
+    const double r = norm3(dx, dy, dz);
+    const double d = r - P.r0[a];
+    const double U = P.hk[a] * (d * d);
+    double kT = P.kT;
+    if (P.kt_kinetic) kT = (double)(*D.ke_fix) * kFixInv / (3.0 * (double)P.n);
+    double prob;
+    if (kT > 0.0) {
+        prob = P.pon[a] * exp(-U / kT);
+        prob = prob < 1.0 ? prob : 1.0;
+    } else {
+        prob = U <= 0.0 ? P.pon[a] : 0.0;
+    }
+    const uint32_t tgi = D.tag[i], tgj = D.tag[j];
+    const uint32_t lo = tgi < tgj ? tgi : tgj, hi = tgi < tgj ? tgj : tgi;
+    const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), lo, hi, P.seed, stream_k1(kOn, a, 0));
+    if (!(u53(w.w0, w.w1) < prob)) return false;
+    const uint32_t ti = type_of(pi), tj = type_of(pj);
+    const uint32_t tagbits = ((uint32_t)a << 24) | kNewBit;
+    for (uint32_t k = 0; k < P.cap[ti]; ++k) {
+        uint32_t* sl = &D.dyn[(size_t)k * P.n + i];
+        if (*sl == kEmpty) { *sl = j | tagbits; break; }
+    }
+    for (uint32_t k = 0; k < P.cap[tj]; ++k) {
+        uint32_t* sl = &D.dyn[(size_t)k * P.n + j];
+        if (*sl == kEmpty) { *sl = i | tagbits; break; }
+    }
+    D.occ[i] = (uint8_t)(D.occ[i] + 1);
+    D.occ[j] = (uint8_t)(D.occ[j] + 1);
+    return true;
+}
+
+// Claim round q: a live proposal whose key is the minimum at both of its
+// sites is part of the greedy matching; it is claimed and tried at once.
+__global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int slot, int q,
+                                               int xcur, int sp) {
+    const unsigned long long s = D.stepv[sp];
+    const int a = sweep_reaction(P, s, slot);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long* __restrict__ B = D.best[q % 3];
+    uint32_t matched = 0, formed = 0;
+    if (i < P.n && D.estate[i] == kEdgeLive) {
+        const uint32_t j = (uint32_t)D.prop[i];
+        const unsigned long long key = D.key[i];
+        if (B[i] == key && B[j] == key) {
+            matched = 1;
+            D.estate[i] = kEdgeMatched;
+            D.claimed[i] = 1;
+            D.claimed[j] = 1;
+            formed = accept_pair(P, D, a, s, D.x[xcur], i, j) ? 1u : 0u;
+        }
+    }
+    wave_add(&D.counters[a * 3 + 0], matched);
+    wave_add(&D.counters[a * 3 + 1], formed);
+}
+
+// Kill round q: drop proposals that touch a claimed site, post the keys of
+// the rest for round q; `compact` appends the survivors to the live list
+// (wave ballot + mbcnt prefix, one atomic per wave).
+__global__ __launch_bounds__(256) void k_kill(const Params P, const Dev D, int q, int compact) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) D.best[(q + 1) % 3][i] = kNoKey;
+    bool live = false;
+    if (i < P.n && D.estate[i] == kEdgeLive) {
+        const uint32_t j = (uint32_t)D.prop[i];
+        if (D.claimed[i] || D.claimed[j]) {
+            D.estate[i] = kEdgeDead;
+        } else {
+            live = true;
+            const unsigned long long key = D.key[i];
+            atomicMin(&D.best[q % 3][i], key);
+            atomicMin(&D.best[q % 3][j], key);
+        }
+    }
+    if (compact) {
+        const unsigned long long mask = __ballot(live);
+        if (mask) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            const int leader = __ffsll((long long)mask) - 1;
+            uint32_t base = 0;
+            if (__lane_id() == leader) base = atomicAdd(D.live_count, (uint32_t)__popcll(mask));
+            base = __shfl(base, leader, 64);
+            if (live) D.live[base + rank] = i;
+        }
+    }
+}
+
+// Remaining matching rounds inside one workgroup over the compacted live list.
+// Every round claims at least the globally smallest live key, so the loop ends
+// after at most `count` rounds.  Phases are separated by an agent-scope fence
+// and a barrier so that plain loads see the atomics and stores of the phase
+// before.
+__global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, int slot, int buf,
+                                                 int xcur, int sp) {
+    const unsigned long long s = D.stepv[sp];
+    const int a = sweep_reaction(P, s, slot);
+    unsigned long long* B = D.best[buf];
+    const uint32_t count = D.live_count[0];
+    __shared__ int any;
+    __shared__ uint32_t n_att, n_form;
+    if (threadIdx.x == 0) { n_att = 0; n_form = 0; }
+    for (uint32_t round = 0; round <= count; ++round) {
+        __syncthreads();
+        if (threadIdx.x == 0) any = 0;
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < count; e += blockDim.x) {
+            const uint32_t i = D.live[e];
+            if (D.estate[i] != kEdgeLive) continue;
+            const uint32_t j = (uint32_t)D.prop[i];
+            if (D.claimed[i] || D.claimed[j]) {
+                D.estate[i] = kEdgeDead;
+                continue;
+            }
+            atomicMin(&B[i], D.key[i]);
+            atomicMin(&B[j], D.key[i]);
+            any = 1;
+        }
+        __threadfence();
+        __syncthreads();
+        if (!any) break;
+        for (uint32_t e = threadIdx.x; e < count; e += blockDim.x) {
+            const uint32_t i = D.live[e];
+            if (D.estate[i] != kEdgeLive) continue;
+            const uint32_t j = (uint32_t)D.prop[i];
+            const unsigned long long key = D.key[i];
+            if (B[i] == key && B[j] == key) {
+                D.estate[i] = kEdgeMatched;
+                D.claimed[i] = 1;
+                D.claimed[j] = 1;
+                atomicAdd(&n_att, 1u);
+                if (accept_pair(P, D, a, s, D.x[xcur], i, j)) atomicAdd(&n_form, 1u);
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < count; e += blockDim.x) {
+            const uint32_t i = D.live[e];
+            B[i] = kNoKey;
+            B[(uint32_t)D.prop[i]] = kNoKey;
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (n_att) atomicAdd(&D.counters[a * 3 + 0], (unsigned long long)n_att);
+        if (n_form) atomicAdd(&D.counters[a * 3 + 1], (unsigned long long)n_form);
+    }
+}
+
+// Breaking phase (Sec. 2.3, Fig. sweep d): bonds of reaction a present at the
+// start of the sweep break with P0_off; bonds formed in this sweep only lose
+// their "new" mark.  Each site edits its own slots; both ends draw the same
+// number.  Also resets best[1] for the next reaction's proposal round.
+__global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int slot, int xcur, int sp,
+                                               int last) {
+    const unsigned long long s = D.stepv[sp];
+    const int a = sweep_reaction(P, s, slot);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (last && i == 0) *D.ke_fix = 0ull;
+    uint32_t broke = 0;
+    if (i < P.n) {
+        D.best[1][i] = kNoKey;
+        const uint32_t ti = type_of(D.x[xcur][i]);
+        const uint32_t tgi = D.tag[i];
+        uint32_t occ = D.occ[i];
+        for (uint32_t k = 0; k < P.cap[ti]; ++k) {
+            uint32_t* sl = &D.dyn[(size_t)k * P.n + i];
+            const uint32_t w = *sl;
+            if (w == kEmpty || ((w >> 24) & 0x7Fu) != (uint32_t)a) continue;
+            if (w & kNewBit) { *sl = w & ~kNewBit; continue; }
+            const uint32_t tgj = D.tag[w & kIdxMask];
+            const uint32_t lo = tgi < tgj ? tgi : tgj, hi = tgi < tgj ? tgj : tgi;
+            const Word4 r = philox((uint32_t)s, (uint32_t)(s >> 32), lo, hi, P.seed, stream_k1(kOff, a, 0));
+            if (u53(r.w0, r.w1) < P.poff[a]) {
+                *sl = kEmpty;
+                --occ;
+                if (tgi < tgj) ++broke;
+            }
+        }
+        D.occ[i] = (uint8_t)occ;
+    }
+    wave_add(&D.counters[a * 3 + 2], broke);
+}
+
+// ------------------------------------------------------------ I/O kernels
+// Scatter tag-ordered staging float4 into index order.
+__global__ void k_scatter_pos(const Params P, const Dev D, const float4* __restrict__ stage, int xdst) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < P.n) D.x[xdst][D.rtag[t]] = stage[t];
+}
+__global__ void k_scatter_vel(const Params P, const Dev D, const float4* __restrict__ stage) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < P.n) D.u[D.rtag[t]] = stage[t];
+}
+// Gather index-ordered float4 (positions, u, or f4 + h F/m) into tag order.
+// mode 0: positions, 1: full-step velocities (u + h F/m, F in f4), 2: forces (f4)
+__global__ void k_gather(const Params P, const Dev D, float4* __restrict__ out, int xin, int mode) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P.n) return;
+    const uint32_t i = D.rtag[t];
+    if (mode == 0) {
+        out[t] = D.x[xin][i];
+    } else if (mode == 1) {
+        const float hm = P.h * P.inv_mass[type_of(D.x[xin][i])];
+        const float4 u = D.u[i], f = D.f4[i];
+        out[t] = make_float4(u.x + hm * f.x, u.y + hm * f.y, u.z + hm * f.z, 0.0f);
+    } else {
+        out[t] = D.f4[i];
+    }
+}
+__global__ void k_gather_img(const Params P, const Dev D, int32_t* __restrict__ out) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P.n) return;
+    const uint32_t i = D.rtag[t];
+    out[3 * t + 0] = D.img[i];
+    out[3 * t + 1] = D.img[P.n + i];
+    out[3 * t + 2] = D.img[2 * P.n + i];
+}
+
+// Energies and bond counts: red[0] = PE, red[1] = KE (2^-32 fixed point),
+// red[2 + a] = bonds of reaction a.
+__global__ __launch_bounds__(256) void k_observe(const Params P, const Dev D, int xin) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint32_t nb[kMaxRx];
+    if (threadIdx.x < kMaxRx) nb[threadIdx.x] = 0u;
+    __syncthreads();
+    unsigned long long pe = 0, ke = 0;
+    if (i < P.n) {
+        const uint32_t ti = type_of(D.x[xin][i]);
+        const float4 f = D.f4[i];
+        const float4 u = D.u[i];
+        const float hm = P.h * P.inv_mass[ti];
+        const double vx = u.x + hm * f.x, vy = u.y + hm * f.y, vz = u.z + hm * f.z;
+        pe = (unsigned long long)rint((double)f.w * 4294967296.0);
+        ke = (unsigned long long)rint(0.5 * (double)P.mass[ti] * ((vx * vx + vy * vy) + vz * vz) * 4294967296.0);
+        const uint32_t tgi = D.tag[i];
+        for (uint32_t k = 0; k < P.cap[ti]; ++k) {
+            const uint32_t w = D.dyn[(size_t)k * P.n + i];
+            if (w == kEmpty) continue;
+            if (D.tag[w & kIdxMask] > tgi) atomicAdd(&nb[(w >> 24) & 0x7Fu], 1u);
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        pe += __shfl_xor(pe, off, 64);
+        ke += __shfl_xor(ke, off, 64);
+    }
+    if (__lane_id() == 0) {
+        atomicAdd(&D.red[0], pe);
+        atomicAdd(&D.red[1], ke);
+    }
+    __syncthreads();
+    if (threadIdx.x < P.nrx && nb[threadIdx.x]) atomicAdd(&D.red[2 + threadIdx.x], (unsigned long long)nb[threadIdx.x]);
+}
+
+// Connected components over static + dynamic bonds (union by minimum index).
+__device__ __forceinline__ uint32_t cc_root(const uint32_t* parent, uint32_t v) {
+    uint32_t p = parent[v];
+    while (p != v) { v = p; p = parent[v]; }
+    return v;
+}
+__global__ void k_cc_init(const Params P, const Dev D) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) D.parent[i] = i;
+}
+__device__ __forceinline__ void cc_hook_edge(const Dev& D, uint32_t i, uint32_t j, uint32_t* changed) {
+    if (j < i) return;                     // each edge once, from its lower index
+    const uint32_t ri = cc_root(D.parent, i), rj = cc_root(D.parent, j);
+    if (ri == rj) return;
+    atomicMin(&D.parent[ri < rj ? rj : ri], ri < rj ? ri : rj);
+    *changed = 1u;
+}
+__global__ void k_cc_hook(const Params P, const Dev D, uint32_t* changed, int xin) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    for (uint32_t k = 0; k < P.stat_max; ++k) {
+        const uint32_t w = D.stat[(size_t)k * P.n + i];
+        if (w == kEmpty) break;
+        cc_hook_edge(D, i, w & kIdxMask, changed);
+    }
+    const uint32_t cap = P.cap[type_of(D.x[xin][i])];
+    for (uint32_t k = 0; k < cap; ++k) {
+        const uint32_t w = D.dyn[(size_t)k * P.n + i];
+        if (w != kEmpty) cc_hook_edge(D, i, w & kIdxMask, changed);
+    }
+}
+__global__ void k_cc_compress(const Params P, const Dev D) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) D.parent[i] = cc_root(D.parent, i);
+}
+__global__ void k_cc_size(const Params P, const Dev D) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) atomicAdd(&D.scan[D.parent[i]], 1u);
+}
+__global__ void k_cc_max(const Params P, const Dev D) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n && D.scan[i]) atomicMax((unsigned long long*)&D.red[2 + kMaxRx], (unsigned long long)D.scan[i]);
+}
+
+// Bond read-out, in tag order.  Pass 1: per tag, the number of its dynamic
+// bonds to a higher tag, exclusive-scanned inside each block (wave shuffles),
+// block totals to `bsum`.  Pass 2 scans `bsum`; pass 3 writes the rows.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t lane = __lane_id(), wid = threadIdx.x / 64;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= (uint32_t)off) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    const uint32_t nw = blockDim.x / 64;
+    for (uint32_t w = 0; w < nw; ++w) {
+        if (w < wid) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+__device__ __forceinline__ int rows_of(const Params& P, const Dev& D, int xin, uint32_t t, uint32_t* ptag,
+                                       uint32_t* pbt) {
+    const uint32_t i = D.rtag[t];
+    const uint32_t ti = type_of(D.x[xin][i]);
+    int c = 0;
+    for (uint32_t k = 0; k < P.cap[ti]; ++k) {
+        const uint32_t w = D.dyn[(size_t)k * P.n + i];
+        if (w == kEmpty) continue;
+        const uint32_t tj = D.tag[w & kIdxMask];
+        if (tj <= t) continue;
+        if (ptag) {
+            const uint32_t bt = P.rbt[(w >> 24) & 0x7Fu];
+            int p = c;   // insertion sort by (partner tag, bond type)
+            while (p > 0 && (ptag[p - 1] > tj || (ptag[p - 1] == tj && pbt[p - 1] > bt))) {
+                ptag[p] = ptag[p - 1];
+                pbt[p] = pbt[p - 1];
+                --p;
+            }
+            ptag[p] = tj;
+            pbt[p] = bt;
+        }
+        ++c;
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(256) void k_rows_count(const Params P, const Dev D, int xin, uint32_t* bsum) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t c = t < P.n ? (uint32_t)rows_of(P, D, xin, t, nullptr, nullptr) : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(c, &tot);
+    if (t < P.n) D.scan[t] = ex;
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_bsum(uint32_t* bsum, uint32_t nb) {
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nb; base += blockDim.x) {
+        const uint32_t k = base + threadIdx.x;
+        const uint32_t v = k < nb ? bsum[k] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(v, &tot);
+        const uint32_t c0 = carry;
+        if (k < nb) bsum[k] = c0 + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c0 + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_rows_emit(const Params P, const Dev D, int xin, const uint32_t* bsum,
+                                                   uint32_t* pairs, uint32_t* btypes) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P.n) return;
+    uint32_t ptag[kMaxValence], pbt[kMaxValence];
+    const int c = rows_of(P, D, xin, t, ptag, pbt);
+    const uint32_t at = bsum[blockIdx.x] + D.scan[t];
+    for (int k = 0; k < c; ++k) {
+        pairs[2 * (at + k)] = t;
+        pairs[2 * (at + k) + 1] = ptag[k];
+        btypes[at + k] = pbt[k];
+    }
+}
+
+}  // namespace dyb

@@ -1,0 +1,338 @@
+"""ctypes binding of the C ABI in include/dybond.h (argument marshalling only).
+
+Every function named ``db_*`` here calls the C function of the same name in
+``libdybond.so``; arrays are passed as contiguous numpy buffers and a
+non-OK status raises :class:`DybondError`.  All computation happens in the
+HIP library; if the library has not been built this module raises instead of
+falling back to anything else.
+"""
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdybond.so")
+
+DB_OK, DB_EINVAL, DB_ENOMEM, DB_EDEVICE, DB_ESTATE, DB_ERANGE, DB_EBOND, DB_ETRUNC, DB_EOVERFLOW = range(9)
+STATUS_NAMES = ["DB_OK", "DB_EINVAL", "DB_ENOMEM", "DB_EDEVICE", "DB_ESTATE", "DB_ERANGE",
+                "DB_EBOND", "DB_ETRUNC", "DB_EOVERFLOW"]
+DB_BOND_HARMONIC, DB_BOND_FENE = 0, 1
+DB_KT_SETPOINT, DB_KT_KINETIC = 0, 1
+MAX_RX = 8
+
+
+class DybondError(RuntimeError):
+    def __init__(self, status, message):
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {message}")
+        self.status = status
+        self.name = name
+
+
+class ReactionDesc(ctypes.Structure):
+    _fields_ = [("type_a", ctypes.c_uint32), ("type_b", ctypes.c_uint32),
+                ("bond_type", ctypes.c_uint32),
+                ("r_min", ctypes.c_double), ("r_max", ctypes.c_double),
+                ("k_on", ctypes.c_double), ("k_off", ctypes.c_double),
+                ("epsilon", ctypes.c_double), ("p_on0", ctypes.c_double),
+                ("self_avoid", ctypes.c_int32)]
+
+
+class Observables(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_uint64), ("n_reactions", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32),
+                ("n_bonds", ctypes.c_uint64 * MAX_RX), ("attempts", ctypes.c_uint64 * MAX_RX),
+                ("forms", ctypes.c_uint64 * MAX_RX), ("breaks", ctypes.c_uint64 * MAX_RX),
+                ("bonded_fraction", ctypes.c_double * MAX_RX),
+                ("largest_cluster_fraction", ctypes.c_double),
+                ("pe", ctypes.c_double), ("ke", ctypes.c_double), ("t_kin", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_U32 = ctypes.c_uint32
+_U64 = ctypes.c_uint64
+_D = ctypes.c_double
+_I = ctypes.c_int
+_SIGS = {
+    "db_create": (_I, [_U32, _U32, _D, _U32, _I, ctypes.POINTER(_P)]),
+    "db_destroy": (None, [_P]),
+    "db_set_type": (_I, [_P, _U32, _U32, _D, _D, _D]),
+    "db_set_particles": (_I, [_P, _P, _P, _P]),
+    "db_add_bond_type": (_I, [_P, _I, _D, _D, ctypes.POINTER(_U32)]),
+    "db_add_static_bonds": (_I, [_P, _P, _P, _U64]),
+    "db_add_reaction": (_I, [_P, ctypes.POINTER(ReactionDesc), ctypes.POINTER(_U32)]),
+    "db_set_integrator": (_I, [_P, _D, _D, _D, _U32, _I]),
+    "db_validate": (_I, [_P]),
+    "db_get_reaction": (_I, [_P, _U32, ctypes.POINTER(ReactionDesc), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "db_commit": (_I, [_P]),
+    "db_step": (_I, [_P, _U64]),
+    "db_sweep_frozen": (_I, [_P, _U64]),
+    "db_set_state": (_I, [_P, _U64, _P, _P, _P, _P, _U64]),
+    "db_read_positions": (_I, [_P, _P, _P]),
+    "db_read_velocities": (_I, [_P, _P]),
+    "db_read_forces": (_I, [_P, _P]),
+    "db_read_bonds": (_I, [_P, _P, _P, _U64, ctypes.POINTER(_U64)]),
+    "db_read_observables": (_I, [_P, ctypes.POINTER(Observables)]),
+    "db_get_step": (_U64, [_P]),
+    "db_last_error": (ctypes.c_char_p, [_P]),
+    "db_set_stream": (_I, [_P, _P]),
+    "db_kernel_timing": (_I, [_P, _I]),
+    "db_read_kernel_time": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_U64), ctypes.POINTER(_D)]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libdybond.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(handle, status):
+    if status != DB_OK:
+        msg = load().db_last_error(handle)
+        raise DybondError(status, msg.decode() if msg else "")
+
+
+def _buf(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(_P)
+
+
+# ---------------------------------------------------------------- thin wrappers
+def db_create(n, n_types, box_L, seed, device=0):
+    h = _P()
+    st = load().db_create(n, n_types, box_L, seed, device, ctypes.byref(h))
+    _check(None, st)
+    return h
+
+
+def db_destroy(h):
+    load().db_destroy(h)
+
+
+def db_set_type(h, t, valence, sigma, eps, mass):
+    _check(h, load().db_set_type(h, t, valence, sigma, eps, mass))
+
+
+def db_set_particles(h, pos, vel, types):
+    p, pp = _buf(pos, np.float32)
+    v, vp = _buf(vel, np.float32)
+    t, tp = _buf(types, np.uint32)
+    _check(h, load().db_set_particles(h, pp, vp, tp))
+
+
+def db_add_bond_type(h, kind, k, r0):
+    i = _U32()
+    _check(h, load().db_add_bond_type(h, kind, k, r0, ctypes.byref(i)))
+    return i.value
+
+
+def db_add_static_bonds(h, pairs, bond_types):
+    p, pp = _buf(np.asarray(pairs).reshape(-1, 2), np.uint32)
+    b, bp = _buf(np.asarray(bond_types).reshape(-1), np.uint32)
+    _check(h, load().db_add_static_bonds(h, pp, bp, len(b)))
+
+
+def make_reaction(type_a, type_b, bond_type, r_min, r_max, k_on=math.nan, k_off=math.nan,
+                  epsilon=math.nan, p_on0=math.nan, self_avoid=-1):
+    sa = -1 if self_avoid is None else int(self_avoid)
+    return ReactionDesc(type_a, type_b, bond_type, r_min, r_max, k_on, k_off, epsilon, p_on0, sa)
+
+
+def db_add_reaction(h, desc):
+    i = _U32()
+    _check(h, load().db_add_reaction(h, ctypes.byref(desc), ctypes.byref(i)))
+    return i.value
+
+
+def db_set_integrator(h, dt, kT, gamma, sweep_period, kt_source=DB_KT_SETPOINT):
+    _check(h, load().db_set_integrator(h, dt, kT, gamma, sweep_period, kt_source))
+
+
+def db_validate(h):
+    _check(h, load().db_validate(h))
+
+
+def db_get_reaction(h, rid):
+    d = ReactionDesc()
+    pon, poff = _D(), _D()
+    _check(h, load().db_get_reaction(h, rid, ctypes.byref(d), ctypes.byref(pon), ctypes.byref(poff)))
+    return d, pon.value, poff.value
+
+
+def db_commit(h):
+    _check(h, load().db_commit(h))
+
+
+def db_step(h, n_steps):
+    _check(h, load().db_step(h, n_steps))
+
+
+def db_sweep_frozen(h, step_key):
+    _check(h, load().db_sweep_frozen(h, step_key))
+
+
+def db_set_state(h, step, pos, vel, dyn_pairs=None, dyn_bond_types=None):
+    p, pp = _buf(pos, np.float32)
+    v, vp = _buf(vel, np.float32)
+    pairs = np.zeros((0, 2), np.uint32) if dyn_pairs is None else np.asarray(dyn_pairs).reshape(-1, 2)
+    bts = np.zeros(0, np.uint32) if dyn_bond_types is None else np.asarray(dyn_bond_types).reshape(-1)
+    a, ap = _buf(pairs, np.uint32)
+    b, bp = _buf(bts, np.uint32)
+    _check(h, load().db_set_state(h, step, pp, vp, ap, bp, len(b)))
+
+
+def db_read_positions(h, n, with_images=False):
+    pos = np.empty((n, 3), np.float32)
+    img = np.empty((n, 3), np.int32) if with_images else None
+    _check(h, load().db_read_positions(h, pos.ctypes.data_as(_P),
+                                       img.ctypes.data_as(_P) if with_images else None))
+    return (pos, img) if with_images else pos
+
+
+def db_read_velocities(h, n):
+    v = np.empty((n, 3), np.float32)
+    _check(h, load().db_read_velocities(h, v.ctypes.data_as(_P)))
+    return v
+
+
+def db_read_forces(h, n):
+    f = np.empty((n, 3), np.float32)
+    _check(h, load().db_read_forces(h, f.ctypes.data_as(_P)))
+    return f
+
+
+def db_read_bonds(h):
+    """Dynamic bonds as an (m, 3) uint32 array (tag_lo, tag_hi, bond_type)."""
+    cnt = _U64()
+    st = load().db_read_bonds(h, None, None, 0, ctypes.byref(cnt))
+    if st not in (DB_OK, DB_ETRUNC):
+        _check(h, st)
+    m = cnt.value
+    pairs = np.empty((m, 2), np.uint32)
+    bts = np.empty(m, np.uint32)
+    if m:
+        _check(h, load().db_read_bonds(h, pairs.ctypes.data_as(_P), bts.ctypes.data_as(_P), m,
+                                       ctypes.byref(cnt)))
+    return np.concatenate([pairs, bts[:, None]], axis=1).reshape(-1, 3)
+
+
+def db_read_observables(h):
+    o = Observables()
+    _check(h, load().db_read_observables(h, ctypes.byref(o)))
+    R = o.n_reactions
+    return {"step": o.step, "n_bonds": np.array(o.n_bonds[:R]), "attempts": np.array(o.attempts[:R]),
+            "forms": np.array(o.forms[:R]), "breaks": np.array(o.breaks[:R]),
+            "bonded_fraction": np.array(o.bonded_fraction[:R]),
+            "largest_cluster_fraction": o.largest_cluster_fraction,
+            "PE": o.pe, "KE": o.ke, "T_kin": o.t_kin}
+
+
+def db_get_step(h):
+    return int(load().db_get_step(h))
+
+
+def db_last_error(h):
+    m = load().db_last_error(h)
+    return m.decode() if m else ""
+
+
+def db_set_stream(h, stream_ptr):
+    _check(h, load().db_set_stream(h, stream_ptr))
+
+
+def db_kernel_timing(h, enable):
+    _check(h, load().db_kernel_timing(h, 1 if enable else 0))
+
+
+def db_read_kernel_time(h, kernel):
+    n, ms = _U64(), _D()
+    _check(h, load().db_read_kernel_time(h, kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+# ---------------------------------------------------------------- convenience
+class System:
+    """Owns one handle; ``from_workload`` replays the set-up calls for a
+    workload built by :mod:`paper_2609_21204_amd.inputs`."""
+
+    def __init__(self, n, n_types, box_L, seed, device=0):
+        self.n = int(n)
+        self.h = db_create(n, n_types, box_L, seed, device)
+
+    @classmethod
+    def from_workload(cls, w, device=0, commit=True, kt_source=DB_KT_SETPOINT):
+        s = cls(w.n, len(w.types), w.L, w.seed, device)
+        for t, (val, sig, eps, m) in enumerate(w.types):
+            db_set_type(s.h, t, val, sig, eps, m)
+        db_set_particles(s.h, w.pos, w.vel, w.type_id)
+        for kind, k, r0 in w.bond_types:
+            db_add_bond_type(s.h, kind, k, r0)
+        if len(w.static_pairs):
+            db_add_static_bonds(s.h, w.static_pairs, w.static_types)
+        for r in w.reactions:
+            db_add_reaction(s.h, make_reaction(**r))
+        db_set_integrator(s.h, w.dt, w.kT, w.gamma, w.period, kt_source)
+        if commit:
+            db_commit(s.h)
+        return s
+
+    def close(self):
+        if self.h:
+            db_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # marshalling shortcuts
+    def step(self, n):
+        db_step(self.h, n)
+
+    def sweep_frozen(self, key):
+        db_sweep_frozen(self.h, key)
+
+    def positions(self, with_images=False):
+        return db_read_positions(self.h, self.n, with_images)
+
+    def velocities(self):
+        return db_read_velocities(self.h, self.n)
+
+    def forces(self):
+        return db_read_forces(self.h, self.n)
+
+    def bonds(self):
+        return db_read_bonds(self.h)
+
+    def observables(self):
+        return db_read_observables(self.h)
+
+    def set_state(self, step, pos, vel, pairs=None, bts=None):
+        db_set_state(self.h, step, pos, vel, pairs, bts)
+
+    @property
+    def step_count(self):
+        return db_get_step(self.h)

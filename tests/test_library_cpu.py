@@ -1,0 +1,126 @@
+"""Host-side checks of the C-ABI library that need no GPU.
+
+The library must load and export every entry point that include/dybond.h
+declares, and its set-up path (validation and rate closure) runs on the host
+before any device is touched.
+"""
+
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.dybond import resolve_rates
+from paper_2609_21204_amd import dybond as db
+from paper_2609_21204_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "dybond.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(db_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = db.load()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding wraps each of them under the same name
+    for name in names:
+        assert callable(getattr(db, name)), name
+
+
+def _configured(w, **over):
+    s = db.System.from_workload(w, commit=False)
+    return s
+
+
+def test_validation_accepts_the_workloads():
+    for make in (inputs.small,):
+        w = make(seed=1)
+        s = _configured(w)
+        db.db_validate(s.h)
+        s.close()
+
+
+def test_rate_closure_matches_oracle_bit_for_bit():
+    w = inputs.small(seed=1)
+    cases = [dict(epsilon=5.0, p_on0=1.0), dict(k_on=3.0, k_off=0.5), dict(k_on=1.5, epsilon=2.0),
+             dict(k_off=0.25, epsilon=1.0), dict(k_off=0.25, epsilon=1.0, p_on0=0.05 * 0.25 * math.exp(1.0))]
+    for c in cases:
+        s = db.System(w.n, 2, w.L, 1)
+        db.db_set_type(s.h, 0, 1, 1.0, 1.0, 1.0)
+        db.db_set_type(s.h, 1, 1, 1.0, 1.0, 1.0)
+        db.db_set_particles(s.h, w.pos, w.vel, w.type_id)
+        db.db_add_bond_type(s.h, db.DB_BOND_HARMONIC, 100.0, 1.0)
+        db.db_add_reaction(s.h, db.make_reaction(0, 1, 0, 0.0, 1.3, self_avoid=0, **c))
+        db.db_set_integrator(s.h, 0.005, 1.0, 1.0, 10)
+        db.db_validate(s.h)
+        d, pon, poff = db.db_get_reaction(s.h, 0)
+        want = resolve_rates(c.get("k_on", math.nan), c.get("k_off", math.nan),
+                             c.get("epsilon", math.nan), c.get("p_on0", math.nan), 0.005, 10)
+        assert (d.k_on, d.k_off, pon, poff) == (want[0], want[1], want[3], want[4])
+        s.close()
+
+
+def _status_of(fn):
+    with pytest.raises(db.DybondError) as e:
+        fn()
+    return e.value.name
+
+
+def _two_particle(rx, L=6.0, period=10, dt=0.005):
+    s = db.System(2, 2, L, 1)
+    db.db_set_type(s.h, 0, 1, 1.0, 1.0, 1.0)
+    db.db_set_type(s.h, 1, 1, 1.0, 1.0, 1.0)
+    db.db_set_particles(s.h, [[0, 0, 0], [1, 0, 0]], np.zeros((2, 3)), [0, 1])
+    db.db_add_bond_type(s.h, db.DB_BOND_HARMONIC, 100.0, 1.0)
+    db.db_add_bond_type(s.h, db.DB_BOND_FENE, 30.0, 1.5)
+    if rx is not None:
+        db.db_add_reaction(s.h, rx)
+    db.db_set_integrator(s.h, dt, 1.0, 1.0, period)
+    return s
+
+
+def _validate_status(rx, **kw):
+    s = _two_particle(rx, **kw)
+    try:
+        db.db_validate(s.h)
+        return "DB_OK"
+    except db.DybondError as e:
+        return e.name
+    finally:
+        s.close()
+
+
+def test_validation_errors_on_host():
+    ok = dict(epsilon=2.0, p_on0=0.5)
+    R = db.make_reaction
+    assert _validate_status(R(0, 1, 0, 0.0, 1.3, self_avoid=None, **ok)) == "DB_EINVAL"
+    assert _validate_status(R(0, 1, 0, 0.0, 1.3, self_avoid=2, **ok)) == "DB_EINVAL"
+    # P0 = k n dt > 1 (Eq. probs)
+    assert _validate_status(R(0, 1, 0, 0.0, 1.3, k_on=30.0, k_off=1.0, self_avoid=0)) == "DB_ERANGE"
+    # under-determined rates
+    assert _validate_status(R(0, 1, 0, 0.0, 1.3, k_on=3.0, self_avoid=0)) == "DB_EINVAL"
+    # inconsistent over-specification
+    assert _validate_status(R(0, 1, 0, 0.0, 1.3, k_on=3.0, k_off=1.0, epsilon=2.0, self_avoid=0)) == "DB_EINVAL"
+    # dynamic bonds must be harmonic; window must be ordered
+    assert _validate_status(R(0, 1, 1, 0.0, 1.3, self_avoid=0, **ok)) == "DB_EINVAL"
+    assert _validate_status(R(0, 1, 0, 1.3, 1.3, self_avoid=0, **ok)) == "DB_EINVAL"
+    # box must hold 3 cells of the search radius
+    assert _validate_status(R(0, 1, 0, 0.0, 1.3, self_avoid=0, **ok), L=3.8) == "DB_EINVAL"
+    # a valid configuration passes validation on the host
+    assert _validate_status(R(0, 1, 0, 0.0, 1.3, self_avoid=1, **ok)) == "DB_OK"
+    # out-of-box positions and bad types are rejected when set
+    with db.System(2, 2, 6.0, 1) as s:
+        assert _status_of(lambda: db.db_set_particles(s.h, [[0, 0, 0], [3.0, 0, 0]], np.zeros((2, 3)), [0, 1])) == "DB_EINVAL"
+        assert _status_of(lambda: db.db_set_particles(s.h, [[0, 0, 0], [1.0, 0, 0]], np.zeros((2, 3)), [0, 2])) == "DB_EINVAL"
+        assert _status_of(lambda: db.db_set_type(s.h, 0, 9, 1.0, 1.0, 1.0)) == "DB_EINVAL"
+        assert _status_of(lambda: db.db_step(s.h, 1)) == "DB_ESTATE"
+    assert _status_of(lambda: db.db_create(0, 1, 5.0, 1)) == "DB_EINVAL"
