@@ -1,0 +1,170 @@
+"""Throughput of the dynamic-bonding Langevin MD step on one GPU.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload gel|telechelic|small]
+
+Prints one JSON line: particle-timesteps/s of db_step (bonding sweeps
+included) on a synthetic workload already resident on the GPU, the roofline
+position of the dominant kernel (k_step, timed with HIP events on the stream
+it runs on), and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_gel200k_traffic.txt")
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10000)
+    p.add_argument("--warmup", type=int, default=200)
+    p.add_argument("--workload", default="gel", choices=["gel", "telechelic", "small"])
+    p.add_argument("--n", type=int, default=0, help="particle count for the gel workload (default 200000)")
+    p.add_argument("--seed", type=int, default=1)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-steps", type=int, default=20)
+    p.add_argument("--profile-steps", type=int, default=2000)
+    return p.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("device.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2609_21204_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_tag):
+    """HBM bytes per k_step launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source and this workload."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    src = re.search(r"kernel_source_hash:\s*(\S+)", text)
+    wl = re.search(r"workload:\s*(\S+)", text)
+    val = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (src and wl and val) or src.group(1) != kernel_source_hash() or wl.group(1) != workload_tag:
+        return None
+    return float(val.group(1))
+
+
+def algorithmic_bytes_per_particle(w):
+    """Minimum bytes one k_step launch must move per particle: position and
+    velocity read + write (4 x 12 B), the type (1 B), and the 5 B bond slot
+    words (4 B partner + 1 B type) the particle's valence and static bonds
+    span."""
+    import numpy as np
+    cap = np.array([t[0] for t in w.types])[w.type_id]
+    stat = np.zeros(w.n)
+    if len(w.static_pairs):
+        np.add.at(stat, w.static_pairs.reshape(-1).astype(np.int64), 1)
+    slots = float(np.mean(cap + stat))
+    return 48.0 + 1.0 + 5.0 * slots, slots
+
+
+def cpu_baseline(w, steps):
+    """The FP64 oracle, single-threaded, on `steps` steps of the same workload
+    (the first sweep falls inside the sample)."""
+    from threadpoolctl import threadpool_limits
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from helpers import oracle_from_workload
+    with threadpool_limits(limits=1):
+        o = oracle_from_workload(w)
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t0
+    return {"value": w.n * steps / dt, "unit": "particle-timesteps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps of the {w.name} workload (N={w.n}, "
+                      f"{steps // w.period} bonding sweeps) from its initial state, {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is described, not built)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2609_21204_amd import dybond as db
+    from paper_2609_21204_amd import inputs
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no HIP device"}))
+        sys.exit(1)
+    if a.workload == "gel":
+        w = inputs.gel(seed=a.seed, n=a.n or 200000)
+    else:
+        w = inputs.WORKLOADS[a.workload](seed=a.seed)
+    tag = f"{w.name}{w.n // 1000}k"
+    s = db.System.from_workload(w, device=0)
+    s.step(a.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(a.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = w.n * a.steps / elapsed
+
+    # per-kernel HIP-event timing on the library's stream (graph replay off)
+    db.db_kernel_timing(s.h, 1)
+    s.step(a.profile_steps)
+    kern = {}
+    for name in ("k_step", "k_propose", "k_claim", "k_kill", "k_finish", "k_break"):
+        cnt, ms = db.db_read_kernel_time(s.h, name)
+        if cnt:
+            kern[name] = {"launches": cnt, "avg_us": 1000.0 * ms / cnt}
+    db.db_kernel_timing(s.h, 0)
+    obs = s.observables()
+    s.close()
+
+    bpp, slots = algorithmic_bytes_per_particle(w)
+    step_us = kern["k_step"]["avg_us"]
+    achieved = bpp * w.n / (step_us * 1e-6) / 1e9
+    traffic = measured_traffic(tag)
+    line = {
+        "metric": "particle-timesteps/sec with bonding (1 GPU)",
+        "value": value,
+        "unit": "particle-timesteps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1000.0 * elapsed / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": tag, "n_particles": w.n, "box_L": round(w.L, 4),
+                   "types": len(w.types), "reactions": len(w.reactions),
+                   "sweep_period": w.period, "dt": w.dt, "kT": w.kT, "gamma": w.gamma,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "k_step", "kernel_avg_us": step_us,
+                     "alg_bytes_per_particle": bpp, "bond_slots_per_particle": slots},
+        "kernels": kern,
+        "state": {"bonds": obs["n_bonds"].tolist(), "bonded_fraction": obs["bonded_fraction"].tolist(),
+                  "T_kin": obs["T_kin"]},
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

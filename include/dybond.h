@@ -141,6 +141,12 @@ DB_API db_status db_add_reaction(db_system* sys, const db_reaction_desc* desc, u
 DB_API db_status db_set_integrator(db_system* sys, double dt, double kT, double gamma,
                             uint32_t sweep_period, int kt_source);
 
+/* Particle slots per cell of the neighbour cell list.  0 (default) = chosen
+ * at commit from the density and the fullest cell of the initial state (at
+ * least 16); any other value in [1, 1024] is used as given.  A cell that
+ * fills up during a run makes db_step return DB_EOVERFLOW. */
+DB_API db_status db_set_cell_capacity(db_system* sys, uint32_t slots);
+
 /* Validate the configuration and close the rate parameters of every reaction
  * (Eq. epsilon, Eq. probs) without touching a GPU.  Errors: DB_EINVAL (bad
  * or missing parameter, under-determined or inconsistent rates, box smaller

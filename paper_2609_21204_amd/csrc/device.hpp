@@ -112,6 +112,8 @@ __device__ __forceinline__ double norm3(double dx, double dy, double dz) {
 
 // ---------------------------------------------------------------- blocks
 struct Params {
+    uint32_t tile[3];      // cells per tile along x, y, z (core of one k_step workgroup)
+    uint32_t ntile[3];     // tiles along x, y, z
     uint32_t n, ntypes, nrx, cap_max;
     uint32_t stat_max, nc, ncell, cellcap;
     uint32_t seed, period, kt_kinetic, any_self_avoid;
@@ -124,16 +126,26 @@ struct Params {
     float noise_sd[kMaxTypes];         // sqrt(1 - c1^2) sqrt(kT / m)
     float mass[kMaxTypes];
     uint32_t cap[kMaxTypes];
-    float sig2[kMaxTypes * kMaxTypes];
-    float eps4[kMaxTypes * kMaxTypes];  // 4 eps_ij (0: no WCA)
-    float rc2[kMaxTypes * kMaxTypes];   // (2^(1/6) sigma_ij)^2
+    float rc2_pre[kMaxTypes * kMaxTypes];  // FP32 prefilter: (2^(1/6) sigma_ij)^2 (1 + 1e-3) + 1e-4; 0 = no WCA
     uint32_t bkind[kMaxBondTypes];
-    float bk[kMaxBondTypes], br0[kMaxBondTypes], bR02[kMaxBondTypes];
+    double bk[kMaxBondTypes], br0[kMaxBondTypes], bR02[kMaxBondTypes], binvR02[kMaxBondTypes];
+    float rmax2_pre[kMaxRx], rmin2_pre[kMaxRx];  // FP32 prefilter of the reaction window
     uint32_t ra[kMaxRx], rb[kMaxRx], rbt[kMaxRx], rself[kMaxRx];
     double rmin[kMaxRx], rmax[kMaxRx], r0[kMaxRx], hk[kMaxRx], pon[kMaxRx], poff[kMaxRx];
 };
 
+// WCA parameters of one type pair, evaluated in FP64.
+struct PairTab {
+    double sig2;   // sigma_ij^2
+    double eps24;  // 24 eps_ij
+    double rc;     // 2^(1/6) sigma_ij (0: no WCA)
+    double rc2_lo, rc2_hi;   // rc^2 (1 -/+ 1e-14): r < rc is decided without sqrt outside this band
+    double eps;    // eps_ij
+    double pad0, pad1;
+};
+
 struct Dev {
+    const PairTab* pair;   // kMaxTypes x kMaxTypes
     float4* x[2];          // positions (xyz) + type bits (w), double-buffered
     float4* u;             // velocity before the closing half kick of the last step
     int32_t* img;          // image counters, 3 x n
@@ -144,7 +156,7 @@ struct Dev {
     uint32_t* stat;        // stat_max x n static slots: partner | bond type << 24
     uint32_t* mol;         // molecule id (static-bond component)
     uint32_t* ccount[3];   // per-cell counts of three rotating cell lists
-    uint32_t* cmem[3];     // per-cell members (cellcap slots per cell)
+    float4* cpos[3];       // per-cell members: position + (index | type << 24) bits, cellcap slots per cell
     int32_t* prop;         // proposed partner index (-1 none)
     unsigned long long* key;        // matching priority of each proposal
     unsigned long long* best[3];    // per-site minimum key of live incident proposals (3 rotating)
@@ -160,9 +172,26 @@ struct Dev {
     unsigned long long* red;        // reduction scratch (observables)
     uint32_t* scan;        // scan scratch (bond read-out)
     uint32_t* parent;      // union-find parents (cluster observable)
+    // spatial reordering (counting sort by cell): new index of every particle,
+    // cell offsets, and second copies of every per-particle array
+    uint32_t* newidx;
+    uint32_t* cstart;      // ncell + 1
+    uint32_t* cbsum;       // block sums of the cell-offset scan
+    float4* x_alt;
+    float4* u_alt;
+    int32_t* img_alt;
+    uint32_t* tag_alt;
+    uint8_t* occ_alt;
+    uint32_t* mol_alt;
+    uint32_t* dyn_alt;
+    uint32_t* stat_alt;
 };
 
 __device__ __forceinline__ uint32_t type_of(const float4& p) { return __float_as_uint(p.w); }
+
+// Cell-slot word: particle index in the low 24 bits, type in the high 8.
+__device__ __forceinline__ uint32_t slot_index(const float4& q) { return __float_as_uint(q.w) & kIdxMask; }
+__device__ __forceinline__ uint32_t slot_type(const float4& q) { return __float_as_uint(q.w) >> 24; }
 
 __device__ __forceinline__ int cell_coord(float x, const Params& P) {
     int c = (int)floorf((x + P.halfLf) * P.cell_scale);
@@ -172,8 +201,40 @@ __device__ __forceinline__ int cell_coord(float x, const Params& P) {
 
 __device__ __forceinline__ int wrapc(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
 
-__device__ __forceinline__ long long to_fix(float f) {
-    return (long long)rint((double)f * 4294967296.0);
+// Round v * 2^32 to the nearest integer (ties to even) with one FMA: adding
+// 1.5 * 2^52 leaves round(v * 2^32) in the low mantissa bits.  Exact for
+// |v| < 2^19; larger contributions are clamped and flagged.
+__device__ __forceinline__ long long to_fix(double v, uint32_t* err) {
+    constexpr double kMagic = 6755399441055744.0;   // 1.5 * 2^52
+    if (!(fabs(v) < 524288.0)) {
+        atomicOr(err, kErrForce);
+        v = v > 0.0 ? 524287.0 : -524287.0;
+    }
+    return __double_as_longlong(fma(v, 4294967296.0, kMagic)) - __double_as_longlong(kMagic);
+}
+
+// 1/x and 1/sqrt(x) in FP64 from the hardware estimates plus two Newton
+// steps (relative error ~1e-16; used for forces only, never for decisions).
+__device__ __forceinline__ double rcp64(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ double rsqrt64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
+
+// FP32 minimum-image component, used only to discard far candidates before
+// the exact FP64 evaluation (its error, ~1e-5, is far below the margins).
+__device__ __forceinline__ float mi_delta_f(float xi, float xj, const Params& P) {
+    float d = xj - xi;
+    d -= P.Lf * rintf(d * (1.0f / P.Lf));
+    return d;
 }
 
 // Wave-aggregated atomic add of a per-lane count to a 64-bit counter.

@@ -23,7 +23,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMatchRounds = 3;        // full-grid matching rounds before the one-workgroup finish
-constexpr uint32_t kCellCap = 16;      // particle slots per cell
+constexpr uint32_t kCellCapMin = 16;   // minimum particle slots per cell
 thread_local std::string g_create_error;
 
 struct TypeCfg { uint32_t valence = 0; double sigma = 1.0, eps = 1.0, mass = 1.0; };
@@ -70,9 +70,13 @@ struct db_system {
     uint64_t step = 0;
     int cur_x = 0, cur_list = 0;
     std::vector<uint32_t> tag_h, rtag_h;   // host mirrors of tag / rtag
+    std::vector<PairTab> pair_h;           // WCA table uploaded to D.pair
     Timing timing;
     std::map<int, hipGraphExec_t> graphs;  // keyed by (cur_x, cur_list)
     bool use_graphs = true;
+    uint32_t cellcap_user = 0;             // 0 = automatic
+    bool tags_dirty = false;               // device tag/rtag changed since the host mirrors were read
+    bool sort_enabled = true;              // renumber particles in cell order every graph span
 };
 
 namespace {
@@ -274,6 +278,48 @@ db_status dalloc(db_system* s, T** p, size_t count) {
         if (st_ != DB_OK) return st_;                 \
     } while (0)
 
+// Slots per cell: room for a Poisson fluctuation far above the mean occupancy
+// and at least twice the fullest cell of the state being uploaded.
+uint32_t cell_capacity(const db_system* s, const Params& P, const float* pos3 = nullptr) {
+    if (s->cellcap_user) return s->cellcap_user;
+    const double lam = (double)s->n / (double)P.ncell;
+    double cap = lam + 8.0 * std::sqrt(lam) + 8.0;
+    const float* x = pos3 ? pos3 : s->pos.data();
+    if (x) {
+        std::vector<uint32_t> occ(P.ncell, 0);
+        uint32_t mx = 0;
+        auto cc = [&](float v) {
+            int c = (int)std::floor((v + P.halfLf) * P.cell_scale);
+            return std::min(std::max(c, 0), (int)P.nc - 1);
+        };
+        for (uint32_t i = 0; i < s->n; ++i) {
+            const size_t c = ((size_t)cc(x[3 * i + 2]) * P.nc + cc(x[3 * i + 1])) * P.nc + cc(x[3 * i]);
+            mx = std::max(mx, ++occ[c]);
+        }
+        cap = std::max(cap, 2.0 * mx);
+    }
+    uint32_t c = std::max<uint32_t>(kCellCapMin, (uint32_t)std::ceil(cap));
+    return (c + 7u) & ~7u;
+}
+
+// Cells per k_step tile: about 96 particles in the tile core at the mean
+// density, shrunk until there are at least 512 tiles (enough workgroups to
+// cover the chip) or the tile is 2 cells wide; t <= 6 so (t + 2)^3 <= kTileMaxHalo.
+void choose_tiles(const db_system* s, Params& P) {
+    const double lam = std::max((double)s->n / (double)P.ncell, 1e-6);
+    int t = (int)std::lround(std::cbrt(96.0 / lam));
+    t = std::max(1, std::min({t, 6, (int)P.nc}));
+    auto ntiles = [&](int tt) {
+        const long k = ((long)P.nc + tt - 1) / tt;
+        return k * k * k;
+    };
+    while (t > 2 && ntiles(t) < 512) --t;
+    for (int d = 0; d < 3; ++d) {
+        P.tile[d] = (uint32_t)t;
+        P.ntile[d] = (P.nc + (uint32_t)t - 1) / (uint32_t)t;
+    }
+}
+
 void fill_params(db_system* s) {
     Params& P = s->P;
     P = Params{};
@@ -301,23 +347,26 @@ void fill_params(db_system* s) {
     }
     P.cap_max = std::max(capmax, 1u);
     double rc = 0.0, rmax_all = 0.0;
+    s->pair_h.assign(kMaxTypes * kMaxTypes, PairTab{0.0, 0.0, 0.0, -1.0, -1.0, 0.0, 0.0, 0.0});
     for (uint32_t a = 0; a < s->ntypes; ++a)
         for (uint32_t b = 0; b < s->ntypes; ++b) {
             const double sig = 0.5 * (s->types[a].sigma + s->types[b].sigma);
             const double eps = std::sqrt(s->types[a].eps * s->types[b].eps);
             const int k = a * kMaxTypes + b;
             if (sig > 0.0 && eps > 0.0) {
-                P.sig2[k] = (float)(sig * sig);
-                P.eps4[k] = (float)(4.0 * eps);
-                P.rc2[k] = (float)(wca_cut(sig) * wca_cut(sig));
-                rc = std::max(rc, wca_cut(sig));
+                const double c = wca_cut(sig);
+                s->pair_h[k] = PairTab{sig * sig, 24.0 * eps, c, c * c * (1.0 - 1e-14), c * c * (1.0 + 1e-14),
+                                       eps, 0.0, 0.0};
+                P.rc2_pre[k] = (float)(c * c * (1.0 + 1e-3) + 1e-4);
+                rc = std::max(rc, c);
             }
         }
     for (size_t b = 0; b < s->bonds.size(); ++b) {
         P.bkind[b] = (uint32_t)s->bonds[b].kind;
-        P.bk[b] = (float)s->bonds[b].k;
-        P.br0[b] = (float)s->bonds[b].r0;
-        P.bR02[b] = (float)(s->bonds[b].r0 * s->bonds[b].r0);
+        P.bk[b] = s->bonds[b].k;
+        P.br0[b] = s->bonds[b].r0;
+        P.bR02[b] = s->bonds[b].r0 * s->bonds[b].r0;
+        P.binvR02[b] = P.bR02[b] > 0.0 ? 1.0 / P.bR02[b] : 0.0;
     }
     for (size_t a = 0; a < s->rx.size(); ++a) {
         const auto& d = s->rx[a];
@@ -332,13 +381,16 @@ void fill_params(db_system* s) {
         P.hk[a] = 0.5 * s->bonds[d.bond_type].k;
         P.pon[a] = s->res[a].p_on;
         P.poff[a] = s->res[a].p_off;
+        P.rmax2_pre[a] = (float)(d.r_max * d.r_max * (1.0 + 1e-3) + 1e-4);
+        P.rmin2_pre[a] = (float)std::max(0.0, d.r_min * d.r_min * (1.0 - 1e-3) - 1e-4);
         rmax_all = std::max(rmax_all, d.r_max);
     }
     const double rsearch = std::max(rc, rmax_all);
     P.nc = (uint32_t)std::floor(s->L / (rsearch * (1.0 + 1e-5)));
     P.ncell = P.nc * P.nc * P.nc;
-    P.cellcap = kCellCap;
     P.cell_scale = (float)((double)P.nc / s->L);
+    P.cellcap = cell_capacity(s, P);
+    choose_tiles(s, P);
     uint32_t smax = 0;
     std::vector<uint32_t> deg(s->n, 0);
     for (size_t k = 0; k < s->stat_bt.size(); ++k) {
@@ -353,6 +405,12 @@ void fill_params(db_system* s) {
 db_status upload_state(db_system* s, const float* pos3, const float* vel3, const uint32_t* pairs,
                        const uint32_t* bts, uint64_t m) {
     const uint32_t n = s->n;
+    if (s->tags_dirty) {
+        HIPCHK(s, hipMemcpyAsync(s->tag_h.data(), s->D.tag, n * 4, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(s, hipMemcpyAsync(s->rtag_h.data(), s->D.rtag, n * 4, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        s->tags_dirty = false;
+    }
     const Params& P = s->P;
     std::vector<float4> xs(n), vs(n);
     for (uint32_t i = 0; i < n; ++i) {
@@ -404,10 +462,32 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
     HIPCHK(s, hipStreamSynchronize(s->stream));
     uint32_t err[4];
     HIPCHK(s, hipMemcpy(err, s->D.err, sizeof err, hipMemcpyDeviceToHost));
-    if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", kCellCap); }
+    if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", s->P.cellcap); }
     if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "FENE bond %u-%u overstretched", err[1], err[2]); }
     if (err[0] & kErrForce) { s->invalid = true; return fail(s, DB_EBOND, "force out of range"); }
     s->invalid = false;
+    return DB_OK;
+}
+
+void destroy_graphs(db_system* s) {
+    for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
+    s->graphs.clear();
+}
+
+// Grow the per-cell member arrays when a new state needs more slots per cell.
+db_status ensure_cell_capacity(db_system* s, const float* pos3) {
+    const uint32_t need = cell_capacity(s, s->P, pos3);
+    if (need <= s->P.cellcap) return DB_OK;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (int l = 0; l < 3; ++l) {
+        auto it = std::find(s->allocs.begin(), s->allocs.end(), (void*)s->D.cpos[l]);
+        if (it != s->allocs.end()) s->allocs.erase(it);
+        HIPCHK(s, hipFree(s->D.cpos[l]));
+        s->D.cpos[l] = nullptr;
+        DALLOC(s, s->D.cpos[l], (size_t)s->P.ncell * need);
+    }
+    s->P.cellcap = need;
+    destroy_graphs(s);
     return DB_OK;
 }
 
@@ -417,7 +497,7 @@ db_status check_errors(db_system* s) {
     flush_timing(s);
     uint32_t err[4];
     HIPCHK(s, hipMemcpy(err, s->D.err, sizeof err, hipMemcpyDeviceToHost));
-    if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", kCellCap); }
+    if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", s->P.cellcap); }
     if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "FENE bond %u-%u reached r >= R0", err[1], err[2]); }
     if (err[0] & kErrForce) { s->invalid = true; return fail(s, DB_EBOND, "force out of the representable range"); }
     return DB_OK;
@@ -439,6 +519,22 @@ void launch_sweep(db_system* s, int xcur, int lst, int sp) {
     }
 }
 
+// Renumber particles in cell order (counting sort over the current cell list),
+// then rebuild that cell list with the new numbers.
+void launch_sort(db_system* s) {
+    const Params& P = s->P;
+    const unsigned gc = grid_of(P.ncell), g = grid_of(P.n);
+    const int xc = s->cur_x, lc = s->cur_list;
+    LAUNCH(s, k_cell_scan_blocks, gc, kBlock, P, s->D, lc);
+    LAUNCH(s, k_scan_bsum, 1, 1024, s->D.cbsum, gc);
+    LAUNCH(s, k_sort_assign, gc, kBlock, P, s->D, lc);
+    LAUNCH(s, k_sort_scatter, g, kBlock, P, s->D, xc);
+    LAUNCH(s, k_sort_copyback, g, kBlock, P, s->D, xc);
+    LAUNCH(s, k_clear_counts, std::min(gc, 65535u), kBlock, P, s->D, lc);
+    LAUNCH(s, k_bin, g, kBlock, P, s->D, xc, lc);
+    s->tags_dirty = true;
+}
+
 // One time step t -> t+1 (plus the sweep when (t+1) % period == 0).
 void launch_step(db_system* s) {
     const Params& P = s->P;
@@ -447,17 +543,12 @@ void launch_step(db_system* s) {
     const int lnext = (lcur + 1) % 3, lclr = (lcur + 2) % 3;
     const int sp = (int)(t & 1);
     const bool sweep = P.nrx > 0 && ((t + 1) % P.period == 0);
-    LAUNCH(s, k_step, grid_of(P.n), kBlock, P, s->D, xin, lcur, lnext, lclr, sp,
-           (sweep && P.kt_kinetic) ? 1 : 0);
+    LAUNCH(s, k_step, P.ntile[0] * P.ntile[1] * P.ntile[2], kTileThreads, P, s->D, xin, lcur, lnext, lclr,
+           sp, (sweep && P.kt_kinetic) ? 1 : 0);
     s->cur_x ^= 1;
     s->cur_list = lnext;
     s->step = t + 1;
     if (sweep) launch_sweep(s, s->cur_x, s->cur_list, (int)((t + 1) & 1));
-}
-
-void destroy_graphs(db_system* s) {
-    for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
-    s->graphs.clear();
 }
 
 // Steps per graph: a whole number of sweep periods that also returns the
@@ -482,6 +573,7 @@ db_status run_steps(db_system* s, uint64_t nsteps) {
                 const int x0 = s->cur_x, l0 = s->cur_list;
                 hipGraph_t g;
                 HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+                if (s->sort_enabled) launch_sort(s);
                 for (uint64_t k = 0; k < span; ++k) launch_step(s);
                 HIPCHK(s, hipStreamEndCapture(s->stream, &g));
                 hipGraphExec_t ge;
@@ -493,9 +585,11 @@ db_status run_steps(db_system* s, uint64_t nsteps) {
                 it = s->graphs.emplace(key, ge).first;
             }
             HIPCHK(s, hipGraphLaunch(it->second, s->stream));
+            if (s->sort_enabled) s->tags_dirty = true;
             s->step += span;       // span is a multiple of 6: buffers return to (x0, l0)
             done += span;
         } else {
+            if (s->sort_enabled && s->timing.on && aligned && (s->step % span) == 0) launch_sort(s);
             launch_step(s);
             ++done;
         }
@@ -630,6 +724,14 @@ db_status db_set_integrator(db_system* s, double dt, double kT, double gamma, ui
     return DB_OK;
 }
 
+db_status db_set_cell_capacity(db_system* s, uint32_t slots) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "cell capacity is fixed after commit");
+    if (slots > 1024) return fail(s, DB_EINVAL, "cell capacity above 1024");
+    s->cellcap_user = slots;
+    return DB_OK;
+}
+
 db_status db_validate(db_system* s) {
     if (!s) return DB_EINVAL;
     return validate(s);
@@ -677,6 +779,13 @@ static db_status commit_impl(db_system* s) {
     HIPCHK(s, hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
     s->stream = s->own_stream;
     s->committed = true;   // from here on db_destroy frees device memory
+    {
+        PairTab* pt = nullptr;
+        DALLOC(s, pt, (size_t)kMaxTypes * kMaxTypes);
+        HIPCHK(s, hipMemcpyAsync(pt, s->pair_h.data(), s->pair_h.size() * sizeof(PairTab),
+                                 hipMemcpyHostToDevice, s->stream));
+        D.pair = pt;
+    }
     DALLOC(s, D.x[0], n);
     DALLOC(s, D.x[1], n);
     DALLOC(s, D.u, n);
@@ -689,7 +798,7 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.mol, n);
     for (int l = 0; l < 3; ++l) {
         DALLOC(s, D.ccount[l], P.ncell);
-        DALLOC(s, D.cmem[l], (size_t)P.ncell * P.cellcap);
+        DALLOC(s, D.cpos[l], (size_t)P.ncell * P.cellcap);
         DALLOC(s, D.best[l], n);
     }
     DALLOC(s, D.prop, n);
@@ -707,6 +816,17 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.scan, (size_t)n + 1);
     DALLOC(s, D.parent, n);
     DALLOC(s, s->bsum, grid_of(n) + 1);
+    DALLOC(s, D.newidx, n);
+    DALLOC(s, D.cstart, (size_t)P.ncell + 1);
+    DALLOC(s, D.cbsum, grid_of(P.ncell) + 1);
+    DALLOC(s, D.x_alt, n);
+    DALLOC(s, D.u_alt, n);
+    DALLOC(s, D.img_alt, 3 * (size_t)n);
+    DALLOC(s, D.tag_alt, n);
+    DALLOC(s, D.occ_alt, n);
+    DALLOC(s, D.mol_alt, n);
+    DALLOC(s, D.dyn_alt, (size_t)P.cap_max * n);
+    DALLOC(s, D.stat_alt, (size_t)std::max(P.stat_max, 1u) * n);
     DALLOC(s, s->stage, n);
     DALLOC(s, s->flag, 1);
     // static topology, molecule ids, tags
@@ -794,6 +914,8 @@ db_status db_set_state(db_system* s, uint64_t step, const float* pos3, const flo
     if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) return fail(s, DB_EINVAL, "duplicate dynamic bond");
     HIPCHK(s, hipSetDevice(s->device));
     HIPCHK(s, hipStreamSynchronize(s->stream));
+    db_status st = ensure_cell_capacity(s, pos3);
+    if (st != DB_OK) return st;
     s->step = step;
     return upload_state(s, pos3, vel3, pairs, bts, m);
 }

@@ -25,82 +25,77 @@ namespace dyb {
 // ------------------------------------------------------------ force kernel
 struct Force3 { float x, y, z; };
 
-// Bond force on site i from partner position pj (slot word w, bond type bt).
+// Bond force on site i from partner position pj (bond type bt), in FP64 from
+// the exact minimum-image separation.
 __device__ __forceinline__ void bond_force(const Params& P, const Dev& D, float4 pi, float4 pj,
                                            uint32_t bt, uint32_t i, uint32_t j,
                                            long long& fx, long long& fy, long long& fz,
                                            double* e) {
-    const float dx = (float)mi_delta(pi.x, pj.x, P.L, P.invL);
-    const float dy = (float)mi_delta(pi.y, pj.y, P.L, P.invL);
-    const float dz = (float)mi_delta(pi.z, pj.z, P.L, P.invL);
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    float f;
+    const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
+    const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
+    const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    double f;
     if (P.bkind[bt] == 1u) {                      // FENE: F_i = k / (1 - r^2/R0^2) d
-        const float g = 1.0f - r2 / P.bR02[bt];
-        if (!(g > 0.0f)) {
+        const double g = 1.0 - r2 * P.binvR02[bt];
+        if (!(g > 0.0)) {
             if (atomicOr(&D.err[0], kErrFene) == 0u) {
                 D.err[1] = D.tag[i];
                 D.err[2] = D.tag[j];
             }
             return;
         }
-        f = P.bk[bt] / g;
-        if (e) *e += 0.5 * (-0.5 * (double)P.bk[bt] * (double)P.bR02[bt] * log((double)g));
+        f = P.bk[bt] * rcp64(g);
+        if (e) *e += 0.5 * (-0.5 * P.bk[bt] * P.bR02[bt] * log(g));
     } else {                                      // harmonic: F_i = k (r - r0) / r d
-        const float r = sqrtf(r2);
-        const float dr = r - P.br0[bt];
-        f = r > 0.0f ? P.bk[bt] * dr / r : 0.0f;
-        if (e) *e += 0.5 * (0.5 * (double)P.bk[bt] * (double)dr * (double)dr);
+        if (!(r2 > 0.0)) return;
+        const double ir = rsqrt64(r2);
+        const double dr = r2 * ir - P.br0[bt];
+        f = P.bk[bt] * dr * ir;
+        if (e) *e += 0.5 * (0.5 * P.bk[bt] * dr * dr);
     }
-    fx += to_fix(f * dx);
-    fy += to_fix(f * dy);
-    fz += to_fix(f * dz);
+    fx += to_fix(f * dx, D.err);
+    fy += to_fix(f * dy, D.err);
+    fz += to_fix(f * dz, D.err);
 }
 
-// Total force on particle i at positions X with cell list `lst`; optional
-// per-particle energy (half of each pair and bond energy).
-__device__ __forceinline__ Force3 force_on(const Params& P, const Dev& D, const float4* __restrict__ X,
-                                           int lst, uint32_t i, float4 pi, uint32_t ti,
-                                           double* e) {
-    long long fx = 0, fy = 0, fz = 0;
-    const uint32_t* __restrict__ cnt = D.ccount[lst];
-    const uint32_t* __restrict__ mem = D.cmem[lst];
-    const int nc = (int)P.nc;
-    const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
-    const int prow = (int)ti * kMaxTypes;
-    for (int oz = -1; oz <= 1; ++oz) {
-        const int z = wrapc(cz + oz, nc);
-        for (int oy = -1; oy <= 1; ++oy) {
-            const int y = wrapc(cy + oy, nc);
-            const int rowbase = (z * nc + y) * nc;
-            for (int ox = -1; ox <= 1; ++ox) {
-                const int c = rowbase + wrapc(cx + ox, nc);
-                uint32_t m = cnt[c];
-                m = m < P.cellcap ? m : P.cellcap;
-                const uint32_t base = (uint32_t)c * P.cellcap;
-                for (uint32_t k = 0; k < m; ++k) {
-                    const uint32_t j = mem[base + k];
-                    if (j == i) continue;
-                    const float4 pj = X[j];
-                    const int pt = prow + (int)type_of(pj);
-                    const float dx = (float)mi_delta(pi.x, pj.x, P.L, P.invL);
-                    const float dy = (float)mi_delta(pi.y, pj.y, P.L, P.invL);
-                    const float dz = (float)mi_delta(pi.z, pj.z, P.L, P.invL);
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 < P.rc2[pt]) {
-                        // F_i = -24 eps (sigma/r)^6 (2 (sigma/r)^6 - 1) / r^2 * d
-                        const float sr2 = P.sig2[pt] / r2;
-                        const float sr6 = sr2 * sr2 * sr2;
-                        const float f = 6.0f * P.eps4[pt] * sr6 * (2.0f * sr6 - 1.0f) / r2;
-                        fx -= to_fix(f * dx);
-                        fy -= to_fix(f * dy);
-                        fz -= to_fix(f * dz);
-                        if (e) *e += 0.5 * ((double)P.eps4[pt] * ((double)sr6 * sr6 - sr6) + 0.25 * P.eps4[pt]);
-                    }
-                }
-            }
-        }
+// WCA force on pi from the cell-slot entry pj (position + index/type bits).
+// Screened in FP32 with a safety margin; pairs that survive are evaluated in
+// FP64.  The cutoff test r < 2^(1/6) sigma_ij is the oracle's: away from the
+// cutoff it is decided on r^2, within 1e-14 of it on the correctly rounded r.
+__device__ __forceinline__ void pair_force(const Params& P, const Dev& D, float4 pi, float4 pj, uint32_t ti,
+                                           long long& fx, long long& fy, long long& fz, double* e) {
+    const int pt = (int)ti * kMaxTypes + (int)slot_type(pj);
+    const float fdx = mi_delta_f(pi.x, pj.x, P);
+    const float fdy = mi_delta_f(pi.y, pj.y, P);
+    const float fdz = mi_delta_f(pi.z, pj.z, P);
+    if (fdx * fdx + fdy * fdy + fdz * fdz >= P.rc2_pre[pt]) return;
+    const PairTab& pp = D.pair[pt];
+    const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
+    const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
+    const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
+    double r2;
+    {
+#pragma clang fp contract(off)
+        r2 = (dx * dx + dy * dy) + dz * dz;
     }
+    if (r2 >= pp.rc2_hi) return;
+    if (r2 > pp.rc2_lo && !(sqrt(r2) < pp.rc)) return;
+    // F_i = -24 eps (sigma/r)^6 (2 (sigma/r)^6 - 1) / r^2 * d
+    const double ir2 = rcp64(r2);
+    const double sr2 = pp.sig2 * ir2;
+    const double sr6 = sr2 * sr2 * sr2;
+    const double f = pp.eps24 * sr6 * (2.0 * sr6 - 1.0) * ir2;
+    fx -= to_fix(f * dx, D.err);
+    fy -= to_fix(f * dy, D.err);
+    fz -= to_fix(f * dz, D.err);
+    if (e) *e += 0.5 * (4.0 * pp.eps * (sr6 * sr6 - sr6) + pp.eps);
+}
+
+// Static and dynamic bond forces on particle i.
+__device__ __forceinline__ void bond_forces(const Params& P, const Dev& D, const float4* __restrict__ X,
+                                            uint32_t i, float4 pi, uint32_t ti,
+                                            long long& fx, long long& fy, long long& fz, double* e) {
     for (uint32_t s = 0; s < P.stat_max; ++s) {
         const uint32_t w = D.stat[(size_t)s * P.n + i];
         if (w == kEmpty) break;
@@ -114,18 +109,54 @@ __device__ __forceinline__ Force3 force_on(const Params& P, const Dev& D, const 
         const uint32_t j = w & kIdxMask;
         bond_force(P, D, pi, X[j], P.rbt[(w >> 24) & 0x7Fu], i, j, fx, fy, fz, e);
     }
-    const long long lim = 1ll << 61;
-    if (fx > lim || fx < -lim || fy > lim || fy < -lim || fz > lim || fz < -lim)
-        atomicOr(&D.err[0], kErrForce);
+}
+
+__device__ __forceinline__ Force3 fix_to_force(const Dev& D, long long fx, long long fy, long long fz) {
     return Force3{(float)((double)fx * kFixInv), (float)((double)fy * kFixInv),
                   (float)((double)fz * kFixInv)};
+}
+
+// Total force on particle i at positions X with cell list `lst`; optional
+// per-particle energy (half of each pair and bond energy).  Candidates are
+// screened in FP32 with a safety margin; pairs that survive are evaluated in
+// FP64 with the same cutoff test as the oracle (r < 2^(1/6) sigma_ij).  Each
+// contribution is rounded to 2^-32 and summed in 64-bit integers.
+__device__ __forceinline__ Force3 force_on(const Params& P, const Dev& D, const float4* __restrict__ X,
+                                           int lst, uint32_t i, float4 pi, uint32_t ti,
+                                           double* e) {
+    long long fx = 0, fy = 0, fz = 0;
+    const uint32_t* __restrict__ cnt = D.ccount[lst];
+    const float4* __restrict__ cp = D.cpos[lst];
+    const int nc = (int)P.nc;
+    const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
+    for (int oz = -1; oz <= 1; ++oz) {
+        const int z = wrapc(cz + oz, nc);
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int y = wrapc(cy + oy, nc);
+            const int rowbase = (z * nc + y) * nc;
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int c = rowbase + wrapc(cx + ox, nc);
+                uint32_t m = cnt[c];
+                m = m < P.cellcap ? m : P.cellcap;
+                const uint32_t base = (uint32_t)c * P.cellcap;
+                for (uint32_t k = 0; k < m; ++k) {
+                    const float4 pj = cp[base + k];
+                    if (slot_index(pj) == i) continue;
+                    pair_force(P, D, pi, pj, ti, fx, fy, fz, e);
+                }
+            }
+        }
+    }
+    bond_forces(P, D, X, i, pi, ti, fx, fy, fz, e);
+    return fix_to_force(D, fx, fy, fz);
 }
 
 // Insert particle i (position p) into cell list `lst`.
 __device__ __forceinline__ void bin_particle(const Params& P, const Dev& D, int lst, uint32_t i, float4 p) {
     const int c = (cell_coord(p.z, P) * (int)P.nc + cell_coord(p.y, P)) * (int)P.nc + cell_coord(p.x, P);
     const uint32_t slot = atomicAdd(&D.ccount[lst][c], 1u);
-    if (slot < P.cellcap) D.cmem[lst][(size_t)c * P.cellcap + slot] = i;
+    if (slot < P.cellcap)
+        D.cpos[lst][(size_t)c * P.cellcap + slot] = make_float4(p.x, p.y, p.z, __uint_as_float(i | (type_of(p) << 24)));
     else atomicOr(&D.err[0], kErrOverflow);
 }
 
@@ -192,74 +223,275 @@ __global__ __launch_bounds__(256) void k_ke_accum(const Params P, const Dev D, i
     if (__lane_id() == 0 && ke) atomicAdd(D.ke_fix, ke);
 }
 
-// One BAOAB step t -> s = t + 1 for every particle.
-//   xin/xout = position buffers, lcur = cell list of x_t, lnext = list that
-//   receives x_s, lclr = list cleared for the step after, sp = slot holding t.
-__global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int xin, int lcur,
-                                              int lnext, int lclr, int sp, int accum_ke) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const unsigned long long t = D.stepv[sp];
-    const unsigned long long s = t + 1ull;
-    if (i == 0) D.stepv[sp ^ 1] = s;
-    for (uint32_t c = i; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
-    unsigned long long ke = 0ull;
-    if (i < P.n) {
-        const float4* __restrict__ X = D.x[xin];
-        const float4 pi = X[i];
-        const uint32_t ti = type_of(pi);
-        const Force3 F = force_on(P, D, X, lcur, i, pi, ti, nullptr);
-        const float4 u = D.u[i];
-        const float hm = P.h * P.inv_mass[ti];
-        // closing half kick of step t-1 (B), then the opening half kick of step t (B)
-        float vx = u.x + hm * F.x, vy = u.y + hm * F.y, vz = u.z + hm * F.z;
-        vx += hm * F.x;
-        vy += hm * F.y;
-        vz += hm * F.z;
-        float x = pi.x + P.h * vx, y = pi.y + P.h * vy, z = pi.z + P.h * vz;          // A
-        const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), D.tag[i], 0u, P.seed,
-                               stream_k1(kThermo, 0, 0));
-        // Box-Muller: u1 in (0, 1], u2 in [0, 1)
-        const float u1a = ((float)w.w0 + 1.0f) * 0x1.0p-32f;
-        const float u1b = ((float)w.w2 + 1.0f) * 0x1.0p-32f;
-        const float ra = sqrtf(-2.0f * logf(u1a));
-        const float rb = sqrtf(-2.0f * logf(u1b));
-        float sa, ca, sb, cb;
-        sincospif(2.0f * ((float)w.w1 * 0x1.0p-32f), &sa, &ca);
-        sincospif(2.0f * ((float)w.w3 * 0x1.0p-32f), &sb, &cb);
-        const float sd = P.noise_sd[ti];
-        vx = P.c1 * vx + sd * (ra * ca);                                              // O
-        vy = P.c1 * vy + sd * (ra * sa);
-        vz = P.c1 * vz + sd * (rb * cb);
-        x += P.h * vx;                                                                // A
-        y += P.h * vy;
-        z += P.h * vz;
-        int ix = 0, iy = 0, iz = 0;
-        if (x < -P.halfLf) { x += P.Lf; --ix; }
-        if (x >= P.halfLf) { x -= P.Lf; ++ix; }
-        if (y < -P.halfLf) { y += P.Lf; --iy; }
-        if (y >= P.halfLf) { y -= P.Lf; ++iy; }
-        if (z < -P.halfLf) { z += P.Lf; --iz; }
-        if (z >= P.halfLf) { z -= P.Lf; ++iz; }
-        if (ix | iy | iz) {
-            D.img[i] += ix;
-            D.img[P.n + i] += iy;
-            D.img[2 * P.n + i] += iz;
+// Block-wide exclusive scan (blockDim a multiple of 64, at most 1024).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t lane = __lane_id(), wid = threadIdx.x / 64;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= (uint32_t)off) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    const uint32_t nw = blockDim.x / 64;
+    for (uint32_t w = 0; w < nw; ++w) {
+        if (w < wid) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+// Rest of one BAOAB step for particle i once its force F at x_t is known:
+// closing half kick of step t-1 (B), opening half kick (B), half drift (A),
+// Ornstein-Uhlenbeck velocity update with Philox Gaussians (O), half drift
+// (A), wrap into [-L/2, L/2), then write x_{t+1} and bin it into `lnext`.
+// Returns m v^2 in 2^-32 fixed point when accum_ke is set.
+__device__ __forceinline__ unsigned long long advance_particle(const Params& P, const Dev& D, int xin, int lnext,
+                                                               uint32_t i, float4 pi, uint32_t ti, Force3 F,
+                                                               unsigned long long s, int accum_ke) {
+    const float4 u = D.u[i];
+    const float hm = P.h * P.inv_mass[ti];
+    float vx = u.x + hm * F.x, vy = u.y + hm * F.y, vz = u.z + hm * F.z;
+    vx += hm * F.x;
+    vy += hm * F.y;
+    vz += hm * F.z;
+    float x = pi.x + P.h * vx, y = pi.y + P.h * vy, z = pi.z + P.h * vz;
+    const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), D.tag[i], 0u, P.seed, stream_k1(kThermo, 0, 0));
+    // Box-Muller: u1 in (0, 1], u2 in [0, 1)
+    const float u1a = ((float)w.w0 + 1.0f) * 0x1.0p-32f;
+    const float u1b = ((float)w.w2 + 1.0f) * 0x1.0p-32f;
+    const float ra = sqrtf(-2.0f * __logf(u1a));
+    const float rb = sqrtf(-2.0f * __logf(u1b));
+    const float ta = 6.28318530717958647692f * ((float)w.w1 * 0x1.0p-32f);
+    const float sa = __sinf(ta), ca = __cosf(ta);
+    const float cb = __cosf(6.28318530717958647692f * ((float)w.w3 * 0x1.0p-32f));
+    const float sd = P.noise_sd[ti];
+    vx = P.c1 * vx + sd * (ra * ca);
+    vy = P.c1 * vy + sd * (ra * sa);
+    vz = P.c1 * vz + sd * (rb * cb);
+    x += P.h * vx;
+    y += P.h * vy;
+    z += P.h * vz;
+    int ix = 0, iy = 0, iz = 0;
+    if (x < -P.halfLf) { x += P.Lf; --ix; }
+    if (x >= P.halfLf) { x -= P.Lf; ++ix; }
+    if (y < -P.halfLf) { y += P.Lf; --iy; }
+    if (y >= P.halfLf) { y -= P.Lf; ++iy; }
+    if (z < -P.halfLf) { z += P.Lf; --iz; }
+    if (z >= P.halfLf) { z -= P.Lf; ++iz; }
+    if (ix | iy | iz) {
+        D.img[i] += ix;
+        D.img[P.n + i] += iy;
+        D.img[2 * P.n + i] += iz;
+    }
+    const float4 po = make_float4(x, y, z, __uint_as_float(ti));
+    D.x[xin ^ 1][i] = po;
+    D.u[i] = make_float4(vx, vy, vz, 0.0f);
+    bin_particle(P, D, lnext, i, po);
+    if (!accum_ke) return 0ull;
+    const double v2 = ((double)vx * vx + (double)vy * vy) + (double)vz * vz;
+    return (unsigned long long)rint((double)P.mass[ti] * v2 * 4294967296.0);
+}
+
+constexpr int kTileThreads = 128;
+constexpr int kTileMaxHalo = 512;       // halo cells of one tile, (t+2)^3 <= 512
+constexpr int kTileMaxEntries = 512;    // particles staged in LDS per tile
+
+// One BAOAB step t -> s = t + 1.  One workgroup per tile of cells: the cell
+// counts of the tile and its one-cell halo are scanned in LDS, the halo's
+// particles (position + index/type words of the cell list of x_t) are staged
+// in LDS with independent coalesced loads, and each thread then takes one
+// particle of the tile core and visits its 27 neighbour cells as 9 contiguous
+// LDS ranges.  Bonds and the integration read global memory by index.
+// Tiles whose halo holds more than kTileMaxEntries particles take the same
+// stencil straight from global memory.  Workgroups are dealt round-robin to
+// the 8 XCDs, so consecutive workgroup ids are remapped to give each XCD a
+// contiguous run of tiles (neighbouring tiles share halo cells in its L2).
+//   xin = buffer of x_t, lcur = cell list of x_t, lnext = list receiving
+//   x_{t+1}, lclr = list cleared for the step after, sp = slot holding t.
+__global__ __launch_bounds__(kTileThreads) void k_step(const Params P, const Dev D, int xin, int lcur,
+                                                       int lnext, int lclr, int sp, int accum_ke) {
+    __shared__ float4 ent[kTileMaxEntries];
+    __shared__ uint32_t hoff[kTileMaxHalo + 1];
+    __shared__ uint32_t core[kTileMaxEntries];
+    __shared__ uint32_t ncore;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t gtid = blockIdx.x * blockDim.x + tid;
+    const unsigned long long s = D.stepv[sp] + 1ull;
+    if (gtid == 0) D.stepv[sp ^ 1] = s;
+    for (uint32_t c = gtid; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
+
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t per = nb / 8u, rem = nb % 8u, xcd = b % 8u;
+    const uint32_t tile = xcd * per + (xcd < rem ? xcd : rem) + b / 8u;
+    const int nc = (int)P.nc;
+    const int bx = (int)(tile % P.ntile[0]), by = (int)((tile / P.ntile[0]) % P.ntile[1]);
+    const int bz = (int)(tile / (P.ntile[0] * P.ntile[1]));
+    const int x0 = bx * (int)P.tile[0], y0 = by * (int)P.tile[1], z0 = bz * (int)P.tile[2];
+    const int ex = min((int)P.tile[0], nc - x0), ey = min((int)P.tile[1], nc - y0), ez = min((int)P.tile[2], nc - z0);
+    const int hx = ex + 2, hy = ey + 2, hz = ez + 2, nh = hx * hy * hz;
+    auto hcell = [&](int h) {
+        const int ix = h % hx, iy = (h / hx) % hy, iz = h / (hx * hy);
+        return (wrapc(z0 - 1 + iz, nc) * nc + wrapc(y0 - 1 + iy, nc)) * nc + wrapc(x0 - 1 + ix, nc);
+    };
+    auto is_core = [&](int h) {
+        const int ix = h % hx, iy = (h / hx) % hy, iz = h / (hx * hy);
+        return ix >= 1 && ix <= ex && iy >= 1 && iy <= ey && iz >= 1 && iz <= ez;
+    };
+    const uint32_t* __restrict__ cnt = D.ccount[lcur];
+    const float4* __restrict__ cp = D.cpos[lcur];
+
+    // halo counts -> exclusive offsets (each thread scans a contiguous chunk)
+    const int chunk = (nh + kTileThreads - 1) / kTileThreads;     // <= 4
+    uint32_t loc[4];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int h = (int)tid * chunk + q;
+        uint32_t c = 0;
+        if (q < chunk && h < nh) {
+            c = cnt[hcell(h)];
+            c = c < P.cellcap ? c : P.cellcap;
         }
-        const float4 po = make_float4(x, y, z, pi.w);
-        D.x[xin ^ 1][i] = po;
-        D.u[i] = make_float4(vx, vy, vz, 0.0f);
-        bin_particle(P, D, lnext, i, po);
-        if (accum_ke) {
-            const double m = (double)P.mass[ti];
-            const double v2 = ((double)vx * vx + (double)vy * vy) + (double)vz * vz;
-            ke = (unsigned long long)rint(m * v2 * 4294967296.0);
+        loc[q] = c;
+        sum += c;
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, &total);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int h = (int)tid * chunk + q;
+        if (q < chunk && h < nh) hoff[h] = run;
+        run += loc[q];
+    }
+    if (tid == 0) {
+        hoff[nh] = total;
+        ncore = 0;
+    }
+    __syncthreads();
+    const bool staged = total <= (uint32_t)kTileMaxEntries;
+    unsigned long long ke = 0ull;
+    if (staged) {
+        for (int h = (int)tid; h < nh; h += kTileThreads) {
+            const uint32_t o = hoff[h], m = hoff[h + 1] - o;
+            const size_t base = (size_t)hcell(h) * P.cellcap;
+            for (uint32_t k = 0; k < m; ++k) ent[o + k] = cp[base + k];
+            if (m && is_core(h)) {
+                const uint32_t at = atomicAdd(&ncore, m);
+                for (uint32_t k = 0; k < m; ++k) core[at + k] = (o + k) | ((uint32_t)h << 16);
+            }
+        }
+        __syncthreads();
+        const float4* __restrict__ X = D.x[xin];
+        for (uint32_t q = tid; q < ncore; q += kTileThreads) {
+            const uint32_t e = core[q] & 0xFFFFu;
+            const int h = (int)(core[q] >> 16);
+            const float4 pi = ent[e];
+            const uint32_t i = slot_index(pi), ti = slot_type(pi);
+            const int ix = h % hx, iy = (h / hx) % hy, iz = h / (hx * hy);
+            long long fx = 0, fy = 0, fz = 0;
+            for (int oz = -1; oz <= 1; ++oz) {
+                for (int oy = -1; oy <= 1; ++oy) {
+                    const int hr = ((iz + oz) * hy + (iy + oy)) * hx + (ix - 1);
+                    const uint32_t lo = hoff[hr], hi = hoff[hr + 3];
+                    for (uint32_t e2 = lo; e2 < hi; ++e2) {
+                        if (e2 == e) continue;
+                        pair_force(P, D, pi, ent[e2], ti, fx, fy, fz, nullptr);
+                    }
+                }
+            }
+            bond_forces(P, D, X, i, pi, ti, fx, fy, fz, nullptr);
+            ke += advance_particle(P, D, xin, lnext, i, pi, ti, fix_to_force(D, fx, fy, fz), s, accum_ke);
+        }
+    } else {
+        const float4* __restrict__ X = D.x[xin];
+        for (int h = (int)tid; h < nh; h += kTileThreads) {
+            if (!is_core(h)) continue;
+            const uint32_t o = hoff[h], m = hoff[h + 1] - o;
+            const size_t base = (size_t)hcell(h) * P.cellcap;
+            for (uint32_t k = 0; k < m; ++k) {
+                const float4 pi = cp[base + k];
+                const uint32_t i = slot_index(pi), ti = slot_type(pi);
+                const Force3 F = force_on(P, D, X, lcur, i, pi, ti, nullptr);
+                ke += advance_particle(P, D, xin, lnext, i, pi, ti, F, s, accum_ke);
+            }
         }
     }
     if (accum_ke) {
-        unsigned long long sum = ke;
-        for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
-        if (__lane_id() == 0 && sum) atomicAdd(D.ke_fix, sum);
+        for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
+        if (__lane_id() == 0 && ke) atomicAdd(D.ke_fix, ke);
     }
+}
+
+// ------------------------------------------------------------ spatial sort
+// Particles are renumbered in cell order (cells in x-fastest order, slot order
+// inside a cell) so that the particles of a tile and their bond partners sit
+// close together in memory.  Nothing computed depends on the numbering: random
+// streams and tie-breaks use tags, sums are in fixed point.
+__global__ __launch_bounds__(256) void k_cell_scan_blocks(const Params P, const Dev D, int lst) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t m = 0;
+    if (c < P.ncell) {
+        m = D.ccount[lst][c];
+        m = m < P.cellcap ? m : P.cellcap;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(m, &tot);
+    if (c < P.ncell) D.cstart[c] = ex;
+    if (threadIdx.x == 0) D.cbsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_sort_assign(const Params P, const Dev D, int lst) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.ncell) return;
+    uint32_t m = D.ccount[lst][c];
+    m = m < P.cellcap ? m : P.cellcap;
+    const uint32_t base = D.cstart[c] + D.cbsum[blockIdx.x];
+    const float4* cp = D.cpos[lst] + (size_t)c * P.cellcap;
+    for (uint32_t k = 0; k < m; ++k) D.newidx[slot_index(cp[k])] = base + k;
+}
+
+__device__ __forceinline__ uint32_t remap_slot(const Dev& D, uint32_t w) {
+    return w == kEmpty ? kEmpty : (D.newidx[w & kIdxMask] | (w & ~kIdxMask));
+}
+
+__global__ __launch_bounds__(256) void k_sort_scatter(const Params P, const Dev D, int xin) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const uint32_t j = D.newidx[i];
+    const size_t n = P.n;
+    D.x_alt[j] = D.x[xin][i];
+    D.u_alt[j] = D.u[i];
+    D.img_alt[j] = D.img[i];
+    D.img_alt[n + j] = D.img[n + i];
+    D.img_alt[2 * n + j] = D.img[2 * n + i];
+    const uint32_t tg = D.tag[i];
+    D.tag_alt[j] = tg;
+    D.rtag[tg] = j;
+    D.occ_alt[j] = D.occ[i];
+    D.mol_alt[j] = D.mol[i];
+    for (uint32_t k = 0; k < P.cap_max; ++k) D.dyn_alt[k * n + j] = remap_slot(D, D.dyn[k * n + i]);
+    for (uint32_t k = 0; k < P.stat_max; ++k) D.stat_alt[k * n + j] = remap_slot(D, D.stat[k * n + i]);
+}
+
+__global__ __launch_bounds__(256) void k_sort_copyback(const Params P, const Dev D, int xin) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const size_t n = P.n;
+    D.x[xin][i] = D.x_alt[i];
+    D.u[i] = D.u_alt[i];
+    D.img[i] = D.img_alt[i];
+    D.img[n + i] = D.img_alt[n + i];
+    D.img[2 * n + i] = D.img_alt[2 * n + i];
+    D.tag[i] = D.tag_alt[i];
+    D.occ[i] = D.occ_alt[i];
+    D.mol[i] = D.mol_alt[i];
+    for (uint32_t k = 0; k < P.cap_max; ++k) D.dyn[k * n + i] = D.dyn_alt[k * n + i];
+    for (uint32_t k = 0; k < P.stat_max; ++k) D.stat[k * n + i] = D.stat_alt[k * n + i];
 }
 
 // ------------------------------------------------------------ sweep kernels
@@ -304,7 +536,7 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
     uint32_t best_tag = 0xFFFFFFFFu;
     int best_j = -1;
     const uint32_t* __restrict__ cnt = D.ccount[lst];
-    const uint32_t* __restrict__ mem = D.cmem[lst];
+    const float4* __restrict__ cp = D.cpos[lst];
     const int nc = (int)P.nc;
     const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
     for (int oz = -1; oz <= 1; ++oz) {
@@ -316,10 +548,10 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
                 uint32_t m = cnt[c];
                 m = m < P.cellcap ? m : P.cellcap;
                 for (uint32_t k = 0; k < m; ++k) {
-                    const uint32_t j = mem[(size_t)c * P.cellcap + k];
+                    const float4 pj = cp[(size_t)c * P.cellcap + k];
+                    const uint32_t j = slot_index(pj);
                     if (j == i) continue;
-                    const float4 pj = X[j];
-                    const uint32_t tj = type_of(pj);
+                    const uint32_t tj = slot_type(pj);
                     if (tj != want) continue;
                     if ((uint32_t)D.occ[j] >= P.cap[tj]) continue;
                     bool bonded = false;
@@ -327,6 +559,11 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
                     for (int q = 0; q < kMaxValence + kMaxStatic; ++q) bonded |= mine[q] == j;
                     if (bonded) continue;
                     if (avoid && D.mol[j] == mol_i) continue;
+                    const float fdx = mi_delta_f(pi.x, pj.x, P);
+                    const float fdy = mi_delta_f(pi.y, pj.y, P);
+                    const float fdz = mi_delta_f(pi.z, pj.z, P);
+                    const float fr2 = fdx * fdx + fdy * fdy + fdz * fdz;
+                    if (fr2 > P.rmax2_pre[a] || fr2 < P.rmin2_pre[a]) continue;
                     const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
                     const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
                     const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
@@ -663,27 +900,6 @@ __global__ void k_cc_max(const Params P, const Dev D) {
 // Bond read-out, in tag order.  Pass 1: per tag, the number of its dynamic
 // bonds to a higher tag, exclusive-scanned inside each block (wave shuffles),
 // block totals to `bsum`.  Pass 2 scans `bsum`; pass 3 writes the rows.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
-    __shared__ uint32_t wsum[16];
-    const uint32_t lane = __lane_id(), wid = threadIdx.x / 64;
-    uint32_t x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= (uint32_t)off) x += y;
-    }
-    if (lane == 63) wsum[wid] = x;
-    __syncthreads();
-    uint32_t base = 0, tot = 0;
-    const uint32_t nw = blockDim.x / 64;
-    for (uint32_t w = 0; w < nw; ++w) {
-        if (w < wid) base += wsum[w];
-        tot += wsum[w];
-    }
-    __syncthreads();
-    *total = tot;
-    return base + x - v;
-}
-
 __device__ __forceinline__ int rows_of(const Params& P, const Dev& D, int xin, uint32_t t, uint32_t* ptag,
                                        uint32_t* pbt) {
     const uint32_t i = D.rtag[t];

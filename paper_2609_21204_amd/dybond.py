@@ -65,6 +65,7 @@ _SIGS = {
     "db_add_static_bonds": (_I, [_P, _P, _P, _U64]),
     "db_add_reaction": (_I, [_P, ctypes.POINTER(ReactionDesc), ctypes.POINTER(_U32)]),
     "db_set_integrator": (_I, [_P, _D, _D, _D, _U32, _I]),
+    "db_set_cell_capacity": (_I, [_P, _U32]),
     "db_validate": (_I, [_P]),
     "db_get_reaction": (_I, [_P, _U32, ctypes.POINTER(ReactionDesc), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "db_commit": (_I, [_P]),
@@ -161,6 +162,10 @@ def db_add_reaction(h, desc):
 
 def db_set_integrator(h, dt, kT, gamma, sweep_period, kt_source=DB_KT_SETPOINT):
     _check(h, load().db_set_integrator(h, dt, kT, gamma, sweep_period, kt_source))
+
+
+def db_set_cell_capacity(h, slots):
+    _check(h, load().db_set_cell_capacity(h, slots))
 
 
 def db_validate(h):
