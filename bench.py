@@ -35,6 +35,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=20)
     p.add_argument("--profile-steps", type=int, default=2000)
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="first run one plain device-to-device copy of this many MiB (the reference "
+                        "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
     return p.parse_args()
 
 
@@ -110,6 +113,13 @@ def main():
     else:
         w = inputs.WORKLOADS[a.workload](seed=a.seed)
     tag = f"{w.name}{w.n // 1000}k"
+    if a.calibrate_copy:
+        src = torch.empty(a.calibrate_copy << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     s = db.System.from_workload(w, device=0)
     s.step(a.warmup)
     torch.cuda.synchronize()
@@ -121,9 +131,11 @@ def main():
 
     # per-kernel HIP-event timing on the library's stream (graph replay off)
     db.db_kernel_timing(s.h, 1)
-    s.step(a.profile_steps)
+    s.step(max(a.profile_steps, 1))
     kern = {}
-    for name in ("k_step", "k_propose", "k_claim", "k_kill", "k_finish", "k_break"):
+    for name in ("k_step", "k_nlist", "k_propose", "k_claim", "k_kill", "k_finish", "k_break",
+                 "k_cell_scan_blocks", "k_scan_bsum", "k_sort_assign", "k_sort_scatter", "k_sort_copyback",
+                 "k_clear_counts", "k_bin"):
         cnt, ms = db.db_read_kernel_time(s.h, name)
         if cnt:
             kern[name] = {"launches": cnt, "avg_us": 1000.0 * ms / cnt}

@@ -147,6 +147,17 @@ DB_API db_status db_set_integrator(db_system* sys, double dt, double kT, double 
  * fills up during a run makes db_step return DB_EOVERFLOW. */
 DB_API db_status db_set_cell_capacity(db_system* sys, uint32_t slots);
 
+/* Neighbour list used by the force and the bonding sweep: radius
+ * r_search + skin (r_search = max(WCA cutoff, r_max of every reaction)),
+ * rebuilt on the device whenever some particle has moved by more than
+ * skin / 2 since the last build, with at most max_neighbors entries per
+ * particle.  skin < 0 selects the default 0.4; max_neighbors == 0 selects
+ * max(64, 2.5 x the mean neighbour count at the system's density + 32);
+ * the skin shrinks automatically when the box holds fewer than 3 cells of
+ * side r_search + skin.  A particle with more neighbours makes db_step return
+ * DB_EOVERFLOW. */
+DB_API db_status db_set_neighbor_list(db_system* sys, double skin, uint32_t max_neighbors);
+
 /* Validate the configuration and close the rate parameters of every reaction
  * (Eq. epsilon, Eq. probs) without touching a GPU.  Errors: DB_EINVAL (bad
  * or missing parameter, under-determined or inconsistent rates, box smaller

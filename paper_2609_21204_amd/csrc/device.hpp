@@ -29,7 +29,7 @@ enum : uint32_t { kThermo = 1, kOrder = 2, kMatch = 3, kOn = 4, kOff = 5 };
 enum : uint8_t { kEdgeNone = 0, kEdgeLive = 1, kEdgeMatched = 2, kEdgeDead = 3 };
 
 // Device error flags (sticky until the host clears them).
-enum : uint32_t { kErrOverflow = 1u, kErrFene = 2u, kErrForce = 4u };
+enum : uint32_t { kErrOverflow = 1u, kErrFene = 2u, kErrForce = 4u, kErrNlist = 8u };
 
 // ---------------------------------------------------------------- Philox
 struct Word4 { uint32_t w0, w1, w2, w3; };
@@ -120,7 +120,9 @@ struct Params {
     double L, invL;
     float Lf, halfLf, cell_scale, h;   // h = dt / 2
     float c1;                          // exp(-gamma dt)
-    float pad0;
+    float rlist2;                      // (r_search + skin)^2 (1 + 1e-4): neighbour-list radius, FP32
+    float disp2;                       // (skin / 2 - 1e-4)^2: displacement that triggers a rebuild
+    uint32_t nlmax;                    // neighbour-list slots per particle
     double kT;
     float inv_mass[kMaxTypes];
     float noise_sd[kMaxTypes];         // sqrt(1 - c1^2) sqrt(kT / m)
@@ -172,6 +174,10 @@ struct Dev {
     unsigned long long* red;        // reduction scratch (observables)
     uint32_t* scan;        // scan scratch (bond read-out)
     uint32_t* parent;      // union-find parents (cluster observable)
+    uint32_t* nl;          // nlmax x n neighbour indices (slot-major)
+    uint32_t* nl_cnt;      // neighbours per particle
+    float4* xref;          // positions at the last neighbour-list build
+    uint32_t* rflag;       // two rebuild flags (parity of the step)
     // spatial reordering (counting sort by cell): new index of every particle,
     // cell offsets, and second copies of every per-particle array
     uint32_t* newidx;

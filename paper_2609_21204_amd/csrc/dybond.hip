@@ -75,6 +75,8 @@ struct db_system {
     std::map<int, hipGraphExec_t> graphs;  // keyed by (cur_x, cur_list)
     bool use_graphs = true;
     uint32_t cellcap_user = 0;             // 0 = automatic
+    double skin = 0.4;                     // neighbour-list skin
+    uint32_t nlmax_user = 0;               // neighbour-list slots per particle, 0 = automatic
     bool tags_dirty = false;               // device tag/rtag changed since the host mirrors were read
     bool sort_enabled = true;              // renumber particles in cell order every graph span
 };
@@ -103,6 +105,7 @@ db_status fail(db_system* s, db_status st, const char* fmt, ...) {
     } while (0)
 
 inline unsigned grid_of(uint32_t n) { return (n + kBlock - 1) / kBlock; }
+inline unsigned ntiles(const Params& P) { return P.ntile[0] * P.ntile[1] * P.ntile[2]; }
 
 struct TimerScope {
     db_system* s;
@@ -190,6 +193,13 @@ db_status close_rates(db_system* s, const db_reaction_desc& d, RxRes& out) {
 
 double wca_cut(double sig) { return std::pow(2.0, 1.0 / 6.0) * sig; }
 
+// The requested skin, shrunk so that the box still holds 3 cells of side
+// r_search + skin (negative when even skin 0 does not fit).
+double effective_skin(const db_system* s, double rsearch) {
+    const double room = s->L / (3.0 * (1.0 + 1e-5)) - rsearch;
+    return std::min(s->skin, room);
+}
+
 db_status validate(db_system* s) {
     s->validated = false;
     if (!s->have_particles) return fail(s, DB_ESTATE, "particles not set");
@@ -228,9 +238,9 @@ db_status validate(db_system* s) {
         }
     const double rsearch = std::max(rc, rmax_all);
     if (!(rsearch > 0.0)) return fail(s, DB_EINVAL, "no interaction range (all sigma 0 and no reaction)");
-    const double nc = std::floor(s->L / (rsearch * (1.0 + 1e-5)));
-    if (nc < 3.0)
+    if (effective_skin(s, rsearch) < 0.0)
         return fail(s, DB_EINVAL, "box L=%g holds fewer than 3 cells of side %g", s->L, rsearch);
+    const double nc = std::floor(s->L / ((rsearch + effective_skin(s, rsearch)) * (1.0 + 1e-5)));
     if (nc * nc * nc > 2.0e9) return fail(s, DB_EINVAL, "too many cells");
     // static bonds: per particle degree, FENE range
     std::vector<uint32_t> deg(s->n, 0);
@@ -386,7 +396,16 @@ void fill_params(db_system* s) {
         rmax_all = std::max(rmax_all, d.r_max);
     }
     const double rsearch = std::max(rc, rmax_all);
-    P.nc = (uint32_t)std::floor(s->L / (rsearch * (1.0 + 1e-5)));
+    const double skin = effective_skin(s, rsearch);
+    const double rlist = rsearch + skin;
+    P.rlist2 = (float)(rlist * rlist * (1.0 + 1e-4));
+    P.disp2 = (float)std::max(0.0, (0.5 * skin - 1e-4) * (0.5 * skin - 1e-4));
+    // neighbour slots: room for 2.5x the mean count of an ideal gas at this
+    // density plus 32, at least 64 (or exactly what the caller asked for)
+    const double mean_nb = 4.18879020478639 * rlist * rlist * rlist * (double)s->n / (s->L * s->L * s->L);
+    const uint32_t auto_nl = (std::max<uint32_t>(64u, (uint32_t)std::ceil(2.5 * mean_nb + 32.0)) + 7u) & ~7u;
+    P.nlmax = s->nlmax_user ? s->nlmax_user : auto_nl;
+    P.nc = (uint32_t)std::floor(s->L / (rlist * (1.0 + 1e-5)));
     P.ncell = P.nc * P.nc * P.nc;
     P.cell_scale = (float)((double)P.nc / s->L);
     P.cellcap = cell_capacity(s, P);
@@ -452,10 +471,12 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
     HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv, sizeof sv, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemsetAsync(s->D.err, 0, 4 * sizeof(uint32_t), s->stream));
     HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, sizeof(unsigned long long), s->stream));
+    HIPCHK(s, hipMemsetAsync(s->D.rflag, 0, 2 * sizeof(uint32_t), s->stream));
     s->cur_x = 0;
     s->cur_list = 0;
     for (int l = 0; l < 3; ++l) LAUNCH(s, k_clear_counts, std::min(grid_of(P.ncell), 65535u), kBlock, s->P, s->D, l);
     LAUNCH(s, k_bin, grid_of(n), kBlock, s->P, s->D, 0, 0);
+    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, s->P, s->D, 0, 0, (int)(s->step & 1), 1);
     LAUNCH(s, k_eval, grid_of(n), kBlock, s->P, s->D, 0, 0, 0u);
     LAUNCH(s, k_init_u, grid_of(n), kBlock, s->P, s->D, 0, 0u);
     HIPCHK(s, hipGetLastError());
@@ -465,6 +486,7 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
     if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", s->P.cellcap); }
     if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "FENE bond %u-%u overstretched", err[1], err[2]); }
     if (err[0] & kErrForce) { s->invalid = true; return fail(s, DB_EBOND, "force out of range"); }
+    if (err[0] & kErrNlist) { s->invalid = true; return fail(s, DB_EOVERFLOW, "more than %u neighbours of one particle", s->P.nlmax); }
     s->invalid = false;
     return DB_OK;
 }
@@ -500,6 +522,7 @@ db_status check_errors(db_system* s) {
     if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", s->P.cellcap); }
     if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "FENE bond %u-%u reached r >= R0", err[1], err[2]); }
     if (err[0] & kErrForce) { s->invalid = true; return fail(s, DB_EBOND, "force out of the representable range"); }
+    if (err[0] & kErrNlist) { s->invalid = true; return fail(s, DB_EOVERFLOW, "more than %u neighbours of one particle", s->P.nlmax); }
     return DB_OK;
 }
 
@@ -508,7 +531,7 @@ void launch_sweep(db_system* s, int xcur, int lst, int sp) {
     const Params& P = s->P;
     const unsigned g = grid_of(P.n);
     for (int slot = 0; slot < (int)P.nrx; ++slot) {
-        LAUNCH(s, k_propose, g, kBlock, P, s->D, slot, xcur, lst, sp);
+        LAUNCH(s, k_propose, g, kBlock, P, s->D, slot, xcur, sp);
         LAUNCH(s, k_claim, g, kBlock, P, s->D, slot, 1, xcur, sp);
         for (int q = 2; q <= kMatchRounds; ++q) {
             LAUNCH(s, k_kill, g, kBlock, P, s->D, q, q == kMatchRounds ? 1 : 0);
@@ -532,6 +555,7 @@ void launch_sort(db_system* s) {
     LAUNCH(s, k_sort_copyback, g, kBlock, P, s->D, xc);
     LAUNCH(s, k_clear_counts, std::min(gc, 65535u), kBlock, P, s->D, lc);
     LAUNCH(s, k_bin, g, kBlock, P, s->D, xc, lc);
+    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, xc, lc, (int)(s->step & 1), 1);
     s->tags_dirty = true;
 }
 
@@ -543,8 +567,8 @@ void launch_step(db_system* s) {
     const int lnext = (lcur + 1) % 3, lclr = (lcur + 2) % 3;
     const int sp = (int)(t & 1);
     const bool sweep = P.nrx > 0 && ((t + 1) % P.period == 0);
-    LAUNCH(s, k_step, P.ntile[0] * P.ntile[1] * P.ntile[2], kTileThreads, P, s->D, xin, lcur, lnext, lclr,
-           sp, (sweep && P.kt_kinetic) ? 1 : 0);
+    LAUNCH(s, k_step, grid_of(P.n), kBlock, P, s->D, xin, lnext, lclr, sp, (sweep && P.kt_kinetic) ? 1 : 0);
+    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, xin ^ 1, lnext, sp ^ 1, 0);
     s->cur_x ^= 1;
     s->cur_list = lnext;
     s->step = t + 1;
@@ -732,6 +756,16 @@ db_status db_set_cell_capacity(db_system* s, uint32_t slots) {
     return DB_OK;
 }
 
+db_status db_set_neighbor_list(db_system* s, double skin, uint32_t max_neighbors) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "neighbour list is fixed after commit");
+    if (!std::isfinite(skin) || skin > 100.0) return fail(s, DB_EINVAL, "skin out of range");
+    if (max_neighbors > 1024) return fail(s, DB_EINVAL, "max_neighbors above 1024");
+    s->skin = skin < 0.0 ? 0.4 : skin;
+    s->nlmax_user = max_neighbors;
+    return DB_OK;
+}
+
 db_status db_validate(db_system* s) {
     if (!s) return DB_EINVAL;
     return validate(s);
@@ -816,6 +850,10 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.scan, (size_t)n + 1);
     DALLOC(s, D.parent, n);
     DALLOC(s, s->bsum, grid_of(n) + 1);
+    DALLOC(s, D.nl, (size_t)P.nlmax * n);
+    DALLOC(s, D.nl_cnt, n);
+    DALLOC(s, D.xref, n);
+    DALLOC(s, D.rflag, 2);
     DALLOC(s, D.newidx, n);
     DALLOC(s, D.cstart, (size_t)P.ncell + 1);
     DALLOC(s, D.cbsum, grid_of(P.ncell) + 1);

@@ -92,6 +92,13 @@ __device__ __forceinline__ void pair_force(const Params& P, const Dev& D, float4
     if (e) *e += 0.5 * (4.0 * pp.eps * (sr6 * sr6 - sr6) + pp.eps);
 }
 
+// WCA force on pi from a position-array entry pj (type in the w bits).
+__device__ __forceinline__ void pair_force_xt(const Params& P, const Dev& D, float4 pi, float4 pj, uint32_t ti,
+                                              long long& fx, long long& fy, long long& fz, double* e) {
+    const float4 q = make_float4(pj.x, pj.y, pj.z, __uint_as_float(type_of(pj) << 24));
+    pair_force(P, D, pi, q, ti, fx, fy, fz, e);
+}
+
 // Static and dynamic bond forces on particle i.
 __device__ __forceinline__ void bond_forces(const Params& P, const Dev& D, const float4* __restrict__ X,
                                             uint32_t i, float4 pi, uint32_t ti,
@@ -252,7 +259,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
 // Returns m v^2 in 2^-32 fixed point when accum_ke is set.
 __device__ __forceinline__ unsigned long long advance_particle(const Params& P, const Dev& D, int xin, int lnext,
                                                                uint32_t i, float4 pi, uint32_t ti, Force3 F,
-                                                               unsigned long long s, int accum_ke) {
+                                                               unsigned long long s, int accum_ke, float4& po) {
     const float4 u = D.u[i];
     const float hm = P.h * P.inv_mass[ti];
     float vx = u.x + hm * F.x, vy = u.y + hm * F.y, vz = u.z + hm * F.z;
@@ -288,7 +295,7 @@ __device__ __forceinline__ unsigned long long advance_particle(const Params& P, 
         D.img[P.n + i] += iy;
         D.img[2 * P.n + i] += iz;
     }
-    const float4 po = make_float4(x, y, z, __uint_as_float(ti));
+    po = make_float4(x, y, z, __uint_as_float(ti));
     D.x[xin ^ 1][i] = po;
     D.u[i] = make_float4(vx, vy, vz, 0.0f);
     bin_particle(P, D, lnext, i, po);
@@ -301,30 +308,29 @@ constexpr int kTileThreads = 128;
 constexpr int kTileMaxHalo = 512;       // halo cells of one tile, (t+2)^3 <= 512
 constexpr int kTileMaxEntries = 512;    // particles staged in LDS per tile
 
-// One BAOAB step t -> s = t + 1.  One workgroup per tile of cells: the cell
-// counts of the tile and its one-cell halo are scanned in LDS, the halo's
-// particles (position + index/type words of the cell list of x_t) are staged
-// in LDS with independent coalesced loads, and each thread then takes one
+// Neighbour list: for every particle, the indices of all particles closer
+// than r_list = r_search + skin at the current positions (the list stays
+// complete for pairs within r_search until some particle has moved by
+// skin / 2).  Built from the cell list `lst` of those positions, one
+// workgroup per tile of cells: the cell counts of the tile and its one-cell
+// halo are scanned in LDS, the halo's particles (position + index/type words)
+// are staged in LDS with independent loads, and each thread takes one
 // particle of the tile core and visits its 27 neighbour cells as 9 contiguous
-// LDS ranges.  Bonds and the integration read global memory by index.
-// Tiles whose halo holds more than kTileMaxEntries particles take the same
-// stencil straight from global memory.  Workgroups are dealt round-robin to
-// the 8 XCDs, so consecutive workgroup ids are remapped to give each XCD a
-// contiguous run of tiles (neighbouring tiles share halo cells in its L2).
-//   xin = buffer of x_t, lcur = cell list of x_t, lnext = list receiving
-//   x_{t+1}, lclr = list cleared for the step after, sp = slot holding t.
-__global__ __launch_bounds__(kTileThreads) void k_step(const Params P, const Dev D, int xin, int lcur,
-                                                       int lnext, int lclr, int sp, int accum_ke) {
+// LDS ranges.  Tiles whose halo holds more than kTileMaxEntries particles
+// read the same stencil from global memory.  Workgroups are dealt round-robin
+// to the 8 XCDs; consecutive workgroup ids are remapped so that each XCD gets
+// a contiguous run of tiles (neighbouring tiles share halo cells in its L2).
+// The kernel does nothing unless the rebuild flag of this step's parity `fp`
+// is set (by k_step, when a particle has moved by more than skin / 2) or
+// `force` is given; it records the positions it was built at.
+__global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const Dev D, int xin, int lst, int fp,
+                                                        int force) {
+    if (!force && D.rflag[fp] == 0u) return;
     __shared__ float4 ent[kTileMaxEntries];
     __shared__ uint32_t hoff[kTileMaxHalo + 1];
     __shared__ uint32_t core[kTileMaxEntries];
     __shared__ uint32_t ncore;
     const uint32_t tid = threadIdx.x;
-    const uint32_t gtid = blockIdx.x * blockDim.x + tid;
-    const unsigned long long s = D.stepv[sp] + 1ull;
-    if (gtid == 0) D.stepv[sp ^ 1] = s;
-    for (uint32_t c = gtid; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
-
     const uint32_t nb = gridDim.x, b = blockIdx.x;
     const uint32_t per = nb / 8u, rem = nb % 8u, xcd = b % 8u;
     const uint32_t tile = xcd * per + (xcd < rem ? xcd : rem) + b / 8u;
@@ -342,8 +348,8 @@ __global__ __launch_bounds__(kTileThreads) void k_step(const Params P, const Dev
         const int ix = h % hx, iy = (h / hx) % hy, iz = h / (hx * hy);
         return ix >= 1 && ix <= ex && iy >= 1 && iy <= ey && iz >= 1 && iz <= ez;
     };
-    const uint32_t* __restrict__ cnt = D.ccount[lcur];
-    const float4* __restrict__ cp = D.cpos[lcur];
+    const uint32_t* __restrict__ cnt = D.ccount[lst];
+    const float4* __restrict__ cp = D.cpos[lst];
 
     // halo counts -> exclusive offsets (each thread scans a contiguous chunk)
     const int chunk = (nh + kTileThreads - 1) / kTileThreads;     // <= 4
@@ -373,9 +379,9 @@ __global__ __launch_bounds__(kTileThreads) void k_step(const Params P, const Dev
         ncore = 0;
     }
     __syncthreads();
-    const bool staged = total <= (uint32_t)kTileMaxEntries;
-    unsigned long long ke = 0ull;
-    if (staged) {
+    const size_t n = P.n;
+    bool over = false;
+    if (total <= (uint32_t)kTileMaxEntries) {
         for (int h = (int)tid; h < nh; h += kTileThreads) {
             const uint32_t o = hoff[h], m = hoff[h + 1] - o;
             const size_t base = (size_t)hcell(h) * P.cellcap;
@@ -386,40 +392,109 @@ __global__ __launch_bounds__(kTileThreads) void k_step(const Params P, const Dev
             }
         }
         __syncthreads();
-        const float4* __restrict__ X = D.x[xin];
         for (uint32_t q = tid; q < ncore; q += kTileThreads) {
             const uint32_t e = core[q] & 0xFFFFu;
             const int h = (int)(core[q] >> 16);
             const float4 pi = ent[e];
-            const uint32_t i = slot_index(pi), ti = slot_type(pi);
+            const uint32_t i = slot_index(pi);
             const int ix = h % hx, iy = (h / hx) % hy, iz = h / (hx * hy);
-            long long fx = 0, fy = 0, fz = 0;
+            uint32_t m = 0;
             for (int oz = -1; oz <= 1; ++oz) {
                 for (int oy = -1; oy <= 1; ++oy) {
                     const int hr = ((iz + oz) * hy + (iy + oy)) * hx + (ix - 1);
                     const uint32_t lo = hoff[hr], hi = hoff[hr + 3];
                     for (uint32_t e2 = lo; e2 < hi; ++e2) {
                         if (e2 == e) continue;
-                        pair_force(P, D, pi, ent[e2], ti, fx, fy, fz, nullptr);
+                        const float4 pj = ent[e2];
+                        const float dx = mi_delta_f(pi.x, pj.x, P), dy = mi_delta_f(pi.y, pj.y, P);
+                        const float dz = mi_delta_f(pi.z, pj.z, P);
+                        if (dx * dx + dy * dy + dz * dz < P.rlist2) {
+                            if (m < P.nlmax) D.nl[m * n + i] = slot_index(pj);
+                            ++m;
+                        }
                     }
                 }
             }
-            bond_forces(P, D, X, i, pi, ti, fx, fy, fz, nullptr);
-            ke += advance_particle(P, D, xin, lnext, i, pi, ti, fix_to_force(D, fx, fy, fz), s, accum_ke);
+            over |= m > P.nlmax;
+            D.nl_cnt[i] = m < P.nlmax ? m : P.nlmax;
+            D.xref[i] = pi;
         }
     } else {
-        const float4* __restrict__ X = D.x[xin];
         for (int h = (int)tid; h < nh; h += kTileThreads) {
             if (!is_core(h)) continue;
-            const uint32_t o = hoff[h], m = hoff[h + 1] - o;
+            const uint32_t o = hoff[h], m0 = hoff[h + 1] - o;
             const size_t base = (size_t)hcell(h) * P.cellcap;
-            for (uint32_t k = 0; k < m; ++k) {
+            for (uint32_t k = 0; k < m0; ++k) {
                 const float4 pi = cp[base + k];
-                const uint32_t i = slot_index(pi), ti = slot_type(pi);
-                const Force3 F = force_on(P, D, X, lcur, i, pi, ti, nullptr);
-                ke += advance_particle(P, D, xin, lnext, i, pi, ti, F, s, accum_ke);
+                const uint32_t i = slot_index(pi);
+                const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
+                uint32_t m = 0;
+                for (int oz = -1; oz <= 1; ++oz)
+                    for (int oy = -1; oy <= 1; ++oy)
+                        for (int ox = -1; ox <= 1; ++ox) {
+                            const int c = (wrapc(cz + oz, nc) * nc + wrapc(cy + oy, nc)) * nc + wrapc(cx + ox, nc);
+                            uint32_t mc = cnt[c];
+                            mc = mc < P.cellcap ? mc : P.cellcap;
+                            for (uint32_t kk = 0; kk < mc; ++kk) {
+                                const float4 pj = cp[(size_t)c * P.cellcap + kk];
+                                if (slot_index(pj) == i) continue;
+                                const float dx = mi_delta_f(pi.x, pj.x, P), dy = mi_delta_f(pi.y, pj.y, P);
+                                const float dz = mi_delta_f(pi.z, pj.z, P);
+                                if (dx * dx + dy * dy + dz * dz < P.rlist2) {
+                                    if (m < P.nlmax) D.nl[m * n + i] = slot_index(pj);
+                                    ++m;
+                                }
+                            }
+                        }
+                over |= m > P.nlmax;
+                D.nl_cnt[i] = m < P.nlmax ? m : P.nlmax;
+                D.xref[i] = pi;
             }
         }
+    }
+    if (over) atomicOr(&D.err[0], kErrNlist);
+}
+
+// One BAOAB step t -> s = t + 1 for every particle: WCA forces over the
+// neighbour list, bond forces, the integration of advance_particle, binning of
+// x_{t+1} into `lnext`, and the rebuild test for the neighbour list of x_{t+1}
+// (any particle farther than skin / 2 from where the list was built sets the
+// flag of parity s).  xin = buffer of x_t, lclr = cell list cleared for the
+// step after, sp = slot (parity) holding t.
+__global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int xin, int lnext, int lclr,
+                                              int sp, int accum_ke) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long s = D.stepv[sp] + 1ull;
+    if (i == 0) {
+        D.stepv[sp ^ 1] = s;
+        D.rflag[sp] = 0u;            // consumed by the k_nlist of step t
+    }
+    for (uint32_t c = i; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
+    unsigned long long ke = 0ull;
+    if (i < P.n) {
+        const float4* __restrict__ X = D.x[xin];
+        const float4 pi = X[i];
+        const uint32_t ti = type_of(pi);
+        long long fx = 0, fy = 0, fz = 0;
+        const uint32_t m = D.nl_cnt[i];
+        const uint32_t* __restrict__ nl = D.nl + i;
+        const size_t n = P.n;
+        uint32_t k = 0;
+        for (; k + 4 <= m; k += 4) {
+            const uint32_t j0 = nl[k * n], j1 = nl[(k + 1) * n], j2 = nl[(k + 2) * n], j3 = nl[(k + 3) * n];
+            const float4 p0 = X[j0], p1 = X[j1], p2 = X[j2], p3 = X[j3];
+            pair_force_xt(P, D, pi, p0, ti, fx, fy, fz, nullptr);
+            pair_force_xt(P, D, pi, p1, ti, fx, fy, fz, nullptr);
+            pair_force_xt(P, D, pi, p2, ti, fx, fy, fz, nullptr);
+            pair_force_xt(P, D, pi, p3, ti, fx, fy, fz, nullptr);
+        }
+        for (; k < m; ++k) pair_force_xt(P, D, pi, X[nl[k * n]], ti, fx, fy, fz, nullptr);
+        bond_forces(P, D, X, i, pi, ti, fx, fy, fz, nullptr);
+        float4 po;
+        ke = advance_particle(P, D, xin, lnext, i, pi, ti, fix_to_force(D, fx, fy, fz), s, accum_ke, po);
+        const float4 r = D.xref[i];
+        const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
+        if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[sp ^ 1] = 1u;
     }
     if (accum_ke) {
         for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
@@ -503,8 +578,7 @@ __device__ __forceinline__ int sweep_reaction(const Params& P, unsigned long lon
 }
 
 // Proposal phase (Sec. 2.3, Fig. sweep a) fused with the first matching round.
-__global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur,
-                                                 int lst, int sp) {
+__global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur, int sp) {
     const unsigned long long s = D.stepv[sp];
     const int a = sweep_reaction(P, s, slot);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -535,49 +609,36 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
     double best_score = 0.0;
     uint32_t best_tag = 0xFFFFFFFFu;
     int best_j = -1;
-    const uint32_t* __restrict__ cnt = D.ccount[lst];
-    const float4* __restrict__ cp = D.cpos[lst];
-    const int nc = (int)P.nc;
-    const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
-    for (int oz = -1; oz <= 1; ++oz) {
-        const int z = wrapc(cz + oz, nc);
-        for (int oy = -1; oy <= 1; ++oy) {
-            const int y = wrapc(cy + oy, nc);
-            for (int ox = -1; ox <= 1; ++ox) {
-                const int c = (z * nc + y) * nc + wrapc(cx + ox, nc);
-                uint32_t m = cnt[c];
-                m = m < P.cellcap ? m : P.cellcap;
-                for (uint32_t k = 0; k < m; ++k) {
-                    const float4 pj = cp[(size_t)c * P.cellcap + k];
-                    const uint32_t j = slot_index(pj);
-                    if (j == i) continue;
-                    const uint32_t tj = slot_type(pj);
-                    if (tj != want) continue;
-                    if ((uint32_t)D.occ[j] >= P.cap[tj]) continue;
-                    bool bonded = false;
+    // candidates: the neighbour list (complete for pairs within r_search >= r_max)
+    const uint32_t m = D.nl_cnt[i];
+    const size_t n = P.n;
+    for (uint32_t k = 0; k < m; ++k) {
+        const uint32_t j = D.nl[k * n + i];
+        const float4 pj = X[j];
+        const uint32_t tj = type_of(pj);
+        if (tj != want) continue;
+        if ((uint32_t)D.occ[j] >= P.cap[tj]) continue;
+        bool bonded = false;
 #pragma unroll
-                    for (int q = 0; q < kMaxValence + kMaxStatic; ++q) bonded |= mine[q] == j;
-                    if (bonded) continue;
-                    if (avoid && D.mol[j] == mol_i) continue;
-                    const float fdx = mi_delta_f(pi.x, pj.x, P);
-                    const float fdy = mi_delta_f(pi.y, pj.y, P);
-                    const float fdz = mi_delta_f(pi.z, pj.z, P);
-                    const float fr2 = fdx * fdx + fdy * fdy + fdz * fdz;
-                    if (fr2 > P.rmax2_pre[a] || fr2 < P.rmin2_pre[a]) continue;
-                    const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
-                    const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
-                    const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
-                    const double r = norm3(dx, dy, dz);
-                    if (!(r >= rmin && r <= rmax)) continue;
-                    const double score = fabs(r - r0);
-                    const uint32_t tgj = D.tag[j];
-                    if (best_j < 0 || score < best_score || (score == best_score && tgj < best_tag)) {
-                        best_score = score;
-                        best_tag = tgj;
-                        best_j = (int)j;
-                    }
-                }
-            }
+        for (int q = 0; q < kMaxValence + kMaxStatic; ++q) bonded |= mine[q] == j;
+        if (bonded) continue;
+        if (avoid && D.mol[j] == mol_i) continue;
+        const float fdx = mi_delta_f(pi.x, pj.x, P);
+        const float fdy = mi_delta_f(pi.y, pj.y, P);
+        const float fdz = mi_delta_f(pi.z, pj.z, P);
+        const float fr2 = fdx * fdx + fdy * fdy + fdz * fdz;
+        if (fr2 > P.rmax2_pre[a] || fr2 < P.rmin2_pre[a]) continue;
+        const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
+        const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
+        const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
+        const double r = norm3(dx, dy, dz);
+        if (!(r >= rmin && r <= rmax)) continue;
+        const double score = fabs(r - r0);
+        const uint32_t tgj = D.tag[j];
+        if (best_j < 0 || score < best_score || (score == best_score && tgj < best_tag)) {
+            best_score = score;
+            best_tag = tgj;
+            best_j = (int)j;
         }
     }
     if (best_j < 0) return;

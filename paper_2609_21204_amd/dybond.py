@@ -66,6 +66,7 @@ _SIGS = {
     "db_add_reaction": (_I, [_P, ctypes.POINTER(ReactionDesc), ctypes.POINTER(_U32)]),
     "db_set_integrator": (_I, [_P, _D, _D, _D, _U32, _I]),
     "db_set_cell_capacity": (_I, [_P, _U32]),
+    "db_set_neighbor_list": (_I, [_P, _D, _U32]),
     "db_validate": (_I, [_P]),
     "db_get_reaction": (_I, [_P, _U32, ctypes.POINTER(ReactionDesc), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "db_commit": (_I, [_P]),
@@ -166,6 +167,10 @@ def db_set_integrator(h, dt, kT, gamma, sweep_period, kt_source=DB_KT_SETPOINT):
 
 def db_set_cell_capacity(h, slots):
     _check(h, load().db_set_cell_capacity(h, slots))
+
+
+def db_set_neighbor_list(h, skin=-1.0, max_neighbors=0):
+    _check(h, load().db_set_neighbor_list(h, skin, max_neighbors))
 
 
 def db_validate(h):
