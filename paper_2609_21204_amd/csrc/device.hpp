@@ -100,8 +100,9 @@ __host__ __device__ inline int reaction_at(uint32_t seed, uint64_t s, int nrx, i
 __device__ __forceinline__ double mi_delta(float xi, float xj, double L, double invL) {
 #pragma clang fp contract(off)
     const double d = (double)xj - (double)xi;
-    const double k = rint(d * invL);
-    return d - k * L;
+    const double q = d * invL;
+    if (!(fabs(q) > 0.5)) return d;       // rint(q) == 0: no image (d - 0 L == d)
+    return d - rint(q) * L;
 }
 
 __device__ __forceinline__ double norm3(double dx, double dy, double dz) {
@@ -120,7 +121,7 @@ struct Params {
     double L, invL;
     float Lf, halfLf, cell_scale, h;   // h = dt / 2
     float c1;                          // exp(-gamma dt)
-    float rlist2;                      // (r_search + skin)^2 (1 + 1e-4): neighbour-list radius, FP32
+    uint32_t tpp;                      // threads per particle in k_step / k_propose
     float disp2;                       // (skin / 2 - 1e-4)^2: displacement that triggers a rebuild
     uint32_t nlmax;                    // neighbour-list slots per particle
     double kT;
@@ -129,6 +130,11 @@ struct Params {
     float mass[kMaxTypes];
     uint32_t cap[kMaxTypes];
     float rc2_pre[kMaxTypes * kMaxTypes];  // FP32 prefilter: (2^(1/6) sigma_ij)^2 (1 + 1e-3) + 1e-4; 0 = no WCA
+    float rc2_in[kMaxTypes * kMaxTypes];   // (0.98 rc)^2: below it the FP32 force has no cancellation
+    float rl2[kMaxTypes * kMaxTypes];      // neighbour-list radius^2 of the type pair: (max(rc, r_max) + skin)^2 (1 + 1e-4)
+    float sig2f[kMaxTypes * kMaxTypes];    // sigma_ij^2
+    float eps24f[kMaxTypes * kMaxTypes];   // 24 eps_ij
+
     uint32_t bkind[kMaxBondTypes];
     double bk[kMaxBondTypes], br0[kMaxBondTypes], bR02[kMaxBondTypes], binvR02[kMaxBondTypes];
     float rmax2_pre[kMaxRx], rmin2_pre[kMaxRx];  // FP32 prefilter of the reaction window
@@ -177,7 +183,7 @@ struct Dev {
     uint32_t* nl;          // nlmax x n neighbour indices (slot-major)
     uint32_t* nl_cnt;      // neighbours per particle
     float4* xref;          // positions at the last neighbour-list build
-    uint32_t* rflag;       // two rebuild flags (parity of the step)
+    uint32_t* rflag;       // neighbour-list rebuild flags of steps t, t+1, t+2 (index step mod 3)
     // spatial reordering (counting sort by cell): new index of every particle,
     // cell offsets, and second copies of every per-particle array
     uint32_t* newidx;
@@ -239,7 +245,7 @@ __device__ __forceinline__ double rsqrt64(double x) {
 // the exact FP64 evaluation (its error, ~1e-5, is far below the margins).
 __device__ __forceinline__ float mi_delta_f(float xi, float xj, const Params& P) {
     float d = xj - xi;
-    d -= P.Lf * rintf(d * (1.0f / P.Lf));
+    if (fabsf(d) > P.halfLf) d -= P.Lf * rintf(d * (1.0f / P.Lf));
     return d;
 }
 

@@ -107,6 +107,7 @@ db_status fail(db_system* s, db_status st, const char* fmt, ...) {
 inline unsigned grid_of(uint32_t n) { return (n + kBlock - 1) / kBlock; }
 inline unsigned ntiles(const Params& P) { return P.ntile[0] * P.ntile[1] * P.ntile[2]; }
 
+
 struct TimerScope {
     db_system* s;
     const char* name;
@@ -126,7 +127,10 @@ struct TimerScope {
     ~TimerScope() {
         if (!a) return;
         (void)hipEventRecord(b, s->stream);
-        s->timing.pending.push_back({name, a, b});
+        std::string nm(name);
+        const size_t lt = nm.find('<');      // k_step<4> is reported as k_step
+        if (lt != std::string::npos) nm.resize(lt);
+        s->timing.pending.push_back({nm, a, b});
     }
 };
 
@@ -312,13 +316,16 @@ uint32_t cell_capacity(const db_system* s, const Params& P, const float* pos3 = 
     return (c + 7u) & ~7u;
 }
 
-// Cells per k_step tile: about 96 particles in the tile core at the mean
-// density, shrunk until there are at least 512 tiles (enough workgroups to
-// cover the chip) or the tile is 2 cells wide; t <= 6 so (t + 2)^3 <= kTileMaxHalo.
+// Cells per neighbour-list tile: about 128 particles in the tile core at the
+// mean density, while the halo, (t + 2)^3 cells, holds at most 400 particles
+// on average (LDS room is 1024, for clusters denser than the mean); shrunk
+// until there are at least 512 tiles (enough workgroups to cover the chip) or
+// the tile is 2 cells wide; t <= 6 so (t + 2)^3 <= kTileMaxHalo.
 void choose_tiles(const db_system* s, Params& P) {
     const double lam = std::max((double)s->n / (double)P.ncell, 1e-6);
-    int t = (int)std::lround(std::cbrt(96.0 / lam));
+    int t = (int)std::lround(std::cbrt(128.0 / lam));
     t = std::max(1, std::min({t, 6, (int)P.nc}));
+    while (t > 1 && lam * (t + 2) * (t + 2) * (t + 2) > 400.0) --t;
     auto ntiles = [&](int tt) {
         const long k = ((long)P.nc + tt - 1) / tt;
         return k * k * k;
@@ -368,6 +375,9 @@ void fill_params(db_system* s) {
                 s->pair_h[k] = PairTab{sig * sig, 24.0 * eps, c, c * c * (1.0 - 1e-14), c * c * (1.0 + 1e-14),
                                        eps, 0.0, 0.0};
                 P.rc2_pre[k] = (float)(c * c * (1.0 + 1e-3) + 1e-4);
+                P.rc2_in[k] = (float)(0.98 * 0.98 * c * c);
+                P.sig2f[k] = (float)(sig * sig);
+                P.eps24f[k] = (float)(24.0 * eps);
                 rc = std::max(rc, c);
             }
         }
@@ -398,13 +408,25 @@ void fill_params(db_system* s) {
     const double rsearch = std::max(rc, rmax_all);
     const double skin = effective_skin(s, rsearch);
     const double rlist = rsearch + skin;
-    P.rlist2 = (float)(rlist * rlist * (1.0 + 1e-4));
+    // list radius per type pair: the WCA cutoff or the largest r_max of a
+    // reaction between the two types, plus the skin
+    for (uint32_t a = 0; a < s->ntypes; ++a)
+        for (uint32_t b = 0; b < s->ntypes; ++b) {
+            double need = s->pair_h.empty() ? 0.0 : s->pair_h[a * kMaxTypes + b].rc;
+            for (const auto& d : s->rx)
+                if ((d.type_a == a && d.type_b == b) || (d.type_a == b && d.type_b == a)) need = std::max(need, d.r_max);
+            const double rl = need > 0.0 ? need + skin : 0.0;
+            P.rl2[a * kMaxTypes + b] = (float)(rl * rl * (1.0 + 1e-4));
+        }
+    P.tpp = 1;
+    while (P.tpp < 32 && (uint64_t)s->n * P.tpp < 524288ull) P.tpp *= 2;
     P.disp2 = (float)std::max(0.0, (0.5 * skin - 1e-4) * (0.5 * skin - 1e-4));
     // neighbour slots: room for 2.5x the mean count of an ideal gas at this
     // density plus 32, at least 64 (or exactly what the caller asked for)
     const double mean_nb = 4.18879020478639 * rlist * rlist * rlist * (double)s->n / (s->L * s->L * s->L);
     const uint32_t auto_nl = (std::max<uint32_t>(64u, (uint32_t)std::ceil(2.5 * mean_nb + 32.0)) + 7u) & ~7u;
     P.nlmax = s->nlmax_user ? s->nlmax_user : auto_nl;
+
     P.nc = (uint32_t)std::floor(s->L / (rlist * (1.0 + 1e-5)));
     P.ncell = P.nc * P.nc * P.nc;
     P.cell_scale = (float)((double)P.nc / s->L);
@@ -471,12 +493,13 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
     HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv, sizeof sv, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemsetAsync(s->D.err, 0, 4 * sizeof(uint32_t), s->stream));
     HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, sizeof(unsigned long long), s->stream));
-    HIPCHK(s, hipMemsetAsync(s->D.rflag, 0, 2 * sizeof(uint32_t), s->stream));
+    const uint32_t flags[3] = {s->step % 3 == 0, s->step % 3 == 1, s->step % 3 == 2};   // lists built below
+    HIPCHK(s, hipMemcpyAsync(s->D.rflag, flags, sizeof flags, hipMemcpyHostToDevice, s->stream));
     s->cur_x = 0;
     s->cur_list = 0;
     for (int l = 0; l < 3; ++l) LAUNCH(s, k_clear_counts, std::min(grid_of(P.ncell), 65535u), kBlock, s->P, s->D, l);
     LAUNCH(s, k_bin, grid_of(n), kBlock, s->P, s->D, 0, 0);
-    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, s->P, s->D, 0, 0, (int)(s->step & 1), 1);
+    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, s->P, s->D, 0, (int)(s->step % 3));
     LAUNCH(s, k_eval, grid_of(n), kBlock, s->P, s->D, 0, 0, 0u);
     LAUNCH(s, k_init_u, grid_of(n), kBlock, s->P, s->D, 0, 0u);
     HIPCHK(s, hipGetLastError());
@@ -527,11 +550,19 @@ db_status check_errors(db_system* s) {
 }
 
 // Sweep at the current positions: buffers xcur / cell list lst, step key in slot sp.
-void launch_sweep(db_system* s, int xcur, int lst, int sp) {
+void launch_sweep(db_system* s, int xcur, int sp) {
     const Params& P = s->P;
     const unsigned g = grid_of(P.n);
     for (int slot = 0; slot < (int)P.nrx; ++slot) {
-        LAUNCH(s, k_propose, g, kBlock, P, s->D, slot, xcur, sp);
+        const unsigned gp = (unsigned)(((uint64_t)P.n * P.tpp + kBlock - 1) / kBlock);
+        switch (P.tpp) {
+            case 1: LAUNCH(s, k_propose<1>, gp, kBlock, P, s->D, slot, xcur, sp); break;
+            case 2: LAUNCH(s, k_propose<2>, gp, kBlock, P, s->D, slot, xcur, sp); break;
+            case 4: LAUNCH(s, k_propose<4>, gp, kBlock, P, s->D, slot, xcur, sp); break;
+            case 8: LAUNCH(s, k_propose<8>, gp, kBlock, P, s->D, slot, xcur, sp); break;
+            case 16: LAUNCH(s, k_propose<16>, gp, kBlock, P, s->D, slot, xcur, sp); break;
+            default: LAUNCH(s, k_propose<32>, gp, kBlock, P, s->D, slot, xcur, sp); break;
+        }
         LAUNCH(s, k_claim, g, kBlock, P, s->D, slot, 1, xcur, sp);
         for (int q = 2; q <= kMatchRounds; ++q) {
             LAUNCH(s, k_kill, g, kBlock, P, s->D, q, q == kMatchRounds ? 1 : 0);
@@ -546,16 +577,16 @@ void launch_sweep(db_system* s, int xcur, int lst, int sp) {
 // then rebuild that cell list with the new numbers.
 void launch_sort(db_system* s) {
     const Params& P = s->P;
-    const unsigned gc = grid_of(P.ncell), g = grid_of(P.n);
+    const unsigned gc = grid_of(P.ncell), gb = grid_of(P.ncell * P.ntypes), g = grid_of(P.n);
     const int xc = s->cur_x, lc = s->cur_list;
-    LAUNCH(s, k_cell_scan_blocks, gc, kBlock, P, s->D, lc);
-    LAUNCH(s, k_scan_bsum, 1, 1024, s->D.cbsum, gc);
-    LAUNCH(s, k_sort_assign, gc, kBlock, P, s->D, lc);
+    LAUNCH(s, k_cell_scan_blocks, gb, kBlock, P, s->D, lc);
+    LAUNCH(s, k_scan_bsum, 1, 1024, s->D.cbsum, gb);
+    LAUNCH(s, k_sort_assign, gb, kBlock, P, s->D, lc);
     LAUNCH(s, k_sort_scatter, g, kBlock, P, s->D, xc);
-    LAUNCH(s, k_sort_copyback, g, kBlock, P, s->D, xc);
+    LAUNCH(s, k_sort_copyback, g, kBlock, P, s->D, xc, (int)(s->step % 3));
     LAUNCH(s, k_clear_counts, std::min(gc, 65535u), kBlock, P, s->D, lc);
     LAUNCH(s, k_bin, g, kBlock, P, s->D, xc, lc);
-    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, xc, lc, (int)(s->step & 1), 1);
+    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, lc, (int)(s->step % 3));
     s->tags_dirty = true;
 }
 
@@ -567,20 +598,30 @@ void launch_step(db_system* s) {
     const int lnext = (lcur + 1) % 3, lclr = (lcur + 2) % 3;
     const int sp = (int)(t & 1);
     const bool sweep = P.nrx > 0 && ((t + 1) % P.period == 0);
-    LAUNCH(s, k_step, grid_of(P.n), kBlock, P, s->D, xin, lnext, lclr, sp, (sweep && P.kt_kinetic) ? 1 : 0);
-    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, xin ^ 1, lnext, sp ^ 1, 0);
+    const int ake = (sweep && P.kt_kinetic) ? 1 : 0;
+    const unsigned gs = (unsigned)(((uint64_t)P.n * P.tpp + kBlock - 1) / kBlock);
+    switch (P.tpp) {
+        case 1: LAUNCH(s, k_step<1>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
+        case 2: LAUNCH(s, k_step<2>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
+        case 4: LAUNCH(s, k_step<4>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
+        case 8: LAUNCH(s, k_step<8>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
+        case 16: LAUNCH(s, k_step<16>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
+        default: LAUNCH(s, k_step<32>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
+    }
+    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, lnext, (int)((t + 1) % 3));
     s->cur_x ^= 1;
     s->cur_list = lnext;
     s->step = t + 1;
-    if (sweep) launch_sweep(s, s->cur_x, s->cur_list, (int)((t + 1) & 1));
+    if (sweep) launch_sweep(s, s->cur_x, (int)((t + 1) & 1));
 }
 
 // Steps per graph: a whole number of sweep periods that also returns the
-// rotating buffers (x: 2, cell lists: 3, step slots: 2) to where they were.
+// rotating buffers (x: 2, cell lists: 3, step slots: 2, rebuild flags: 3) to
+// where they were.
 uint64_t graph_span(const db_system* s) {
     uint64_t g = s->period;
     while (g % 6 != 0) g += s->period;
-    while (g < 30) g *= 2;
+    while (g < 120) g *= 2;
     return g;
 }
 
@@ -853,10 +894,10 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.nl, (size_t)P.nlmax * n);
     DALLOC(s, D.nl_cnt, n);
     DALLOC(s, D.xref, n);
-    DALLOC(s, D.rflag, 2);
+    DALLOC(s, D.rflag, 4);
     DALLOC(s, D.newidx, n);
-    DALLOC(s, D.cstart, (size_t)P.ncell + 1);
-    DALLOC(s, D.cbsum, grid_of(P.ncell) + 1);
+    DALLOC(s, D.cstart, (size_t)P.ncell * P.ntypes + 1);
+    DALLOC(s, D.cbsum, grid_of(P.ncell * P.ntypes) + 1);
     DALLOC(s, D.x_alt, n);
     DALLOC(s, D.u_alt, n);
     DALLOC(s, D.img_alt, 3 * (size_t)n);
@@ -914,7 +955,7 @@ db_status db_sweep_frozen(db_system* s, uint64_t step_key) {
         HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, 8, s->stream));
         LAUNCH(s, k_ke_accum, g, kBlock, s->P, s->D, xc);
     }
-    launch_sweep(s, xc, lc, (int)(step_key & 1));
+    launch_sweep(s, xc, (int)(step_key & 1));
     LAUNCH(s, k_eval, g, kBlock, s->P, s->D, xc, lc, s->n);
     LAUNCH(s, k_fix_u, g, kBlock, s->P, s->D, xc);
     HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv_back, sizeof sv_back, hipMemcpyHostToDevice, s->stream));

@@ -99,6 +99,34 @@ __device__ __forceinline__ void pair_force_xt(const Params& P, const Dev& D, flo
     pair_force(P, D, pi, q, ti, fx, fy, fz, e);
 }
 
+// WCA force on pi from neighbour-list entry pj (type in the w bits).  When no
+// component of x_j - x_i needs a periodic image, the FP32 difference is the
+// correctly rounded separation, and pairs inside 0.98 rc (where
+// 2 (sigma/r)^6 - 1 > 0.12, no cancellation) are evaluated in FP32.  Pairs
+// near the cutoff and pairs across the boundary take the FP64 path of
+// pair_force.
+__device__ __forceinline__ void pair_force_list(const Params& P, const Dev& D, float4 pi, float4 pj, uint32_t ti,
+                                                long long& fx, long long& fy, long long& fz) {
+    const int pt = (int)ti * kMaxTypes + (int)type_of(pj);
+    const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    if (fabsf(dx) <= P.halfLf && fabsf(dy) <= P.halfLf && fabsf(dz) <= P.halfLf) {
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= P.rc2_pre[pt]) return;
+        if (r2 < P.rc2_in[pt]) {
+            const float ir2 = __builtin_amdgcn_rcpf(r2);
+            const float sr2 = P.sig2f[pt] * ir2;
+            const float sr6 = sr2 * sr2 * sr2;
+            const float f = P.eps24f[pt] * sr6 * (2.0f * sr6 - 1.0f) * ir2;
+            fx -= to_fix((double)(f * dx), D.err);
+            fy -= to_fix((double)(f * dy), D.err);
+            fz -= to_fix((double)(f * dz), D.err);
+            return;
+        }
+    }
+    const float4 q = make_float4(pj.x, pj.y, pj.z, __uint_as_float(type_of(pj) << 24));
+    pair_force(P, D, pi, q, ti, fx, fy, fz, nullptr);
+}
+
 // Static and dynamic bond forces on particle i.
 __device__ __forceinline__ void bond_forces(const Params& P, const Dev& D, const float4* __restrict__ X,
                                             uint32_t i, float4 pi, uint32_t ti,
@@ -306,34 +334,49 @@ __device__ __forceinline__ unsigned long long advance_particle(const Params& P, 
 
 constexpr int kTileThreads = 128;
 constexpr int kTileMaxHalo = 512;       // halo cells of one tile, (t+2)^3 <= 512
-constexpr int kTileMaxEntries = 512;    // particles staged in LDS per tile
+constexpr int kTileMaxEntries = 1024;   // particles staged in LDS per tile
 
-// Neighbour list: for every particle, the indices of all particles closer
-// than r_list = r_search + skin at the current positions (the list stays
+// Workgroups are dealt round-robin to the 8 XCDs.  This remaps the workgroup
+// id so that each XCD gets a contiguous run of work items (particles are kept
+// in cell order, so a run is a compact slab of space whose data fits that
+// XCD's L2).
+__device__ __forceinline__ uint32_t xcd_block() {
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t per = nb / 8u, rem = nb % 8u, xcd = b % 8u;
+    return xcd * per + (xcd < rem ? xcd : rem) + b / 8u;
+}
+
+// Append j to the neighbour list of i when it lies within the list radius of
+// their type pair (only pairs that interact or can react are listed).
+__device__ __forceinline__ void nl_consider(const Params& P, const Dev& D, uint32_t i, float4 pi, float4 pj,
+                                            uint32_t& m) {
+    const float dx = mi_delta_f(pi.x, pj.x, P), dy = mi_delta_f(pi.y, pj.y, P), dz = mi_delta_f(pi.z, pj.z, P);
+    if (dx * dx + dy * dy + dz * dz < P.rl2[slot_type(pi) * kMaxTypes + slot_type(pj)]) {
+        if (m < P.nlmax) D.nl[(size_t)m * P.n + i] = slot_index(pj);
+        ++m;
+    }
+}
+
+// Neighbour lists: for every particle, the indices of all particles closer
+// than r_list = r_search + skin at the current positions; a list stays
 // complete for pairs within r_search until some particle has moved by
-// skin / 2).  Built from the cell list `lst` of those positions, one
-// workgroup per tile of cells: the cell counts of the tile and its one-cell
-// halo are scanned in LDS, the halo's particles (position + index/type words)
-// are staged in LDS with independent loads, and each thread takes one
-// particle of the tile core and visits its 27 neighbour cells as 9 contiguous
-// LDS ranges.  Tiles whose halo holds more than kTileMaxEntries particles
-// read the same stencil from global memory.  Workgroups are dealt round-robin
-// to the 8 XCDs; consecutive workgroup ids are remapped so that each XCD gets
-// a contiguous run of tiles (neighbouring tiles share halo cells in its L2).
-// The kernel does nothing unless the rebuild flag of this step's parity `fp`
-// is set (by k_step, when a particle has moved by more than skin / 2) or
-// `force` is given; it records the positions it was built at.
-__global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const Dev D, int xin, int lst, int fp,
-                                                        int force) {
-    if (!force && D.rflag[fp] == 0u) return;
+// skin / 2 from where it was built.  Built from the cell list `lst` of those
+// positions, one workgroup per tile of cells: the cell counts of the tile and
+// its one-cell halo are scanned in LDS, the halo's particles (position +
+// index/type words) are staged in LDS with independent loads, and each thread
+// takes one particle of the tile core and visits its 27 neighbour cells as 9
+// contiguous LDS ranges.  Tiles whose halo holds more than kTileMaxEntries
+// particles read the same stencil from global memory.  Does nothing unless
+// the rebuild flag `f3` (set by k_step when a particle has moved by more than
+// skin / 2, or by a renumbering) is set.
+__global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const Dev D, int lst, int f3) {
+    if (D.rflag[f3] == 0u) return;
     __shared__ float4 ent[kTileMaxEntries];
     __shared__ uint32_t hoff[kTileMaxHalo + 1];
     __shared__ uint32_t core[kTileMaxEntries];
     __shared__ uint32_t ncore;
     const uint32_t tid = threadIdx.x;
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
-    const uint32_t per = nb / 8u, rem = nb % 8u, xcd = b % 8u;
-    const uint32_t tile = xcd * per + (xcd < rem ? xcd : rem) + b / 8u;
+    const uint32_t tile = xcd_block();
     const int nc = (int)P.nc;
     const int bx = (int)(tile % P.ntile[0]), by = (int)((tile / P.ntile[0]) % P.ntile[1]);
     const int bz = (int)(tile / (P.ntile[0] * P.ntile[1]));
@@ -350,7 +393,6 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
     };
     const uint32_t* __restrict__ cnt = D.ccount[lst];
     const float4* __restrict__ cp = D.cpos[lst];
-
     // halo counts -> exclusive offsets (each thread scans a contiguous chunk)
     const int chunk = (nh + kTileThreads - 1) / kTileThreads;     // <= 4
     uint32_t loc[4];
@@ -379,7 +421,6 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
         ncore = 0;
     }
     __syncthreads();
-    const size_t n = P.n;
     bool over = false;
     if (total <= (uint32_t)kTileMaxEntries) {
         for (int h = (int)tid; h < nh; h += kTileThreads) {
@@ -403,16 +444,8 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
                 for (int oy = -1; oy <= 1; ++oy) {
                     const int hr = ((iz + oz) * hy + (iy + oy)) * hx + (ix - 1);
                     const uint32_t lo = hoff[hr], hi = hoff[hr + 3];
-                    for (uint32_t e2 = lo; e2 < hi; ++e2) {
-                        if (e2 == e) continue;
-                        const float4 pj = ent[e2];
-                        const float dx = mi_delta_f(pi.x, pj.x, P), dy = mi_delta_f(pi.y, pj.y, P);
-                        const float dz = mi_delta_f(pi.z, pj.z, P);
-                        if (dx * dx + dy * dy + dz * dz < P.rlist2) {
-                            if (m < P.nlmax) D.nl[m * n + i] = slot_index(pj);
-                            ++m;
-                        }
-                    }
+                    for (uint32_t e2 = lo; e2 < hi; ++e2)
+                        if (e2 != e) nl_consider(P, D, i, pi, ent[e2], m);
                 }
             }
             over |= m > P.nlmax;
@@ -424,8 +457,8 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
             if (!is_core(h)) continue;
             const uint32_t o = hoff[h], m0 = hoff[h + 1] - o;
             const size_t base = (size_t)hcell(h) * P.cellcap;
-            for (uint32_t k = 0; k < m0; ++k) {
-                const float4 pi = cp[base + k];
+            for (uint32_t k0 = 0; k0 < m0; ++k0) {
+                const float4 pi = cp[base + k0];
                 const uint32_t i = slot_index(pi);
                 const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
                 uint32_t m = 0;
@@ -437,13 +470,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
                             mc = mc < P.cellcap ? mc : P.cellcap;
                             for (uint32_t kk = 0; kk < mc; ++kk) {
                                 const float4 pj = cp[(size_t)c * P.cellcap + kk];
-                                if (slot_index(pj) == i) continue;
-                                const float dx = mi_delta_f(pi.x, pj.x, P), dy = mi_delta_f(pi.y, pj.y, P);
-                                const float dz = mi_delta_f(pi.z, pj.z, P);
-                                if (dx * dx + dy * dy + dz * dz < P.rlist2) {
-                                    if (m < P.nlmax) D.nl[m * n + i] = slot_index(pj);
-                                    ++m;
-                                }
+                                if (slot_index(pj) != i) nl_consider(P, D, i, pi, pj, m);
                             }
                         }
                 over |= m > P.nlmax;
@@ -455,46 +482,63 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
     if (over) atomicOr(&D.err[0], kErrNlist);
 }
 
-// One BAOAB step t -> s = t + 1 for every particle: WCA forces over the
-// neighbour list, bond forces, the integration of advance_particle, binning of
-// x_{t+1} into `lnext`, and the rebuild test for the neighbour list of x_{t+1}
-// (any particle farther than skin / 2 from where the list was built sets the
-// flag of parity s).  xin = buffer of x_t, lclr = cell list cleared for the
-// step after, sp = slot (parity) holding t.
-__global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int xin, int lnext, int lclr,
-                                              int sp, int accum_ke) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+// One BAOAB step t -> s = t + 1.  TPP threads share a particle: each takes
+// every TPP-th entry of the particle's neighbour list and every TPP-th bond
+// slot, and the fixed-point partial sums are combined with wave shuffles (the
+// sum is exact, so the split does not change the result).  The first thread
+// of the group then integrates (advance_particle), bins x_{t+1} into
+// `lnext`, and tests the list: a particle farther than skin / 2 from where
+// its list was built sets the flag of step t+1, read by the k_nlist launched
+// right after.  Several threads per particle keep enough waves in flight to
+// hide the latency of the neighbour gathers when the system is small for the
+// chip.
+//   xin = buffer of x_t, lnext = cell list receiving x_{t+1}, lclr = list
+//   cleared for the step after, sp = t mod 2, f3 = t mod 3.
+template <int TPP>
+__global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
+                                              int f3, int accum_ke) {
+    const uint32_t tg = xcd_block() * blockDim.x + threadIdx.x;
+    const uint32_t i = tg / TPP, lane = tg % TPP;
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned long long s = D.stepv[sp] + 1ull;
-    if (i == 0) {
+    const int fnext = f3 == 2 ? 0 : f3 + 1;
+    if (gtid == 0) {
         D.stepv[sp ^ 1] = s;
-        D.rflag[sp] = 0u;            // consumed by the k_nlist of step t
+        D.rflag[f3] = 0u;               // consumed by the k_nlist of step t
     }
-    for (uint32_t c = i; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
+    for (uint32_t c = gtid; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
     unsigned long long ke = 0ull;
     if (i < P.n) {
+        const size_t n = P.n;
         const float4* __restrict__ X = D.x[xin];
         const float4 pi = X[i];
         const uint32_t ti = type_of(pi);
         long long fx = 0, fy = 0, fz = 0;
         const uint32_t m = D.nl_cnt[i];
-        const uint32_t* __restrict__ nl = D.nl + i;
-        const size_t n = P.n;
-        uint32_t k = 0;
-        for (; k + 4 <= m; k += 4) {
-            const uint32_t j0 = nl[k * n], j1 = nl[(k + 1) * n], j2 = nl[(k + 2) * n], j3 = nl[(k + 3) * n];
-            const float4 p0 = X[j0], p1 = X[j1], p2 = X[j2], p3 = X[j3];
-            pair_force_xt(P, D, pi, p0, ti, fx, fy, fz, nullptr);
-            pair_force_xt(P, D, pi, p1, ti, fx, fy, fz, nullptr);
-            pair_force_xt(P, D, pi, p2, ti, fx, fy, fz, nullptr);
-            pair_force_xt(P, D, pi, p3, ti, fx, fy, fz, nullptr);
+        for (uint32_t k = lane; k < m; k += TPP) pair_force_list(P, D, pi, X[D.nl[k * n + i]], ti, fx, fy, fz);
+        for (uint32_t k = lane; k < P.stat_max; k += TPP) {
+            const uint32_t w = D.stat[k * n + i];
+            if (w != kEmpty) bond_force(P, D, pi, X[w & kIdxMask], w >> 24, i, w & kIdxMask, fx, fy, fz, nullptr);
         }
-        for (; k < m; ++k) pair_force_xt(P, D, pi, X[nl[k * n]], ti, fx, fy, fz, nullptr);
-        bond_forces(P, D, X, i, pi, ti, fx, fy, fz, nullptr);
-        float4 po;
-        ke = advance_particle(P, D, xin, lnext, i, pi, ti, fix_to_force(D, fx, fy, fz), s, accum_ke, po);
-        const float4 r = D.xref[i];
-        const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
-        if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[sp ^ 1] = 1u;
+        const uint32_t cap = P.cap[ti];
+        for (uint32_t k = lane; k < cap; k += TPP) {
+            const uint32_t w = D.dyn[k * n + i];
+            if (w != kEmpty)
+                bond_force(P, D, pi, X[w & kIdxMask], P.rbt[(w >> 24) & 0x7Fu], i, w & kIdxMask, fx, fy, fz, nullptr);
+        }
+#pragma unroll
+        for (int o = TPP / 2; o >= 1; o >>= 1) {
+            fx += __shfl_xor(fx, o, 64);
+            fy += __shfl_xor(fy, o, 64);
+            fz += __shfl_xor(fz, o, 64);
+        }
+        if (lane == 0) {
+            float4 po;
+            ke = advance_particle(P, D, xin, lnext, i, pi, ti, fix_to_force(D, fx, fy, fz), s, accum_ke, po);
+            const float4 r = D.xref[i];
+            const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
+            if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[fnext] = 1u;
+        }
     }
     if (accum_ke) {
         for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
@@ -507,27 +551,38 @@ __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int x
 // inside a cell) so that the particles of a tile and their bond partners sit
 // close together in memory.  Nothing computed depends on the numbering: random
 // streams and tie-breaks use tags, sums are in fixed point.
+// Buckets are (type, cell) in type-major order, so that consecutive particles
+// (and hence the lanes of a wave) share one type and its valence.
+__device__ __forceinline__ uint32_t bucket_count(const Params& P, const Dev& D, int lst, uint32_t b) {
+    const uint32_t t = b / P.ncell, c = b - t * P.ncell;
+    uint32_t m = D.ccount[lst][c];
+    m = m < P.cellcap ? m : P.cellcap;
+    const float4* cp = D.cpos[lst] + (size_t)c * P.cellcap;
+    uint32_t r = 0;
+    for (uint32_t k = 0; k < m; ++k) r += slot_type(cp[k]) == t;
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_cell_scan_blocks(const Params P, const Dev D, int lst) {
-    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t m = 0;
-    if (c < P.ncell) {
-        m = D.ccount[lst][c];
-        m = m < P.cellcap ? m : P.cellcap;
-    }
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nbk = P.ntypes * P.ncell;
+    const uint32_t m = b < nbk ? bucket_count(P, D, lst, b) : 0u;
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan(m, &tot);
-    if (c < P.ncell) D.cstart[c] = ex;
+    if (b < nbk) D.cstart[b] = ex;
     if (threadIdx.x == 0) D.cbsum[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_sort_assign(const Params P, const Dev D, int lst) {
-    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P.ncell) return;
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= P.ntypes * P.ncell) return;
+    const uint32_t t = b / P.ncell, c = b - t * P.ncell;
     uint32_t m = D.ccount[lst][c];
     m = m < P.cellcap ? m : P.cellcap;
-    const uint32_t base = D.cstart[c] + D.cbsum[blockIdx.x];
+    uint32_t at = D.cstart[b] + D.cbsum[blockIdx.x];
     const float4* cp = D.cpos[lst] + (size_t)c * P.cellcap;
-    for (uint32_t k = 0; k < m; ++k) D.newidx[slot_index(cp[k])] = base + k;
+    for (uint32_t k = 0; k < m; ++k)
+        if (slot_type(cp[k]) == t) D.newidx[slot_index(cp[k])] = at++;
 }
 
 __device__ __forceinline__ uint32_t remap_slot(const Dev& D, uint32_t w) {
@@ -553,8 +608,9 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const Params P, const Dev 
     for (uint32_t k = 0; k < P.stat_max; ++k) D.stat_alt[k * n + j] = remap_slot(D, D.stat[k * n + i]);
 }
 
-__global__ __launch_bounds__(256) void k_sort_copyback(const Params P, const Dev D, int xin) {
+__global__ __launch_bounds__(256) void k_sort_copyback(const Params P, const Dev D, int xin, int f3) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) D.rflag[f3] = 1u;    // indices changed: the next step rebuilds the neighbour lists
     if (i >= P.n) return;
     const size_t n = P.n;
     D.x[xin][i] = D.x_alt[i];
@@ -578,16 +634,22 @@ __device__ __forceinline__ int sweep_reaction(const Params& P, unsigned long lon
 }
 
 // Proposal phase (Sec. 2.3, Fig. sweep a) fused with the first matching round.
+// TPP threads share a proposer: each scans every TPP-th neighbour-list entry
+// and the group keeps the lexicographic minimum of (|r - r0|, tag).
+template <int TPP>
 __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur, int sp) {
     const unsigned long long s = D.stepv[sp];
     const int a = sweep_reaction(P, s, slot);
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) D.live_count[0] = 0u;
+    const uint32_t tg = xcd_block() * blockDim.x + threadIdx.x;
+    const uint32_t i = tg / TPP, lane = tg % TPP;
+    if (tg == 0) D.live_count[0] = 0u;
     if (i >= P.n) return;
-    D.best[2][i] = kNoKey;
-    D.claimed[i] = 0;
-    D.estate[i] = kEdgeNone;
-    D.prop[i] = -1;
+    if (lane == 0) {
+        D.best[2][i] = kNoKey;
+        D.claimed[i] = 0;
+        D.estate[i] = kEdgeNone;
+        D.prop[i] = -1;
+    }
     const float4* __restrict__ X = D.x[xcur];
     const float4 pi = X[i];
     const uint32_t ti = type_of(pi);
@@ -609,30 +671,27 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
     double best_score = 0.0;
     uint32_t best_tag = 0xFFFFFFFFu;
     int best_j = -1;
-    // candidates: the neighbour list (complete for pairs within r_search >= r_max)
-    const uint32_t m = D.nl_cnt[i];
-    const size_t n = P.n;
-    for (uint32_t k = 0; k < m; ++k) {
-        const uint32_t j = D.nl[k * n + i];
-        const float4 pj = X[j];
-        const uint32_t tj = type_of(pj);
-        if (tj != want) continue;
-        if ((uint32_t)D.occ[j] >= P.cap[tj]) continue;
+    // candidate j: partner type, free, not yet bonded to i, other molecule if
+    // required, inside [r_min, r_max] (FP32 screen, then the exact FP64 r);
+    // keep the smallest (|r - r0|, tag)
+    auto consider = [&](uint32_t j, float4 pj, uint32_t tj) {
+        if (tj != want) return;
+        if ((uint32_t)D.occ[j] >= P.cap[tj]) return;
         bool bonded = false;
 #pragma unroll
         for (int q = 0; q < kMaxValence + kMaxStatic; ++q) bonded |= mine[q] == j;
-        if (bonded) continue;
-        if (avoid && D.mol[j] == mol_i) continue;
+        if (bonded) return;
+        if (avoid && D.mol[j] == mol_i) return;
         const float fdx = mi_delta_f(pi.x, pj.x, P);
         const float fdy = mi_delta_f(pi.y, pj.y, P);
         const float fdz = mi_delta_f(pi.z, pj.z, P);
         const float fr2 = fdx * fdx + fdy * fdy + fdz * fdz;
-        if (fr2 > P.rmax2_pre[a] || fr2 < P.rmin2_pre[a]) continue;
+        if (fr2 > P.rmax2_pre[a] || fr2 < P.rmin2_pre[a]) return;
         const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
         const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
         const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
         const double r = norm3(dx, dy, dz);
-        if (!(r >= rmin && r <= rmax)) continue;
+        if (!(r >= rmin && r <= rmax)) return;
         const double score = fabs(r - r0);
         const uint32_t tgj = D.tag[j];
         if (best_j < 0 || score < best_score || (score == best_score && tgj < best_tag)) {
@@ -640,8 +699,28 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
             best_tag = tgj;
             best_j = (int)j;
         }
+    };
+    // the neighbour list (rebuilt right after every step that needed it) holds
+    // every pair within r_search >= r_max
+    const uint32_t m = D.nl_cnt[i];
+    const size_t n = P.n;
+    for (uint32_t k = lane; k < m; k += TPP) {
+        const uint32_t j = D.nl[k * n + i];
+        const float4 pj = X[j];
+        consider(j, pj, type_of(pj));
     }
-    if (best_j < 0) return;
+#pragma unroll
+    for (int o = TPP / 2; o >= 1; o >>= 1) {
+        const double os = __shfl_xor(best_score, o, 64);
+        const uint32_t ot = __shfl_xor(best_tag, o, 64);
+        const int oj = __shfl_xor(best_j, o, 64);
+        if (oj >= 0 && (best_j < 0 || os < best_score || (os == best_score && ot < best_tag))) {
+            best_score = os;
+            best_tag = ot;
+            best_j = oj;
+        }
+    }
+    if (lane != 0 || best_j < 0) return;
     const uint32_t tgi = D.tag[i];
     const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), tgi, 0u, P.seed, stream_k1(kMatch, a, 0));
     const uint64_t key = ((uint64_t)w.w0 << 32) | tgi;
@@ -697,7 +776,7 @@ __global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int 
                                                int xcur, int sp) {
     const unsigned long long s = D.stepv[sp];
     const int a = sweep_reaction(P, s, slot);
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = xcd_block() * blockDim.x + threadIdx.x;
     const unsigned long long* __restrict__ B = D.best[q % 3];
     uint32_t matched = 0, formed = 0;
     if (i < P.n && D.estate[i] == kEdgeLive) {
@@ -719,7 +798,7 @@ __global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int 
 // the rest for round q; `compact` appends the survivors to the live list
 // (wave ballot + mbcnt prefix, one atomic per wave).
 __global__ __launch_bounds__(256) void k_kill(const Params P, const Dev D, int q, int compact) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i < P.n) D.best[(q + 1) % 3][i] = kNoKey;
     bool live = false;
     if (i < P.n && D.estate[i] == kEdgeLive) {
@@ -817,7 +896,7 @@ __global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int 
                                                int last) {
     const unsigned long long s = D.stepv[sp];
     const int a = sweep_reaction(P, s, slot);
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (last && i == 0) *D.ke_fix = 0ull;
     uint32_t broke = 0;
     if (i < P.n) {
