@@ -517,3 +517,19 @@ def test_forms_balance_breaks_at_equilibrium():
     B = o.counters[0, 2] - c0[0, 2]
     assert F + B > 200
     assert abs(F - B) <= 4 * math.sqrt(F + B)
+
+
+def test_observable_definitions_on_hand_built_states():
+    """Bonded fraction and largest cluster on states whose answer is counted by hand."""
+    # 6 A (valence 1) and 3 B (valence 2); static chain 6-7-8 joins the three B
+    pts = [(k * 2.0, 0, 0) for k in range(9)]
+    types = [0] * 6 + [1] * 3
+    o = _frozen(pts, types, [1, 2], [(0, 1, dict(epsilon=1.0, p_on0=0.5))], L=40.0,
+                static=[(6, 7), (7, 8)])
+    # dynamic bonds: A0-B6, A1-B6, A2-B7
+    o.set_state(0, pts, np.zeros((9, 3)), [(0, 6), (1, 6), (2, 7)], [0, 0, 0])
+    ob = o.observables()
+    assert ob["n_bonds"].tolist() == [3]
+    assert ob["bonded_fraction"][0] == 3 / min(6 * 1, 3 * 2)      # 3 / 6
+    assert ob["largest_cluster_fraction"] == 6 / 9              # {0,1,2,6,7,8}
+    assert abs(ob["KE"]) == 0.0
