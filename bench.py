@@ -35,6 +35,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=20)
     p.add_argument("--profile-steps", type=int, default=2000)
+    p.add_argument("--skin", type=float, default=None, help="neighbour-list skin (default: the library's)")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="first run one plain device-to-device copy of this many MiB (the reference "
                         "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
@@ -120,7 +121,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    s = db.System.from_workload(w, device=0)
+    s = db.System.from_workload(w, device=0, skin=a.skin)
     s.step(a.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -285,8 +285,10 @@ class System:
         self.h = db_create(n, n_types, box_L, seed, device)
 
     @classmethod
-    def from_workload(cls, w, device=0, commit=True, kt_source=DB_KT_SETPOINT):
+    def from_workload(cls, w, device=0, commit=True, kt_source=DB_KT_SETPOINT, skin=None, max_neighbors=0):
         s = cls(w.n, len(w.types), w.L, w.seed, device)
+        if skin is not None or max_neighbors:
+            db_set_neighbor_list(s.h, -1.0 if skin is None else skin, max_neighbors)
         for t, (val, sig, eps, m) in enumerate(w.types):
             db_set_type(s.h, t, val, sig, eps, m)
         db_set_particles(s.h, w.pos, w.vel, w.type_id)
