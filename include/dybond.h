@@ -158,6 +158,15 @@ DB_API db_status db_set_cell_capacity(db_system* sys, uint32_t slots);
  * DB_EOVERFLOW. */
 DB_API db_status db_set_neighbor_list(db_system* sys, double skin, uint32_t max_neighbors);
 
+/* Schedule of the matching phase of every sweep (Sec. 2.3: greedy matching
+ * of the proposals in ascending priority key).  grid_rounds (1..8, default 1)
+ * local-minimum rounds run over the whole particle grid; the surviving
+ * proposals are then matched by one workgroup, in LDS when there are at most
+ * lds_limit of them (0..256, default 256), else in global memory.  Every
+ * schedule yields the same matching; this only moves work between launches.
+ * Before db_commit only (DB_ESTATE after); DB_EINVAL out of range. */
+DB_API db_status db_set_matching(db_system* sys, uint32_t grid_rounds, uint32_t lds_limit);
+
 /* Validate the configuration and close the rate parameters of every reaction
  * (Eq. epsilon, Eq. probs) without touching a GPU.  Errors: DB_EINVAL (bad
  * or missing parameter, under-determined or inconsistent rates, box smaller

@@ -172,7 +172,7 @@ struct Dev {
     uint8_t* claimed;      // site claimed in the running reaction
     uint32_t* live;        // compacted live proposals handed to the finishing pass
     uint32_t* live_count;  // [0] = length of `live`
-    unsigned long long* counters;   // nrx x 3: attempts, forms, breaks
+    unsigned long long* counters;   // nrx x 3 x kCtrSlots: attempts, forms, breaks
     unsigned long long* stepv;      // two step slots (parity of the step)
     unsigned long long* ke_fix;     // sum m v^2 in 2^-32 fixed point (kinetic kT)
     uint32_t* err;         // [0] flags, [1], [2] tags of the offending pair
@@ -249,12 +249,24 @@ __device__ __forceinline__ float mi_delta_f(float xi, float xj, const Params& P)
     return d;
 }
 
-// Wave-aggregated atomic add of a per-lane count to a 64-bit counter.
-__device__ __forceinline__ void wave_add(unsigned long long* dst, uint32_t v) {
-    unsigned long long sum = v;
+// Event counters (attempts, forms, breaks per reaction) are spread over
+// kCtrSlots addresses each; a wave adds its total to the slot of its wave
+// index, so that the waves of one launch do not queue on one address.  The
+// host sums the slots when it reads the counters.
+constexpr uint32_t kCtrSlots = 1024;
+enum : int { kCtrAttempt = 0, kCtrForm = 1, kCtrBreak = 2 };
+
+__device__ __forceinline__ unsigned long long* ctr_slot(const Dev& D, int a, int kind, uint32_t w) {
+    return &D.counters[((size_t)a * 3 + (size_t)kind) * kCtrSlots + (w & (kCtrSlots - 1))];
+}
+
+__device__ __forceinline__ void count_add(const Dev& D, int a, int kind, uint32_t v) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
-    if (__lane_id() == 0 && sum) atomicAdd(dst, sum);
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (__lane_id() == 0 && v) {
+        const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        atomicAdd(ctr_slot(D, a, kind, w), (unsigned long long)v);
+    }
 }
 
 }  // namespace dyb

@@ -22,7 +22,6 @@ using namespace dyb;
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMatchRounds = 3;        // full-grid matching rounds before the one-workgroup finish
 constexpr uint32_t kCellCapMin = 16;   // minimum particle slots per cell
 thread_local std::string g_create_error;
 
@@ -77,6 +76,8 @@ struct db_system {
     uint32_t cellcap_user = 0;             // 0 = automatic
     double skin = 0.4;                     // neighbour-list skin
     uint32_t nlmax_user = 0;               // neighbour-list slots per particle, 0 = automatic
+    uint32_t match_rounds = 1;             // full-grid matching rounds before the one-workgroup finish
+    uint32_t finish_lds = kFinishLds;      // largest live list the finish matches in LDS
     bool tags_dirty = false;               // device tag/rtag changed since the host mirrors were read
     bool sort_enabled = true;              // renumber particles in cell order every graph span
 };
@@ -418,7 +419,7 @@ void fill_params(db_system* s) {
             const double rl = need > 0.0 ? need + skin : 0.0;
             P.rl2[a * kMaxTypes + b] = (float)(rl * rl * (1.0 + 1e-4));
         }
-    P.tpp = 1;
+    P.tpp = 4;
     while (P.tpp < 32 && (uint64_t)s->n * P.tpp < 524288ull) P.tpp *= 2;
     P.disp2 = (float)std::max(0.0, (0.5 * skin - 1e-4) * (0.5 * skin - 1e-4));
     // neighbour slots: room for 2.5x the mean count of an ideal gas at this
@@ -556,19 +557,19 @@ void launch_sweep(db_system* s, int xcur, int sp) {
     for (int slot = 0; slot < (int)P.nrx; ++slot) {
         const unsigned gp = (unsigned)(((uint64_t)P.n * P.tpp + kBlock - 1) / kBlock);
         switch (P.tpp) {
-            case 1: LAUNCH(s, k_propose<1>, gp, kBlock, P, s->D, slot, xcur, sp); break;
-            case 2: LAUNCH(s, k_propose<2>, gp, kBlock, P, s->D, slot, xcur, sp); break;
             case 4: LAUNCH(s, k_propose<4>, gp, kBlock, P, s->D, slot, xcur, sp); break;
             case 8: LAUNCH(s, k_propose<8>, gp, kBlock, P, s->D, slot, xcur, sp); break;
             case 16: LAUNCH(s, k_propose<16>, gp, kBlock, P, s->D, slot, xcur, sp); break;
             default: LAUNCH(s, k_propose<32>, gp, kBlock, P, s->D, slot, xcur, sp); break;
         }
         LAUNCH(s, k_claim, g, kBlock, P, s->D, slot, 1, xcur, sp);
-        for (int q = 2; q <= kMatchRounds; ++q) {
-            LAUNCH(s, k_kill, g, kBlock, P, s->D, q, q == kMatchRounds ? 1 : 0);
+        const int R = (int)s->match_rounds;
+        for (int q = 2; q <= R; ++q) {
+            LAUNCH(s, k_kill, g, kBlock, P, s->D, q, 0);
             LAUNCH(s, k_claim, g, kBlock, P, s->D, slot, q, xcur, sp);
         }
-        LAUNCH(s, k_finish, 1, 1024, P, s->D, slot, (kMatchRounds + 1) % 3, xcur, sp);
+        LAUNCH(s, k_kill, g, kBlock, P, s->D, R + 1, 1);
+        LAUNCH(s, k_finish, 1, 1024, P, s->D, slot, (R + 1) % 3, xcur, sp, s->finish_lds);
         LAUNCH(s, k_break, g, kBlock, P, s->D, slot, xcur, sp, slot == (int)P.nrx - 1 ? 1 : 0);
     }
 }
@@ -601,8 +602,6 @@ void launch_step(db_system* s) {
     const int ake = (sweep && P.kt_kinetic) ? 1 : 0;
     const unsigned gs = (unsigned)(((uint64_t)P.n * P.tpp + kBlock - 1) / kBlock);
     switch (P.tpp) {
-        case 1: LAUNCH(s, k_step<1>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
-        case 2: LAUNCH(s, k_step<2>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
         case 4: LAUNCH(s, k_step<4>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
         case 8: LAUNCH(s, k_step<8>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
         case 16: LAUNCH(s, k_step<16>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
@@ -807,6 +806,16 @@ db_status db_set_neighbor_list(db_system* s, double skin, uint32_t max_neighbors
     return DB_OK;
 }
 
+db_status db_set_matching(db_system* s, uint32_t grid_rounds, uint32_t lds_limit) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "matching schedule is fixed after commit");
+    if (grid_rounds < 1 || grid_rounds > 8) return fail(s, DB_EINVAL, "grid_rounds must be in [1, 8]");
+    if (lds_limit > kFinishLds) return fail(s, DB_EINVAL, "lds_limit above %u", kFinishLds);
+    s->match_rounds = grid_rounds;
+    s->finish_lds = lds_limit;
+    return DB_OK;
+}
+
 db_status db_validate(db_system* s) {
     if (!s) return DB_EINVAL;
     return validate(s);
@@ -882,7 +891,7 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.claimed, n);
     DALLOC(s, D.live, n);
     DALLOC(s, D.live_count, 4);
-    DALLOC(s, D.counters, 3 * kMaxRx);
+    DALLOC(s, D.counters, (size_t)3 * kMaxRx * kCtrSlots);
     DALLOC(s, D.stepv, 2);
     DALLOC(s, D.ke_fix, 1);
     DALLOC(s, D.err, 4);
@@ -921,12 +930,13 @@ static db_status commit_impl(db_system* s) {
     HIPCHK(s, hipMemcpyAsync(D.mol, mol.data(), n * 4, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(D.tag, s->tag_h.data(), n * 4, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(D.rtag, s->rtag_h.data(), n * 4, hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, hipMemsetAsync(D.counters, 0, 3 * kMaxRx * sizeof(unsigned long long), s->stream));
+    HIPCHK(s, hipMemsetAsync(D.counters, 0, (size_t)3 * kMaxRx * kCtrSlots * sizeof(unsigned long long), s->stream));
     for (int l = 0; l < 3; ++l) HIPCHK(s, hipMemsetAsync(D.best[l], 0xFF, (size_t)n * 8, s->stream));
     HIPCHK(s, hipMemsetAsync(D.estate, 0, n, s->stream));
     HIPCHK(s, hipMemsetAsync(D.claimed, 0, n, s->stream));
     HIPCHK(s, hipMemsetAsync(D.prop, 0xFF, (size_t)n * 4, s->stream));
     HIPCHK(s, hipMemsetAsync(D.live_count, 0, 16, s->stream));
+    HIPCHK(s, hipMemsetAsync(D.nl, 0, (size_t)P.nlmax * n * 4, s->stream));
     s->step = 0;
     return upload_state(s, s->pos.data(), s->vel.data(), nullptr, nullptr, 0);
 }
@@ -1098,11 +1108,16 @@ db_status db_read_observables(db_system* s, db_observables* out) {
     HIPCHK(s, hipMemsetAsync(s->D.scan, 0, (size_t)s->n * 4, s->stream));
     LAUNCH(s, k_cc_size, g, kBlock, P, s->D);
     LAUNCH(s, k_cc_max, g, kBlock, P, s->D);
-    unsigned long long red[4 + kMaxRx], ctr[3 * kMaxRx];
+    unsigned long long red[4 + kMaxRx];
+    std::vector<unsigned long long> slots((size_t)3 * kMaxRx * kCtrSlots);
     HIPCHK(s, hipMemcpyAsync(red, s->D.red, sizeof red, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipMemcpyAsync(ctr, s->D.counters, sizeof ctr, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(slots.data(), s->D.counters, slots.size() * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s->stream));
     st = check_errors(s);
     if (st != DB_OK) return st;
+    unsigned long long ctr[3 * kMaxRx] = {};
+    for (size_t c = 0; c < (size_t)3 * kMaxRx; ++c)
+        for (uint32_t w = 0; w < kCtrSlots; ++w) ctr[c] += slots[c * kCtrSlots + w];
     std::memset(out, 0, sizeof *out);
     out->step = s->step;
     out->n_reactions = P.nrx;

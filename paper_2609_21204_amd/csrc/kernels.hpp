@@ -285,17 +285,18 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
 // Ornstein-Uhlenbeck velocity update with Philox Gaussians (O), half drift
 // (A), wrap into [-L/2, L/2), then write x_{t+1} and bin it into `lnext`.
 // Returns m v^2 in 2^-32 fixed point when accum_ke is set.
-__device__ __forceinline__ unsigned long long advance_particle(const Params& P, const Dev& D, int xin, int lnext,
-                                                               uint32_t i, float4 pi, uint32_t ti, Force3 F,
+template <class Tabs>
+__device__ __forceinline__ unsigned long long advance_particle(const Params& P, const Tabs& T, const Dev& D, int xin,
+                                                               int lnext, uint32_t i, float4 pi, uint32_t ti,
+                                                               Force3 F, float4 u, uint32_t tag,
                                                                unsigned long long s, int accum_ke, float4& po) {
-    const float4 u = D.u[i];
-    const float hm = P.h * P.inv_mass[ti];
+    const float hm = T.hm[ti];
     float vx = u.x + hm * F.x, vy = u.y + hm * F.y, vz = u.z + hm * F.z;
     vx += hm * F.x;
     vy += hm * F.y;
     vz += hm * F.z;
     float x = pi.x + P.h * vx, y = pi.y + P.h * vy, z = pi.z + P.h * vz;
-    const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), D.tag[i], 0u, P.seed, stream_k1(kThermo, 0, 0));
+    const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), tag, 0u, P.seed, stream_k1(kThermo, 0, 0));
     // Box-Muller: u1 in (0, 1], u2 in [0, 1)
     const float u1a = ((float)w.w0 + 1.0f) * 0x1.0p-32f;
     const float u1b = ((float)w.w2 + 1.0f) * 0x1.0p-32f;
@@ -304,7 +305,7 @@ __device__ __forceinline__ unsigned long long advance_particle(const Params& P, 
     const float ta = 6.28318530717958647692f * ((float)w.w1 * 0x1.0p-32f);
     const float sa = __sinf(ta), ca = __cosf(ta);
     const float cb = __cosf(6.28318530717958647692f * ((float)w.w3 * 0x1.0p-32f));
-    const float sd = P.noise_sd[ti];
+    const float sd = T.noise_sd[ti];
     vx = P.c1 * vx + sd * (ra * ca);
     vy = P.c1 * vy + sd * (ra * sa);
     vz = P.c1 * vz + sd * (rb * cb);
@@ -329,7 +330,7 @@ __device__ __forceinline__ unsigned long long advance_particle(const Params& P, 
     bin_particle(P, D, lnext, i, po);
     if (!accum_ke) return 0ull;
     const double v2 = ((double)vx * vx + (double)vy * vy) + (double)vz * vz;
-    return (unsigned long long)rint((double)P.mass[ti] * v2 * 4294967296.0);
+    return (unsigned long long)rint((double)T.mass[ti] * v2 * 4294967296.0);
 }
 
 constexpr int kTileThreads = 128;
@@ -482,63 +483,249 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
     if (over) atomicOr(&D.err[0], kErrNlist);
 }
 
-// One BAOAB step t -> s = t + 1.  TPP threads share a particle: each takes
-// every TPP-th entry of the particle's neighbour list and every TPP-th bond
-// slot, and the fixed-point partial sums are combined with wave shuffles (the
-// sum is exact, so the split does not change the result).  The first thread
-// of the group then integrates (advance_particle), bins x_{t+1} into
-// `lnext`, and tests the list: a particle farther than skin / 2 from where
-// its list was built sets the flag of step t+1, read by the k_nlist launched
-// right after.  Several threads per particle keep enough waves in flight to
-// hide the latency of the neighbour gathers when the system is small for the
-// chip.
+// Per-type and per-type-pair constants of the step, staged in LDS once per
+// workgroup.  The force loop indexes them with lane-varying types; read from
+// the kernel-argument block each lookup would be one more dependent memory
+// round trip per neighbour.
+struct StepTabs {
+    float rc2_pre[kMaxTypes * kMaxTypes], rc2_in[kMaxTypes * kMaxTypes];
+    float sig2f[kMaxTypes * kMaxTypes], eps24f[kMaxTypes * kMaxTypes];
+    PairTab pair[kMaxTypes * kMaxTypes];
+    double bk[kMaxBondTypes], br0[kMaxBondTypes], binvR02[kMaxBondTypes];
+    uint32_t bkind[kMaxBondTypes];
+    uint32_t rbt[kMaxRx];
+    float hm[kMaxTypes], noise_sd[kMaxTypes], mass[kMaxTypes];
+    uint32_t cap[kMaxTypes];
+};
+
+__device__ __forceinline__ void stage_tabs(const Params& P, const Dev& D, StepTabs& T, uint32_t tid) {
+    if (tid < kMaxTypes * kMaxTypes) {
+        T.rc2_pre[tid] = P.rc2_pre[tid];
+        T.rc2_in[tid] = P.rc2_in[tid];
+        T.sig2f[tid] = P.sig2f[tid];
+        T.eps24f[tid] = P.eps24f[tid];
+        T.pair[tid] = D.pair[tid];
+    } else if (tid < kMaxTypes * kMaxTypes + 8) {
+        const uint32_t k = tid - kMaxTypes * kMaxTypes;
+        T.bk[k] = P.bk[k];
+        T.br0[k] = P.br0[k];
+        T.binvR02[k] = P.binvR02[k];
+        T.bkind[k] = P.bkind[k];
+        T.rbt[k] = P.rbt[k];
+        T.hm[k] = P.h * P.inv_mass[k];
+        T.noise_sd[k] = P.noise_sd[k];
+        T.mass[k] = P.mass[k];
+        T.cap[k] = P.cap[k];
+    }
+}
+
+// WCA force on pi from neighbour pj (type in the w bits), constants from LDS.
+// When no component of x_j - x_i needs a periodic image, the FP32 difference
+// is the correctly rounded separation, and pairs inside 0.98 rc (where
+// 2 (sigma/r)^6 - 1 > 0.12, no cancellation) are evaluated in FP32.  Pairs
+// near the cutoff and pairs across the boundary are screened in FP32 and
+// evaluated in FP64 with the oracle's cutoff test r < 2^(1/6) sigma_ij.
+__device__ __forceinline__ void pair_force_tab(const Params& P, const StepTabs& T, uint32_t* err, float4 pi,
+                                               float4 pj, uint32_t ti, long long& fx, long long& fy,
+                                               long long& fz) {
+    const int pt = (int)ti * kMaxTypes + (int)type_of(pj);
+    const float rc2p = T.rc2_pre[pt];
+    float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    if (fabsf(dx) <= P.halfLf && fabsf(dy) <= P.halfLf && fabsf(dz) <= P.halfLf) {
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= rc2p) return;
+        if (r2 < T.rc2_in[pt]) {
+            const float ir2 = __builtin_amdgcn_rcpf(r2);
+            const float sr2 = T.sig2f[pt] * ir2;
+            const float sr6 = sr2 * sr2 * sr2;
+            const float f = T.eps24f[pt] * sr6 * (2.0f * sr6 - 1.0f) * ir2;
+            fx -= to_fix((double)(f * dx), err);
+            fy -= to_fix((double)(f * dy), err);
+            fz -= to_fix((double)(f * dz), err);
+            return;
+        }
+    } else {
+        dx = mi_delta_f(pi.x, pj.x, P);
+        dy = mi_delta_f(pi.y, pj.y, P);
+        dz = mi_delta_f(pi.z, pj.z, P);
+        if (dx * dx + dy * dy + dz * dz >= rc2p) return;
+    }
+    const PairTab& pp = T.pair[pt];
+    const double ex = mi_delta(pi.x, pj.x, P.L, P.invL);
+    const double ey = mi_delta(pi.y, pj.y, P.L, P.invL);
+    const double ez = mi_delta(pi.z, pj.z, P.L, P.invL);
+    double r2;
+    {
+#pragma clang fp contract(off)
+        r2 = (ex * ex + ey * ey) + ez * ez;
+    }
+    if (r2 >= pp.rc2_hi) return;
+    if (r2 > pp.rc2_lo && !(sqrt(r2) < pp.rc)) return;
+    const double ir2 = rcp64(r2);
+    const double sr2 = pp.sig2 * ir2;
+    const double sr6 = sr2 * sr2 * sr2;
+    const double f = pp.eps24 * sr6 * (2.0 * sr6 - 1.0) * ir2;
+    fx -= to_fix(f * ex, err);
+    fy -= to_fix(f * ey, err);
+    fz -= to_fix(f * ez, err);
+}
+
+// Bond force on site i from partner j (bond type bt), FP64 from the exact
+// minimum-image separation, constants from LDS.
+__device__ __forceinline__ void bond_force_tab(const Params& P, const StepTabs& T, const Dev& D, float4 pi,
+                                               float4 pj, uint32_t bt, uint32_t i, uint32_t j,
+                                               long long& fx, long long& fy, long long& fz) {
+    const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
+    const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
+    const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    double f;
+    if (T.bkind[bt] == 1u) {                      // FENE: F_i = k / (1 - r^2/R0^2) d
+        const double g = 1.0 - r2 * T.binvR02[bt];
+        if (!(g > 0.0)) {
+            if (atomicOr(&D.err[0], kErrFene) == 0u) {
+                D.err[1] = D.tag[i];
+                D.err[2] = D.tag[j];
+            }
+            return;
+        }
+        f = T.bk[bt] * rcp64(g);
+    } else {                                      // harmonic: F_i = k (r - r0) / r d
+        if (!(r2 > 0.0)) return;
+        const double ir = rsqrt64(r2);
+        f = T.bk[bt] * (r2 * ir - T.br0[bt]) * ir;
+    }
+    fx += to_fix(f * dx, D.err);
+    fy += to_fix(f * dy, D.err);
+    fz += to_fix(f * dz, D.err);
+}
+
+// One BAOAB step t -> s = t + 1 over 256 / TPP particles per workgroup.
+//
+// Force phase: TPP threads share a particle; each takes every TPP-th entry
+// of the particle's neighbour list and every TPP-th bond slot (static slots,
+// then dynamic ones).  All loads that depend only on the particle index (its
+// position, list length, the first Q list entries per thread, the bond
+// words) are issued together, then the neighbour and partner positions
+// together, so that a thread waits for about three memory round trips
+// instead of two per neighbour.  Each contribution is rounded to 2^-32 and
+// the partial sums are added into LDS as 64-bit integers (exact, so the
+// split and the order do not change the result).
+//
+// Integration phase: the first wave integrates the workgroup's particles,
+// one per lane (advance_particle), bins x_{t+1} into `lnext`, and tests the
+// list: a particle farther than skin / 2 from where its list was built sets
+// the flag of step t+1, read by the k_nlist launched right after.  The other
+// waves have retired by then, so no lane idles through the integration.
 //   xin = buffer of x_t, lnext = cell list receiving x_{t+1}, lclr = list
 //   cleared for the step after, sp = t mod 2, f3 = t mod 3.
 template <int TPP>
 __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
                                               int f3, int accum_ke) {
-    const uint32_t tg = xcd_block() * blockDim.x + threadIdx.x;
-    const uint32_t i = tg / TPP, lane = tg % TPP;
-    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    static_assert(TPP >= 4 && TPP <= 64, "one wave integrates the workgroup's particles");
+    constexpr int PPB = 256 / TPP;                       // particles per workgroup
+    constexpr int Q = 16 / TPP > 1 ? 16 / TPP : 1;      // list entries per thread issued up front
+    constexpr int BQ = 8 / TPP > 1 ? 8 / TPP : 1;       // bond slots per thread issued up front
+    __shared__ StepTabs T;
+    __shared__ unsigned long long fsum[3][PPB];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t base = xcd_block() * PPB;
+    const uint32_t i = base + tid / TPP, lane = tid % TPP;
+    const uint32_t gtid = blockIdx.x * blockDim.x + tid;
+    const size_t n = P.n;
+    const float4* __restrict__ X = D.x[xin];
+    const uint32_t nslot = P.stat_max + P.cap_max;
+    // loads that need only i
+    float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t m = 0;
+    uint32_t nb[Q], bw[BQ];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) nb[q] = 0u;
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) bw[q] = kEmpty;
+    if (i < P.n) {
+        pi = X[i];
+        m = D.nl_cnt[i];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const uint32_t k = lane + (uint32_t)q * TPP;
+            if (k < P.nlmax) nb[q] = D.nl[k * n + i];
+        }
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
+            const uint32_t b = lane + (uint32_t)q * TPP;
+            if (b < P.stat_max) bw[q] = D.stat[b * n + i];
+            else if (b < nslot) bw[q] = D.dyn[(b - P.stat_max) * n + i];
+        }
+    }
+    stage_tabs(P, D, T, tid);
+    if (tid < PPB) fsum[0][tid] = fsum[1][tid] = fsum[2][tid] = 0ull;
     const unsigned long long s = D.stepv[sp] + 1ull;
-    const int fnext = f3 == 2 ? 0 : f3 + 1;
     if (gtid == 0) {
         D.stepv[sp ^ 1] = s;
         D.rflag[f3] = 0u;               // consumed by the k_nlist of step t
     }
     for (uint32_t c = gtid; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
-    unsigned long long ke = 0ull;
+    __syncthreads();
     if (i < P.n) {
-        const size_t n = P.n;
-        const float4* __restrict__ X = D.x[xin];
-        const float4 pi = X[i];
         const uint32_t ti = type_of(pi);
-        long long fx = 0, fy = 0, fz = 0;
-        const uint32_t m = D.nl_cnt[i];
-        for (uint32_t k = lane; k < m; k += TPP) pair_force_list(P, D, pi, X[D.nl[k * n + i]], ti, fx, fy, fz);
-        for (uint32_t k = lane; k < P.stat_max; k += TPP) {
-            const uint32_t w = D.stat[k * n + i];
-            if (w != kEmpty) bond_force(P, D, pi, X[w & kIdxMask], w >> 24, i, w & kIdxMask, fx, fy, fz, nullptr);
-        }
-        const uint32_t cap = P.cap[ti];
-        for (uint32_t k = lane; k < cap; k += TPP) {
-            const uint32_t w = D.dyn[k * n + i];
-            if (w != kEmpty)
-                bond_force(P, D, pi, X[w & kIdxMask], P.rbt[(w >> 24) & 0x7Fu], i, w & kIdxMask, fx, fy, fz, nullptr);
+        // neighbour and partner positions
+        float4 pj[Q], pb[BQ];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const uint32_t k = lane + (uint32_t)q * TPP;
+            if (k < m) pj[q] = X[nb[q]];
         }
 #pragma unroll
-        for (int o = TPP / 2; o >= 1; o >>= 1) {
-            fx += __shfl_xor(fx, o, 64);
-            fy += __shfl_xor(fy, o, 64);
-            fz += __shfl_xor(fz, o, 64);
+        for (int q = 0; q < BQ; ++q)
+            if (bw[q] != kEmpty) pb[q] = X[bw[q] & kIdxMask];
+        long long fx = 0, fy = 0, fz = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const uint32_t k = lane + (uint32_t)q * TPP;
+            if (k < m) pair_force_tab(P, T, D.err, pi, pj[q], ti, fx, fy, fz);
         }
-        if (lane == 0) {
-            float4 po;
-            ke = advance_particle(P, D, xin, lnext, i, pi, ti, fix_to_force(D, fx, fy, fz), s, accum_ke, po);
-            const float4 r = D.xref[i];
-            const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
-            if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[fnext] = 1u;
+        for (uint32_t k = lane + (uint32_t)Q * TPP; k < m; k += TPP)
+            pair_force_tab(P, T, D.err, pi, X[D.nl[k * n + i]], ti, fx, fy, fz);
+        auto bond = [&](uint32_t b, uint32_t w, float4 pw) {
+            const uint32_t j = w & kIdxMask;
+            if (b < P.stat_max) bond_force_tab(P, T, D, pi, pw, w >> 24, i, j, fx, fy, fz);
+            else if (b - P.stat_max < T.cap[ti])
+                bond_force_tab(P, T, D, pi, pw, T.rbt[(w >> 24) & 0x7Fu], i, j, fx, fy, fz);
+        };
+#pragma unroll
+        for (int q = 0; q < BQ; ++q)
+            if (bw[q] != kEmpty) bond(lane + (uint32_t)q * TPP, bw[q], pb[q]);
+        for (uint32_t b = lane + (uint32_t)BQ * TPP; b < nslot; b += TPP) {
+            const uint32_t w = b < P.stat_max ? D.stat[b * n + i] : D.dyn[(b - P.stat_max) * n + i];
+            if (w != kEmpty) bond(b, w, X[w & kIdxMask]);
         }
+        atomicAdd(&fsum[0][tid / TPP], (unsigned long long)fx);
+        atomicAdd(&fsum[1][tid / TPP], (unsigned long long)fy);
+        atomicAdd(&fsum[2][tid / TPP], (unsigned long long)fz);
+    }
+    // the integrating wave fetches its particles' state before the barrier
+    const uint32_t i2 = base + tid;
+    const bool own = tid < (uint32_t)PPB && i2 < P.n;
+    float4 p2 = make_float4(0.f, 0.f, 0.f, 0.f), u2 = p2, r2 = p2;
+    uint32_t tag2 = 0;
+    if (own) {
+        p2 = X[i2];
+        u2 = D.u[i2];
+        r2 = D.xref[i2];
+        tag2 = D.tag[i2];
+    }
+    __syncthreads();
+    if (tid >= 64) return;
+    unsigned long long ke = 0ull;
+    if (own) {
+        const uint32_t t2 = type_of(p2);
+        const Force3 F = fix_to_force(D, (long long)fsum[0][tid], (long long)fsum[1][tid], (long long)fsum[2][tid]);
+        float4 po;
+        ke = advance_particle(P, T, D, xin, lnext, i2, p2, t2, F, u2, tag2, s, accum_ke, po);
+        const float4 r = r2;
+        const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
+        if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[f3 == 2 ? 0 : f3 + 1] = 1u;
     }
     if (accum_ke) {
         for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
@@ -635,9 +822,14 @@ __device__ __forceinline__ int sweep_reaction(const Params& P, unsigned long lon
 
 // Proposal phase (Sec. 2.3, Fig. sweep a) fused with the first matching round.
 // TPP threads share a proposer: each scans every TPP-th neighbour-list entry
-// and the group keeps the lexicographic minimum of (|r - r0|, tag).
+// and the group keeps the lexicographic minimum of (|r - r0|, tag).  As in
+// k_step, the loads that need only i (including the first Q list entries
+// per thread and the bond words) are issued together, then everything the
+// candidates need (position, occupancy, molecule, tag), so that a proposer
+// waits for about three memory round trips.
 template <int TPP>
 __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur, int sp) {
+    constexpr int Q = 16 / TPP > 1 ? 16 / TPP : 1;
     const unsigned long long s = D.stepv[sp];
     const int a = sweep_reaction(P, s, slot);
     const uint32_t tg = xcd_block() * blockDim.x + threadIdx.x;
@@ -650,50 +842,62 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
         D.estate[i] = kEdgeNone;
         D.prop[i] = -1;
     }
+    const size_t n = P.n;
     const float4* __restrict__ X = D.x[xcur];
     const float4 pi = X[i];
-    const uint32_t ti = type_of(pi);
-    const uint32_t ta = P.ra[a], tb = P.rb[a];
-    if (ti != ta && ti != tb) return;
-    if ((uint32_t)D.occ[i] >= P.cap[ti]) return;
-    const uint32_t want = ti == ta ? tb : ta;
-    // partners already bonded to i (any bond) are excluded
+    const uint32_t occ_i = D.occ[i];
+    const uint32_t m = D.nl_cnt[i];
+    uint32_t nb[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t k = lane + (uint32_t)q * TPP;
+        nb[q] = k < P.nlmax ? D.nl[k * n + i] : 0u;
+    }
+    // partners already bonded to i (any bond) are excluded; slots beyond the
+    // site's valence are empty
     uint32_t mine[kMaxValence + kMaxStatic];
 #pragma unroll
     for (int k = 0; k < kMaxValence; ++k)
-        mine[k] = (uint32_t)k < P.cap[ti] ? (D.dyn[(size_t)k * P.n + i] & kIdxMask) : kIdxMask;
+        mine[k] = (uint32_t)k < P.cap_max ? (D.dyn[(size_t)k * n + i] & kIdxMask) : kIdxMask;
 #pragma unroll
     for (int k = 0; k < kMaxStatic; ++k)
-        mine[kMaxValence + k] = (uint32_t)k < P.stat_max ? (D.stat[(size_t)k * P.n + i] & kIdxMask) : kIdxMask;
+        mine[kMaxValence + k] = (uint32_t)k < P.stat_max ? (D.stat[(size_t)k * n + i] & kIdxMask) : kIdxMask;
     const bool avoid = P.rself[a] != 0u;
     const uint32_t mol_i = avoid ? D.mol[i] : 0u;
+    const uint32_t tgi = D.tag[i];
+    const uint32_t ti = type_of(pi);
+    const uint32_t ta = P.ra[a], tb = P.rb[a];
+    if (ti != ta && ti != tb) return;
+    if (occ_i >= P.cap[ti]) return;
+    const uint32_t want = ti == ta ? tb : ta;
+    const uint32_t cap_want = P.cap[want];
     const double rmin = P.rmin[a], rmax = P.rmax[a], r0 = P.r0[a];
+    const float rmax2 = P.rmax2_pre[a], rmin2 = P.rmin2_pre[a];
     double best_score = 0.0;
     uint32_t best_tag = 0xFFFFFFFFu;
     int best_j = -1;
     // candidate j: partner type, free, not yet bonded to i, other molecule if
     // required, inside [r_min, r_max] (FP32 screen, then the exact FP64 r);
     // keep the smallest (|r - r0|, tag)
-    auto consider = [&](uint32_t j, float4 pj, uint32_t tj) {
-        if (tj != want) return;
-        if ((uint32_t)D.occ[j] >= P.cap[tj]) return;
+    auto consider = [&](uint32_t j, float4 pj, uint32_t occ_j, uint32_t mol_j, uint32_t tgj) {
+        if (type_of(pj) != want) return;
+        if (occ_j >= cap_want) return;
         bool bonded = false;
 #pragma unroll
         for (int q = 0; q < kMaxValence + kMaxStatic; ++q) bonded |= mine[q] == j;
         if (bonded) return;
-        if (avoid && D.mol[j] == mol_i) return;
+        if (avoid && mol_j == mol_i) return;
         const float fdx = mi_delta_f(pi.x, pj.x, P);
         const float fdy = mi_delta_f(pi.y, pj.y, P);
         const float fdz = mi_delta_f(pi.z, pj.z, P);
         const float fr2 = fdx * fdx + fdy * fdy + fdz * fdz;
-        if (fr2 > P.rmax2_pre[a] || fr2 < P.rmin2_pre[a]) return;
+        if (fr2 > rmax2 || fr2 < rmin2) return;
         const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
         const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
         const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
         const double r = norm3(dx, dy, dz);
         if (!(r >= rmin && r <= rmax)) return;
         const double score = fabs(r - r0);
-        const uint32_t tgj = D.tag[j];
         if (best_j < 0 || score < best_score || (score == best_score && tgj < best_tag)) {
             best_score = score;
             best_tag = tgj;
@@ -702,26 +906,37 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
     };
     // the neighbour list (rebuilt right after every step that needed it) holds
     // every pair within r_search >= r_max
-    const uint32_t m = D.nl_cnt[i];
-    const size_t n = P.n;
-    for (uint32_t k = lane; k < m; k += TPP) {
+    float4 pj[Q];
+    uint32_t oj[Q], mj[Q], gj[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t k = lane + (uint32_t)q * TPP;
+        if (k < m) {
+            pj[q] = X[nb[q]];
+            oj[q] = D.occ[nb[q]];
+            mj[q] = avoid ? D.mol[nb[q]] : 0u;
+            gj[q] = D.tag[nb[q]];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (lane + (uint32_t)q * TPP < m) consider(nb[q], pj[q], oj[q], mj[q], gj[q]);
+    for (uint32_t k = lane + (uint32_t)Q * TPP; k < m; k += TPP) {
         const uint32_t j = D.nl[k * n + i];
-        const float4 pj = X[j];
-        consider(j, pj, type_of(pj));
+        consider(j, X[j], D.occ[j], avoid ? D.mol[j] : 0u, D.tag[j]);
     }
 #pragma unroll
     for (int o = TPP / 2; o >= 1; o >>= 1) {
         const double os = __shfl_xor(best_score, o, 64);
         const uint32_t ot = __shfl_xor(best_tag, o, 64);
-        const int oj = __shfl_xor(best_j, o, 64);
-        if (oj >= 0 && (best_j < 0 || os < best_score || (os == best_score && ot < best_tag))) {
+        const int oj2 = __shfl_xor(best_j, o, 64);
+        if (oj2 >= 0 && (best_j < 0 || os < best_score || (os == best_score && ot < best_tag))) {
             best_score = os;
             best_tag = ot;
-            best_j = oj;
+            best_j = oj2;
         }
     }
     if (lane != 0 || best_j < 0) return;
-    const uint32_t tgi = D.tag[i];
     const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), tgi, 0u, P.seed, stream_k1(kMatch, a, 0));
     const uint64_t key = ((uint64_t)w.w0 << 32) | tgi;
     D.prop[i] = best_j;
@@ -732,18 +947,28 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
 }
 
 // Acceptance of a claimed pair (Eq. pon): returns true when the bond forms,
-// in which case both sites get the bond in their first free slot.
+// in which case both sites get the bond in their first free slot.  The
+// positions, tags and all slot words of both sites are loaded together.
 __device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a, unsigned long long s,
                                             const float4* __restrict__ X, uint32_t i, uint32_t j) {
+    const size_t n = P.n;
     const float4 pi = X[i], pj = X[j];
+    const uint32_t tgi = D.tag[i], tgj = D.tag[j];
+    uint32_t wi[kMaxValence], wj[kMaxValence];
+#pragma unroll
+    for (int k = 0; k < kMaxValence; ++k) {
+        wi[k] = (uint32_t)k < P.cap_max ? D.dyn[(size_t)k * n + i] : 0u;
+        wj[k] = (uint32_t)k < P.cap_max ? D.dyn[(size_t)k * n + j] : 0u;
+    }
+    const uint32_t occ_i = D.occ[i], occ_j = D.occ[j];
+    double kT = P.kT;
+    if (P.kt_kinetic) kT = (double)(*D.ke_fix) * kFixInv / (3.0 * (double)P.n);
     const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
     const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
     const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
     const double r = norm3(dx, dy, dz);
     const double d = r - P.r0[a];
     const double U = P.hk[a] * (d * d);
-    double kT = P.kT;
-    if (P.kt_kinetic) kT = (double)(*D.ke_fix) * kFixInv / (3.0 * (double)P.n);
     double prob;
     if (kT > 0.0) {
         prob = P.pon[a] * exp(-U / kT);
@@ -751,22 +976,21 @@ __device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a
     } else {
         prob = U <= 0.0 ? P.pon[a] : 0.0;
     }
-    const uint32_t tgi = D.tag[i], tgj = D.tag[j];
     const uint32_t lo = tgi < tgj ? tgi : tgj, hi = tgi < tgj ? tgj : tgi;
     const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), lo, hi, P.seed, stream_k1(kOn, a, 0));
     if (!(u53(w.w0, w.w1) < prob)) return false;
     const uint32_t ti = type_of(pi), tj = type_of(pj);
     const uint32_t tagbits = ((uint32_t)a << 24) | kNewBit;
-    for (uint32_t k = 0; k < P.cap[ti]; ++k) {
-        uint32_t* sl = &D.dyn[(size_t)k * P.n + i];
-        if (*sl == kEmpty) { *sl = j | tagbits; break; }
+    int fi = -1, fj = -1;
+#pragma unroll
+    for (int k = kMaxValence - 1; k >= 0; --k) {
+        if ((uint32_t)k < P.cap[ti] && wi[k] == kEmpty) fi = k;
+        if ((uint32_t)k < P.cap[tj] && wj[k] == kEmpty) fj = k;
     }
-    for (uint32_t k = 0; k < P.cap[tj]; ++k) {
-        uint32_t* sl = &D.dyn[(size_t)k * P.n + j];
-        if (*sl == kEmpty) { *sl = i | tagbits; break; }
-    }
-    D.occ[i] = (uint8_t)(D.occ[i] + 1);
-    D.occ[j] = (uint8_t)(D.occ[j] + 1);
+    if (fi >= 0) D.dyn[(size_t)fi * n + i] = j | tagbits;
+    if (fj >= 0) D.dyn[(size_t)fj * n + j] = i | tagbits;
+    D.occ[i] = (uint8_t)(occ_i + 1);
+    D.occ[j] = (uint8_t)(occ_j + 1);
     return true;
 }
 
@@ -779,10 +1003,13 @@ __global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int 
     const uint32_t i = xcd_block() * blockDim.x + threadIdx.x;
     const unsigned long long* __restrict__ B = D.best[q % 3];
     uint32_t matched = 0, formed = 0;
-    if (i < P.n && D.estate[i] == kEdgeLive) {
-        const uint32_t j = (uint32_t)D.prop[i];
+    if (i < P.n) {
+        const uint8_t st = D.estate[i];
+        const int32_t pj = D.prop[i];
         const unsigned long long key = D.key[i];
-        if (B[i] == key && B[j] == key) {
+        const unsigned long long bi = B[i];
+        if (st == kEdgeLive && bi == key && B[(uint32_t)pj] == key) {
+            const uint32_t j = (uint32_t)pj;
             matched = 1;
             D.estate[i] = kEdgeMatched;
             D.claimed[i] = 1;
@@ -790,8 +1017,8 @@ __global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int 
             formed = accept_pair(P, D, a, s, D.x[xcur], i, j) ? 1u : 0u;
         }
     }
-    wave_add(&D.counters[a * 3 + 0], matched);
-    wave_add(&D.counters[a * 3 + 1], formed);
+    count_add(D, a, kCtrAttempt, matched);
+    count_add(D, a, kCtrForm, formed);
 }
 
 // Kill round q: drop proposals that touch a claimed site, post the keys of
@@ -831,12 +1058,83 @@ __global__ __launch_bounds__(256) void k_kill(const Params P, const Dev D, int q
 // after at most `count` rounds.  Phases are separated by an agent-scope fence
 // and a barrier so that plain loads see the atomics and stores of the phase
 // before.
+constexpr uint32_t kFinishLds = 256;    // live proposals matched inside LDS by k_finish
+
+// k_finish for at most kFinishLds live proposals: the rounds run on copies in
+// LDS.  An edge is claimed when no live edge sharing one of its sites has a
+// smaller key; then live edges touching a claimed site die.  Claimed edges
+// are vertex-disjoint and acceptance depends only on the pair, so they are
+// all tried after the last round.
+__device__ __forceinline__ void finish_in_lds(const Params& P, const Dev& D, int a, unsigned long long s,
+                                              int xcur, unsigned long long* B, uint32_t count) {
+    __shared__ uint32_t ei[kFinishLds], ej[kFinishLds];
+    __shared__ unsigned long long ek[kFinishLds];
+    __shared__ uint8_t est[kFinishLds];
+    __shared__ int live_left;
+    const uint32_t t = threadIdx.x;
+    if (t < count) {
+        const uint32_t i = D.live[t];
+        const uint32_t j = (uint32_t)D.prop[i];
+        ei[t] = i;
+        ej[t] = j;
+        ek[t] = D.key[i];
+        est[t] = (D.estate[i] == kEdgeLive && !D.claimed[i] && !D.claimed[j]) ? kEdgeLive : kEdgeDead;
+    }
+    auto touches = [&](uint32_t e, uint32_t f) {
+        return ei[f] == ei[e] || ei[f] == ej[e] || ej[f] == ei[e] || ej[f] == ej[e];
+    };
+    for (uint32_t round = 0; round <= count; ++round) {
+        __syncthreads();                 // everyone has read live_left of the last round
+        if (t == 0) live_left = 0;
+        __syncthreads();
+        bool win = false;
+        if (t < count && est[t] == kEdgeLive) {
+            win = true;
+            for (uint32_t f = 0; f < count; ++f)
+                if (f != t && est[f] == kEdgeLive && ek[f] < ek[t] && touches(t, f)) { win = false; break; }
+        }
+        __syncthreads();
+        if (win) est[t] = kEdgeMatched;
+        __syncthreads();
+        if (t < count && est[t] == kEdgeLive) {
+            for (uint32_t f = 0; f < count; ++f)
+                if (est[f] == kEdgeMatched && touches(t, f)) { est[t] = kEdgeDead; break; }
+            if (est[t] == kEdgeLive) live_left = 1;
+        }
+        __syncthreads();
+        if (!live_left) break;
+    }
+    uint32_t att = 0, form = 0;
+    if (t < count) {
+        const uint32_t i = ei[t], j = ej[t];
+        B[i] = kNoKey;
+        B[j] = kNoKey;
+        if (est[t] == kEdgeMatched) {
+            D.estate[i] = kEdgeMatched;
+            D.claimed[i] = 1;
+            D.claimed[j] = 1;
+            att = 1;
+            form = accept_pair(P, D, a, s, D.x[xcur], i, j) ? 1u : 0u;
+        } else {
+            D.estate[i] = kEdgeDead;
+        }
+    }
+    if (t < kFinishLds) {
+        count_add(D, a, kCtrAttempt, att);
+        count_add(D, a, kCtrForm, form);
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, int slot, int buf,
-                                                 int xcur, int sp) {
+                                                 int xcur, int sp, uint32_t lds_limit) {
     const unsigned long long s = D.stepv[sp];
     const int a = sweep_reaction(P, s, slot);
     unsigned long long* B = D.best[buf];
     const uint32_t count = D.live_count[0];
+    if (count <= lds_limit && count <= kFinishLds) {
+        finish_in_lds(P, D, a, s, xcur, B, count);
+        return;
+    }
     __shared__ int any;
     __shared__ uint32_t n_att, n_form;
     if (threadIdx.x == 0) { n_att = 0; n_form = 0; }
@@ -883,15 +1181,16 @@ __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, in
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (n_att) atomicAdd(&D.counters[a * 3 + 0], (unsigned long long)n_att);
-        if (n_form) atomicAdd(&D.counters[a * 3 + 1], (unsigned long long)n_form);
+        if (n_att) atomicAdd(ctr_slot(D, a, kCtrAttempt, 0), (unsigned long long)n_att);
+        if (n_form) atomicAdd(ctr_slot(D, a, kCtrForm, 0), (unsigned long long)n_form);
     }
 }
 
 // Breaking phase (Sec. 2.3, Fig. sweep d): bonds of reaction a present at the
 // start of the sweep break with P0_off; bonds formed in this sweep only lose
 // their "new" mark.  Each site edits its own slots; both ends draw the same
-// number.  Also resets best[1] for the next reaction's proposal round.
+// number.  Also resets best[1] for the next reaction's proposal round.  All
+// slot words are loaded at once, then the partners' tags.
 __global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int slot, int xcur, int sp,
                                                int last) {
     const unsigned long long s = D.stepv[sp];
@@ -900,27 +1199,42 @@ __global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int 
     if (last && i == 0) *D.ke_fix = 0ull;
     uint32_t broke = 0;
     if (i < P.n) {
+        const size_t n = P.n;
         D.best[1][i] = kNoKey;
-        const uint32_t ti = type_of(D.x[xcur][i]);
-        const uint32_t tgi = D.tag[i];
-        uint32_t occ = D.occ[i];
-        for (uint32_t k = 0; k < P.cap[ti]; ++k) {
-            uint32_t* sl = &D.dyn[(size_t)k * P.n + i];
-            const uint32_t w = *sl;
-            if (w == kEmpty || ((w >> 24) & 0x7Fu) != (uint32_t)a) continue;
-            if (w & kNewBit) { *sl = w & ~kNewBit; continue; }
-            const uint32_t tgj = D.tag[w & kIdxMask];
-            const uint32_t lo = tgi < tgj ? tgi : tgj, hi = tgi < tgj ? tgj : tgi;
-            const Word4 r = philox((uint32_t)s, (uint32_t)(s >> 32), lo, hi, P.seed, stream_k1(kOff, a, 0));
-            if (u53(r.w0, r.w1) < P.poff[a]) {
-                *sl = kEmpty;
-                --occ;
-                if (tgi < tgj) ++broke;
-            }
+        uint32_t w[kMaxValence];
+        bool mine[kMaxValence];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kMaxValence; ++k) {
+            w[k] = (uint32_t)k < P.cap_max ? D.dyn[(size_t)k * n + i] : kEmpty;
+            mine[k] = w[k] != kEmpty && ((w[k] >> 24) & 0x7Fu) == (uint32_t)a;
+            any |= mine[k];
         }
-        D.occ[i] = (uint8_t)occ;
+        if (any) {
+            const uint32_t tgi = D.tag[i];
+            uint32_t tgj[kMaxValence];
+#pragma unroll
+            for (int k = 0; k < kMaxValence; ++k)
+                tgj[k] = (mine[k] && !(w[k] & kNewBit)) ? D.tag[w[k] & kIdxMask] : 0u;
+            uint32_t occ = D.occ[i];
+            const uint32_t occ0 = occ;
+#pragma unroll
+            for (int k = 0; k < kMaxValence; ++k) {
+                if (!mine[k]) continue;
+                uint32_t* sl = &D.dyn[(size_t)k * n + i];
+                if (w[k] & kNewBit) { *sl = w[k] & ~kNewBit; continue; }
+                const uint32_t lo = tgi < tgj[k] ? tgi : tgj[k], hi = tgi < tgj[k] ? tgj[k] : tgi;
+                const Word4 r = philox((uint32_t)s, (uint32_t)(s >> 32), lo, hi, P.seed, stream_k1(kOff, a, 0));
+                if (u53(r.w0, r.w1) < P.poff[a]) {
+                    *sl = kEmpty;
+                    --occ;
+                    if (tgi < tgj[k]) ++broke;
+                }
+            }
+            if (occ != occ0) D.occ[i] = (uint8_t)occ;
+        }
     }
-    wave_add(&D.counters[a * 3 + 2], broke);
+    count_add(D, a, kCtrBreak, broke);
 }
 
 // ------------------------------------------------------------ I/O kernels

@@ -67,6 +67,7 @@ _SIGS = {
     "db_set_integrator": (_I, [_P, _D, _D, _D, _U32, _I]),
     "db_set_cell_capacity": (_I, [_P, _U32]),
     "db_set_neighbor_list": (_I, [_P, _D, _U32]),
+    "db_set_matching": (_I, [_P, _U32, _U32]),
     "db_validate": (_I, [_P]),
     "db_get_reaction": (_I, [_P, _U32, ctypes.POINTER(ReactionDesc), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "db_commit": (_I, [_P]),
@@ -171,6 +172,10 @@ def db_set_cell_capacity(h, slots):
 
 def db_set_neighbor_list(h, skin=-1.0, max_neighbors=0):
     _check(h, load().db_set_neighbor_list(h, skin, max_neighbors))
+
+
+def db_set_matching(h, grid_rounds=1, lds_limit=256):
+    _check(h, load().db_set_matching(h, grid_rounds, lds_limit))
 
 
 def db_validate(h):
@@ -285,10 +290,13 @@ class System:
         self.h = db_create(n, n_types, box_L, seed, device)
 
     @classmethod
-    def from_workload(cls, w, device=0, commit=True, kt_source=DB_KT_SETPOINT, skin=None, max_neighbors=0):
+    def from_workload(cls, w, device=0, commit=True, kt_source=DB_KT_SETPOINT, skin=None, max_neighbors=0,
+                      matching=None):
         s = cls(w.n, len(w.types), w.L, w.seed, device)
         if skin is not None or max_neighbors:
             db_set_neighbor_list(s.h, -1.0 if skin is None else skin, max_neighbors)
+        if matching is not None:
+            db_set_matching(s.h, *matching)
         for t, (val, sig, eps, m) in enumerate(w.types):
             db_set_type(s.h, t, val, sig, eps, m)
         db_set_particles(s.h, w.pos, w.vel, w.type_id)

@@ -189,7 +189,7 @@ def test_kinetic_temperature_sweep_matches_oracle():
             assert_same_bonds(s, o, f"kinetic key {key}")
 
 
-def _dense_contention_system(seed, n=600, L=7.0):
+def _dense_contention_system(seed, n=600, L=7.0, matching=(1, 256)):
     """Random frozen system with heavy contention: many sites per partner,
     valences 1/2/4, a homotypic reaction, molecules with self-avoidance."""
     rng = np.random.default_rng(seed)
@@ -217,15 +217,19 @@ def _dense_contention_system(seed, n=600, L=7.0):
         o.add_reaction(Reaction(a, b, bt, rmin, rmax, self_avoid=sa, **rates))
     db.db_set_integrator(s.h, 0.005, 1.0, 1.0, 10)
     o.set_integrator(0.005, 1.0, 1.0, 10)
+    db.db_set_matching(s.h, *matching)
     db.db_commit(s.h)
     o.commit()
     return s, o
 
 
-def test_matching_under_heavy_contention():
+# (grid rounds, LDS finish limit): one grid round + LDS finish (default), the
+# finish in global memory, and several grid rounds before either finish
+@pytest.mark.parametrize("matching", [(1, 256), (1, 0), (3, 256), (2, 0)])
+def test_matching_under_heavy_contention(matching):
     for seed in (1, 2, 3):
-        log(f"case contention seed {seed}")
-        s, o = _dense_contention_system(seed)
+        log(f"case contention seed {seed} matching {matching}")
+        s, o = _dense_contention_system(seed, matching=matching)
         with s:
             for key in range(10, 260, 10):
                 s.sweep_frozen(key)
