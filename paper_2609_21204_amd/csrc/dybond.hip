@@ -317,21 +317,24 @@ uint32_t cell_capacity(const db_system* s, const Params& P, const float* pos3 = 
     return (c + 7u) & ~7u;
 }
 
-// Cells per neighbour-list tile: about 128 particles in the tile core at the
-// mean density, while the halo, (t + 2)^3 cells, holds at most 400 particles
-// on average (LDS room is 1024, for clusters denser than the mean); shrunk
-// until there are at least 512 tiles (enough workgroups to cover the chip) or
-// the tile is 2 cells wide; t <= 6 so (t + 2)^3 <= kTileMaxHalo.
+// Cells per neighbour-list tile (t x t x t): the widest tile whose halo,
+// (t + 2)^3 cells, fits the LDS tables (at most kTileMaxHalo cells, on
+// average at most 3/4 of kTileMaxEntries particles so that clusters denser
+// than the mean still fit) and that still leaves at least 512 tiles to cover
+// the chip; the narrowest admissible tile when no width gives 512.
 void choose_tiles(const db_system* s, Params& P) {
     const double lam = std::max((double)s->n / (double)P.ncell, 1e-6);
-    int t = (int)std::lround(std::cbrt(128.0 / lam));
-    t = std::max(1, std::min({t, 6, (int)P.nc}));
-    while (t > 1 && lam * (t + 2) * (t + 2) * (t + 2) > 400.0) --t;
-    auto ntiles = [&](int tt) {
+    auto ntiles_of = [&](int tt) {
         const long k = ((long)P.nc + tt - 1) / tt;
         return k * k * k;
     };
-    while (t > 2 && ntiles(t) < 512) --t;
+    int t = 1;
+    for (int tt = std::min(10, (int)P.nc); tt >= 1; --tt) {
+        const double halo = (double)(tt + 2) * (tt + 2) * (tt + 2);
+        if (halo > kTileMaxHalo || lam * halo > 0.75 * kTileMaxEntries) continue;
+        t = tt;
+        if (ntiles_of(tt) >= 512) break;
+    }
     for (int d = 0; d < 3; ++d) {
         P.tile[d] = (uint32_t)t;
         P.ntile[d] = (P.nc + (uint32_t)t - 1) / (uint32_t)t;
@@ -937,6 +940,7 @@ static db_status commit_impl(db_system* s) {
     HIPCHK(s, hipMemsetAsync(D.prop, 0xFF, (size_t)n * 4, s->stream));
     HIPCHK(s, hipMemsetAsync(D.live_count, 0, 16, s->stream));
     HIPCHK(s, hipMemsetAsync(D.nl, 0, (size_t)P.nlmax * n * 4, s->stream));
+    HIPCHK(s, hipMemsetAsync(D.nl_cnt, 0, (size_t)n * 4, s->stream));
     s->step = 0;
     return upload_state(s, s->pos.data(), s->vel.data(), nullptr, nullptr, 0);
 }

@@ -333,9 +333,12 @@ __device__ __forceinline__ unsigned long long advance_particle(const Params& P, 
     return (unsigned long long)rint((double)T.mass[ti] * v2 * 4294967296.0);
 }
 
-constexpr int kTileThreads = 128;
-constexpr int kTileMaxHalo = 512;       // halo cells of one tile, (t+2)^3 <= 512
-constexpr int kTileMaxEntries = 1024;   // particles staged in LDS per tile
+constexpr int kTileThreads = 512;
+constexpr int kTileMaxHalo = 1728;      // halo cells of one tile, (t+2)^3 <= 1728 (t <= 10)
+constexpr int kTileMaxEntries = 2048;   // particles staged in LDS per tile
+constexpr int kTileChunk = (kTileMaxHalo + kTileThreads - 1) / kTileThreads;   // halo cells per thread in the scan
+constexpr int kTileLoads = kTileMaxEntries / kTileThreads;                     // staged entries per thread
+constexpr int kTileMaxCore = 1024;      // core particles whose candidates are dealt out evenly
 
 // Workgroups are dealt round-robin to the 8 XCDs.  This remaps the workgroup
 // id so that each XCD gets a contiguous run of work items (particles are kept
@@ -349,10 +352,10 @@ __device__ __forceinline__ uint32_t xcd_block() {
 
 // Append j to the neighbour list of i when it lies within the list radius of
 // their type pair (only pairs that interact or can react are listed).
-__device__ __forceinline__ void nl_consider(const Params& P, const Dev& D, uint32_t i, float4 pi, float4 pj,
-                                            uint32_t& m) {
+__device__ __forceinline__ void nl_consider(const Params& P, const Dev& D, const float* rl2, uint32_t i, float4 pi,
+                                            float4 pj, uint32_t& m) {
     const float dx = mi_delta_f(pi.x, pj.x, P), dy = mi_delta_f(pi.y, pj.y, P), dz = mi_delta_f(pi.z, pj.z, P);
-    if (dx * dx + dy * dy + dz * dz < P.rl2[slot_type(pi) * kMaxTypes + slot_type(pj)]) {
+    if (dx * dx + dy * dy + dz * dz < rl2[slot_type(pi) * kMaxTypes + slot_type(pj)]) {
         if (m < P.nlmax) D.nl[(size_t)m * P.n + i] = slot_index(pj);
         ++m;
     }
@@ -364,17 +367,27 @@ __device__ __forceinline__ void nl_consider(const Params& P, const Dev& D, uint3
 // skin / 2 from where it was built.  Built from the cell list `lst` of those
 // positions, one workgroup per tile of cells: the cell counts of the tile and
 // its one-cell halo are scanned in LDS, the halo's particles (position +
-// index/type words) are staged in LDS with independent loads, and each thread
-// takes one particle of the tile core and visits its 27 neighbour cells as 9
-// contiguous LDS ranges.  Tiles whose halo holds more than kTileMaxEntries
-// particles read the same stencil from global memory.  Does nothing unless
-// the rebuild flag `f3` (set by k_step when a particle has moved by more than
-// skin / 2, or by a renumbering) is set.
+// index/type words) are staged in LDS (each thread issues its loads together,
+// locating its entries' cells by binary search over the scanned offsets),
+// and each thread takes one particle of the tile core and visits its 27
+// neighbour cells as 9 contiguous LDS ranges.  Tiles whose halo holds more
+// than kTileMaxEntries particles read the same stencil from global memory.
+// Does nothing unless the rebuild flag `f3` (set by k_step when a particle
+// has moved by more than skin / 2, or by a renumbering) is set; the grid is
+// a few hundred workgroups, so that the launch is cheap when nothing moved
+// that far.
 __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const Dev D, int lst, int f3) {
     if (D.rflag[f3] == 0u) return;
+    __shared__ float rl2[kMaxTypes * kMaxTypes];   // list radii, indexed by lane-varying type pairs
     __shared__ float4 ent[kTileMaxEntries];
     __shared__ uint32_t hoff[kTileMaxHalo + 1];
-    __shared__ uint32_t core[kTileMaxEntries];
+    __shared__ uint32_t hglob[kTileMaxHalo];       // global cell index of each halo cell
+    __shared__ uint16_t ecell[kTileMaxEntries];    // halo cell of each staged entry
+    __shared__ uint16_t core[kTileMaxEntries];     // staged entries that lie in the tile core
+    __shared__ uint8_t hshift[kTileMaxHalo];       // periodic image of each halo cell (2 bits per axis)
+    __shared__ uint32_t pstart[kTileMaxCore + 1];  // first candidate of each core particle
+    __shared__ uint32_t pcnt[kTileMaxCore];        // neighbours found so far
+    __shared__ uint16_t prow0[kTileMaxCore];       // first halo row of its 3 x 3 x 3 stencil
     __shared__ uint32_t ncore;
     const uint32_t tid = threadIdx.x;
     const uint32_t tile = xcd_block();
@@ -384,74 +397,245 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
     const int x0 = bx * (int)P.tile[0], y0 = by * (int)P.tile[1], z0 = bz * (int)P.tile[2];
     const int ex = min((int)P.tile[0], nc - x0), ey = min((int)P.tile[1], nc - y0), ez = min((int)P.tile[2], nc - z0);
     const int hx = ex + 2, hy = ey + 2, hz = ez + 2, nh = hx * hy * hz;
+    // halo cell h = (iz * hy + iy) * hx + ix; quotients of these small
+    // integers (< 2^11) are taken in FP32 and corrected, not with the
+    // integer division sequence
+    const float rx = 1.0f / (float)hx, rxy = 1.0f / (float)(hx * hy);
+    auto qdiv = [](int a, int b, float rb) {
+        int q = (int)((float)a * rb);
+        q += (q + 1) * b <= a ? 1 : 0;
+        q -= q * b > a ? 1 : 0;
+        return q;
+    };
+    auto split = [&](int h, int& ix, int& iy, int& iz) {
+        iz = qdiv(h, hx * hy, rxy);
+        const int r = h - iz * hx * hy;
+        iy = qdiv(r, hx, rx);
+        ix = r - iy * hx;
+    };
     auto hcell = [&](int h) {
-        const int ix = h % hx, iy = (h / hx) % hy, iz = h / (hx * hy);
+        int ix, iy, iz;
+        split(h, ix, iy, iz);
         return (wrapc(z0 - 1 + iz, nc) * nc + wrapc(y0 - 1 + iy, nc)) * nc + wrapc(x0 - 1 + ix, nc);
     };
+    // 1: the halo cell lies below cell 0 along that axis (its particles are
+    // shifted by -L), 2: above cell nc - 1 (+L); staged positions then form
+    // one continuous frame and plain differences are minimum images
+    auto hcode = [&](int h) {
+        int ix, iy, iz;
+        split(h, ix, iy, iz);
+        auto c1 = [&](int g) { return g < 0 ? 1u : (g >= nc ? 2u : 0u); };
+        return c1(x0 - 1 + ix) | (c1(y0 - 1 + iy) << 2) | (c1(z0 - 1 + iz) << 4);
+    };
     auto is_core = [&](int h) {
-        const int ix = h % hx, iy = (h / hx) % hy, iz = h / (hx * hy);
+        int ix, iy, iz;
+        split(h, ix, iy, iz);
         return ix >= 1 && ix <= ex && iy >= 1 && iy <= ey && iz >= 1 && iz <= ez;
     };
     const uint32_t* __restrict__ cnt = D.ccount[lst];
     const float4* __restrict__ cp = D.cpos[lst];
+    if (tid < kMaxTypes * kMaxTypes) rl2[tid] = P.rl2[tid];
+    if (tid == 0) ncore = 0;
     // halo counts -> exclusive offsets (each thread scans a contiguous chunk)
-    const int chunk = (nh + kTileThreads - 1) / kTileThreads;     // <= 4
-    uint32_t loc[4];
+    // (loads issued unconditionally from clamped cells, then masked, so that
+    // they are all in flight together)
+    const int chunk = (nh + kTileThreads - 1) / kTileThreads;
+    uint32_t loc[kTileChunk], gc[kTileChunk];
+#pragma unroll
+    for (int q = 0; q < kTileChunk; ++q) {
+        gc[q] = (uint32_t)hcell(min((int)tid * chunk + q, nh - 1));
+        loc[q] = cnt[gc[q]];
+    }
     uint32_t sum = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kTileChunk; ++q) {
         const int h = (int)tid * chunk + q;
-        uint32_t c = 0;
-        if (q < chunk && h < nh) {
-            c = cnt[hcell(h)];
-            c = c < P.cellcap ? c : P.cellcap;
-        }
+        const uint32_t c = (q < chunk && h < nh) ? (loc[q] < P.cellcap ? loc[q] : P.cellcap) : 0u;
         loc[q] = c;
         sum += c;
     }
     uint32_t total;
     uint32_t run = block_exclusive_scan(sum, &total);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kTileChunk; ++q) {
         const int h = (int)tid * chunk + q;
-        if (q < chunk && h < nh) hoff[h] = run;
+        if (q < chunk && h < nh) {
+            hoff[h] = run;
+            hglob[h] = gc[q];
+            hshift[h] = (uint8_t)hcode(h);
+        }
         run += loc[q];
     }
-    if (tid == 0) {
-        hoff[nh] = total;
-        ncore = 0;
-    }
+    if (tid == 0) hoff[nh] = total;
     __syncthreads();
     bool over = false;
-    if (total <= (uint32_t)kTileMaxEntries) {
-        for (int h = (int)tid; h < nh; h += kTileThreads) {
-            const uint32_t o = hoff[h], m = hoff[h + 1] - o;
-            const size_t base = (size_t)hcell(h) * P.cellcap;
-            for (uint32_t k = 0; k < m; ++k) ent[o + k] = cp[base + k];
-            if (m && is_core(h)) {
-                const uint32_t at = atomicAdd(&ncore, m);
-                for (uint32_t k = 0; k < m; ++k) core[at + k] = (o + k) | ((uint32_t)h << 16);
+    if (total == 0u) {
+        // nothing in this tile or its halo
+    } else if (total <= (uint32_t)kTileMaxEntries) {
+        // stage entry e: its cell h is the last one with hoff[h] <= e; loads
+        // from clamped entries are issued together, stores masked after
+        int hv[kTileLoads];
+        float4 v[kTileLoads];
+#pragma unroll
+        for (int q = 0; q < kTileLoads; ++q) {
+            const uint32_t e = min(tid + (uint32_t)q * kTileThreads, total - 1u);
+            int lo = 0;                       // hoff[0] = 0 <= e < hoff[nh]
+#pragma unroll
+            for (int step = 1024; step >= 1; step >>= 1)
+                if (lo + step < nh && hoff[lo + step] <= e) lo += step;
+            hv[q] = lo;
+            v[q] = cp[(size_t)hglob[lo] * P.cellcap + (e - hoff[lo])];
+        }
+        // threads past the end rewrite the last entry with its own value, so
+        // the stores need no branch (which would pull the loads after it)
+        auto shifted = [&](float x, uint32_t code) {
+            return code == 1u ? x - P.Lf : (code == 2u ? x + P.Lf : x);
+        };
+#pragma unroll
+        for (int q = 0; q < kTileLoads; ++q) {
+            const uint32_t e = min(tid + (uint32_t)q * kTileThreads, total - 1u);
+            const uint32_t code = hshift[hv[q]];
+            float4 w = v[q];
+            w.x = shifted(w.x, code & 3u);
+            w.y = shifted(w.y, (code >> 2) & 3u);
+            w.z = shifted(w.z, code >> 4);
+            ent[e] = w;
+            ecell[e] = (uint16_t)hv[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kTileLoads; ++q)
+            if (tid + (uint32_t)q * kTileThreads >= total) hv[q] = -1;
+        // core entries: wave ballot, one LDS atomic per wave
+#pragma unroll
+        for (int q = 0; q < kTileLoads; ++q) {
+            const uint32_t e = tid + (uint32_t)q * kTileThreads;
+            const bool c = hv[q] >= 0 && is_core(hv[q]);
+            const unsigned long long mask = __ballot(c);
+            if (mask) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                const int leader = __ffsll((long long)mask) - 1;
+                uint32_t base = 0;
+                if (__lane_id() == leader) base = atomicAdd(&ncore, (uint32_t)__popcll(mask));
+                base = __shfl(base, leader, 64);
+                if (c) core[base + rank] = (uint16_t)e;
             }
         }
         __syncthreads();
-        for (uint32_t q = tid; q < ncore; q += kTileThreads) {
-            const uint32_t e = core[q] & 0xFFFFu;
-            const int h = (int)(core[q] >> 16);
-            const float4 pi = ent[e];
-            const uint32_t i = slot_index(pi);
-            const int ix = h % hx, iy = (h / hx) % hy, iz = h / (hx * hy);
-            uint32_t m = 0;
-            for (int oz = -1; oz <= 1; ++oz) {
-                for (int oy = -1; oy <= 1; ++oy) {
-                    const int hr = ((iz + oz) * hy + (iy + oy)) * hx + (ix - 1);
-                    const uint32_t lo = hoff[hr], hi = hoff[hr + 3];
-                    for (uint32_t e2 = lo; e2 < hi; ++e2)
-                        if (e2 != e) nl_consider(P, D, i, pi, ent[e2], m);
+        if (ncore <= (uint32_t)kTileMaxCore) {
+            // candidates of each core particle: its 9 stencil rows of 3
+            // cells; they are numbered consecutively over the core particles
+            // and each thread takes an equal run of them
+            uint32_t sz[2] = {0u, 0u};
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const uint32_t p = 2u * tid + (uint32_t)k;
+                if (p < ncore) {
+                    int ix, iy, iz;
+                    split(ecell[core[p]], ix, iy, iz);
+                    const int hr0 = ((iz - 1) * hy + (iy - 1)) * hx + (ix - 1);
+                    uint32_t c = 0;
+#pragma unroll
+                    for (int r = 0; r < 9; ++r) {
+                        const int hr = hr0 + ((r / 3) * hy + (r % 3)) * hx;
+                        c += hoff[hr + 3] - hoff[hr];
+                    }
+                    prow0[p] = (uint16_t)hr0;
+                    pcnt[p] = 0u;
+                    sz[k] = c;
                 }
             }
-            over |= m > P.nlmax;
-            D.nl_cnt[i] = m < P.nlmax ? m : P.nlmax;
-            D.xref[i] = pi;
+            uint32_t ctot;
+            const uint32_t run0 = block_exclusive_scan(sz[0] + sz[1], &ctot);
+            if (2u * tid < ncore) pstart[2u * tid] = run0;
+            if (2u * tid + 1u < ncore) pstart[2u * tid + 1u] = run0 + sz[0];
+            if (tid == 0) pstart[ncore] = ctot;
+            __syncthreads();
+            const uint32_t per = (ctot + kTileThreads - 1) / kTileThreads;
+            uint32_t c = tid * per;
+            const uint32_t cend = min(c + per, ctot);
+            if (c < cend) {
+                uint32_t p = 0;                   // last p with pstart[p] <= c
+#pragma unroll
+                for (uint32_t step = kTileMaxCore / 2; step >= 1; step >>= 1)
+                    if (p + step < ncore && pstart[p + step] <= c) p += step;
+                uint32_t ep = core[p];
+                float4 pi = ent[ep];
+                uint32_t hr0 = prow0[p];
+                const float* rrow = rl2 + slot_type(pi) * kMaxTypes;
+                uint32_t o = c - pstart[p], r = 0, lo = hoff[hr0], hi = hoff[hr0 + 3];
+                while (o >= hi - lo) {
+                    o -= hi - lo;
+                    ++r;
+                    const uint32_t hr = hr0 + ((r / 3) * hy + (r % 3)) * hx;
+                    lo = hoff[hr];
+                    hi = hoff[hr + 3];
+                }
+                uint32_t e2 = lo + o;
+                for (;;) {
+                    if (e2 != ep) {
+                        const float4 q = ent[e2];
+                        const float dx = q.x - pi.x, dy = q.y - pi.y, dz = q.z - pi.z;
+                        if (dx * dx + dy * dy + dz * dz < rrow[slot_type(q)]) {
+                            const uint32_t k = atomicAdd(&pcnt[p], 1u);
+                            if (k < P.nlmax) D.nl[(size_t)k * P.n + slot_index(pi)] = slot_index(q);
+                        }
+                    }
+                    if (++c >= cend) break;
+                    ++e2;
+                    while (e2 >= hi) {            // next non-empty row, next particle
+                        if (++r == 9) {
+                            ++p;
+                            r = 0;
+                            ep = core[p];
+                            pi = ent[ep];
+                            hr0 = prow0[p];
+                            rrow = rl2 + slot_type(pi) * kMaxTypes;
+                        }
+                        const uint32_t hr = hr0 + ((r / 3) * hy + (r % 3)) * hx;
+                        lo = hoff[hr];
+                        hi = hoff[hr + 3];
+                        e2 = lo;
+                    }
+                }
+            }
+            __syncthreads();
+            for (uint32_t q = tid; q < ncore; q += kTileThreads) {
+                const float4 pi = ent[core[q]];
+                const uint32_t m = pcnt[q];
+                over |= m > P.nlmax;
+                D.nl_cnt[slot_index(pi)] = m < P.nlmax ? m : P.nlmax;
+                D.xref[slot_index(pi)] = pi;
+            }
+        } else {
+            for (uint32_t q = tid; q < ncore; q += kTileThreads) {
+                const uint32_t e = core[q];
+                const int h = ecell[e];
+                const float4 pi = ent[e];
+                const uint32_t i = slot_index(pi);
+                const float* rrow = rl2 + slot_type(pi) * kMaxTypes;
+                int ix, iy, iz;
+                split(h, ix, iy, iz);
+                uint32_t m = 0;
+                for (int oz = -1; oz <= 1; ++oz) {
+                    for (int oy = -1; oy <= 1; ++oy) {
+                        const int hr = ((iz + oz) * hy + (iy + oy)) * hx + (ix - 1);
+                        const uint32_t lo = hoff[hr], hi = hoff[hr + 3];
+                        for (uint32_t e2 = lo; e2 < hi; ++e2) {
+                            if (e2 == e) continue;
+                            const float4 q2 = ent[e2];
+                            const float dx = q2.x - pi.x, dy = q2.y - pi.y, dz = q2.z - pi.z;
+                            if (dx * dx + dy * dy + dz * dz < rrow[slot_type(q2)]) {
+                                if (m < P.nlmax) D.nl[(size_t)m * P.n + i] = slot_index(q2);
+                                ++m;
+                            }
+                        }
+                    }
+                }
+                over |= m > P.nlmax;
+                D.nl_cnt[i] = m < P.nlmax ? m : P.nlmax;
+                D.xref[i] = pi;
+            }
         }
     } else {
         for (int h = (int)tid; h < nh; h += kTileThreads) {
@@ -471,7 +655,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
                             mc = mc < P.cellcap ? mc : P.cellcap;
                             for (uint32_t kk = 0; kk < mc; ++kk) {
                                 const float4 pj = cp[(size_t)c * P.cellcap + kk];
-                                if (slot_index(pj) != i) nl_consider(P, D, i, pi, pj, m);
+                                if (slot_index(pj) != i) nl_consider(P, D, rl2, i, pi, pj, m);
                             }
                         }
                 over |= m > P.nlmax;
@@ -612,18 +796,20 @@ __device__ __forceinline__ void bond_force_tab(const Params& P, const StepTabs& 
 // the partial sums are added into LDS as 64-bit integers (exact, so the
 // split and the order do not change the result).
 //
-// Integration phase: the first wave integrates the workgroup's particles,
-// one per lane (advance_particle), bins x_{t+1} into `lnext`, and tests the
-// list: a particle farther than skin / 2 from where its list was built sets
-// the flag of step t+1, read by the k_nlist launched right after.  The other
-// waves have retired by then, so no lane idles through the integration.
+// Integration phase: the first 256 / TPP threads (whole waves) integrate the
+// workgroup's particles, one per thread (advance_particle), bin x_{t+1} into
+// `lnext`, and test the list: a particle farther than skin / 2 from where its
+// list was built sets the flag of step t+1, read by the k_nlist launched right
+// after.  The other waves have retired by then, so no lane idles through the
+// integration.
 //   xin = buffer of x_t, lnext = cell list receiving x_{t+1}, lclr = list
 //   cleared for the step after, sp = t mod 2, f3 = t mod 3.
 template <int TPP>
 __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
                                               int f3, int accum_ke) {
-    static_assert(TPP >= 4 && TPP <= 64, "one wave integrates the workgroup's particles");
+    static_assert(TPP >= 1 && TPP <= 64, "256 threads per workgroup");
     constexpr int PPB = 256 / TPP;                       // particles per workgroup
+    constexpr uint32_t kIntThreads = PPB > 64 ? PPB : 64;   // whole waves that integrate
     constexpr int Q = 16 / TPP > 1 ? 16 / TPP : 1;      // list entries per thread issued up front
     constexpr int BQ = 8 / TPP > 1 ? 8 / TPP : 1;       // bond slots per thread issued up front
     __shared__ StepTabs T;
@@ -671,14 +857,12 @@ __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int x
         const uint32_t ti = type_of(pi);
         // neighbour and partner positions
         float4 pj[Q], pb[BQ];
+        // (unconditional loads from clamped indices, so that all are in flight
+        // together; entries past the list and empty slots are masked below)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const uint32_t k = lane + (uint32_t)q * TPP;
-            if (k < m) pj[q] = X[nb[q]];
-        }
+        for (int q = 0; q < Q; ++q) pj[q] = X[lane + (uint32_t)q * TPP < m ? nb[q] : i];
 #pragma unroll
-        for (int q = 0; q < BQ; ++q)
-            if (bw[q] != kEmpty) pb[q] = X[bw[q] & kIdxMask];
+        for (int q = 0; q < BQ; ++q) pb[q] = X[bw[q] != kEmpty ? (bw[q] & kIdxMask) : i];
         long long fx = 0, fy = 0, fz = 0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -716,7 +900,7 @@ __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int x
         tag2 = D.tag[i2];
     }
     __syncthreads();
-    if (tid >= 64) return;
+    if (tid >= kIntThreads) return;
     unsigned long long ke = 0ull;
     if (own) {
         const uint32_t t2 = type_of(p2);
@@ -822,11 +1006,12 @@ __device__ __forceinline__ int sweep_reaction(const Params& P, unsigned long lon
 
 // Proposal phase (Sec. 2.3, Fig. sweep a) fused with the first matching round.
 // TPP threads share a proposer: each scans every TPP-th neighbour-list entry
-// and the group keeps the lexicographic minimum of (|r - r0|, tag).  As in
-// k_step, the loads that need only i (including the first Q list entries
-// per thread and the bond words) are issued together, then everything the
-// candidates need (position, occupancy, molecule, tag), so that a proposer
-// waits for about three memory round trips.
+// and the group keeps the lexicographic minimum of (|r - r0|, tag).  Sites
+// that cannot propose leave after loading their position and occupancy.  For
+// a proposer, the loads that need only i (the first Q list entries per
+// thread, the bond words) are issued together, then everything the
+// candidates need (position, occupancy, molecule, tag), so that it waits for
+// about four memory round trips.
 template <int TPP>
 __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur, int sp) {
     constexpr int Q = 16 / TPP > 1 ? 16 / TPP : 1;
@@ -844,8 +1029,13 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
     }
     const size_t n = P.n;
     const float4* __restrict__ X = D.x[xcur];
+    // sites that cannot propose (wrong type, full valence) leave after one load
     const float4 pi = X[i];
     const uint32_t occ_i = D.occ[i];
+    const uint32_t ti = type_of(pi);
+    const uint32_t ta = P.ra[a], tb = P.rb[a];
+    if (ti != ta && ti != tb) return;
+    if (occ_i >= P.cap[ti]) return;
     const uint32_t m = D.nl_cnt[i];
     uint32_t nb[Q];
 #pragma unroll
@@ -865,10 +1055,6 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
     const bool avoid = P.rself[a] != 0u;
     const uint32_t mol_i = avoid ? D.mol[i] : 0u;
     const uint32_t tgi = D.tag[i];
-    const uint32_t ti = type_of(pi);
-    const uint32_t ta = P.ra[a], tb = P.rb[a];
-    if (ti != ta && ti != tb) return;
-    if (occ_i >= P.cap[ti]) return;
     const uint32_t want = ti == ta ? tb : ta;
     const uint32_t cap_want = P.cap[want];
     const double rmin = P.rmin[a], rmax = P.rmax[a], r0 = P.r0[a];
@@ -910,13 +1096,11 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
     uint32_t oj[Q], mj[Q], gj[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const uint32_t k = lane + (uint32_t)q * TPP;
-        if (k < m) {
-            pj[q] = X[nb[q]];
-            oj[q] = D.occ[nb[q]];
-            mj[q] = avoid ? D.mol[nb[q]] : 0u;
-            gj[q] = D.tag[nb[q]];
-        }
+        const uint32_t j = lane + (uint32_t)q * TPP < m ? nb[q] : i;
+        pj[q] = X[j];
+        oj[q] = D.occ[j];
+        mj[q] = D.mol[j];
+        gj[q] = D.tag[j];
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q)
@@ -1003,12 +1187,11 @@ __global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int 
     const uint32_t i = xcd_block() * blockDim.x + threadIdx.x;
     const unsigned long long* __restrict__ B = D.best[q % 3];
     uint32_t matched = 0, formed = 0;
-    if (i < P.n) {
-        const uint8_t st = D.estate[i];
+    if (i < P.n && D.estate[i] == kEdgeLive) {
         const int32_t pj = D.prop[i];
         const unsigned long long key = D.key[i];
         const unsigned long long bi = B[i];
-        if (st == kEdgeLive && bi == key && B[(uint32_t)pj] == key) {
+        if (bi == key && B[(uint32_t)pj] == key) {
             const uint32_t j = (uint32_t)pj;
             matched = 1;
             D.estate[i] = kEdgeMatched;
@@ -1214,8 +1397,8 @@ __global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int 
             const uint32_t tgi = D.tag[i];
             uint32_t tgj[kMaxValence];
 #pragma unroll
-            for (int k = 0; k < kMaxValence; ++k)
-                tgj[k] = (mine[k] && !(w[k] & kNewBit)) ? D.tag[w[k] & kIdxMask] : 0u;
+            for (int k = 0; k < kMaxValence; ++k)     // unconditional (clamped) loads, issued together
+                tgj[k] = D.tag[mine[k] ? (w[k] & kIdxMask) : i];
             uint32_t occ = D.occ[i];
             const uint32_t occ0 = occ;
 #pragma unroll
