@@ -2,6 +2,7 @@
 // validation and rate closure (Eqs. epsilon and probs), device memory, kernel
 // launches of one time step and of the bonding sweep, graph replay of whole
 // sweep periods, and the read-out paths.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -123,11 +124,9 @@ struct TimerScope {
         };
         a = take();
         b = take();
-        (void)hipEventRecord(a, s->stream);
     }
     ~TimerScope() {
         if (!a) return;
-        (void)hipEventRecord(b, s->stream);
         std::string nm(name);
         const size_t lt = nm.find('<');      // k_step<4> is reported as k_step
         if (lt != std::string::npos) nm.resize(lt);
@@ -135,10 +134,17 @@ struct TimerScope {
     }
 };
 
+// With timing on, the launch carries a start and a stop event that the
+// runtime stamps when the kernel itself begins and ends (not when the stream
+// reaches the launch), so the per-kernel times are kernel execution times.
 #define LAUNCH(sys, kern, grid, block, ...)                                                      \
     do {                                                                                         \
         TimerScope ts_((sys), #kern);                                                            \
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (sys)->stream, __VA_ARGS__);       \
+        if (ts_.a)                                                                               \
+            hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (sys)->stream, ts_.a, ts_.b, \
+                                  0u, __VA_ARGS__);                                              \
+        else                                                                                     \
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (sys)->stream, __VA_ARGS__);   \
     } while (0)
 
 void flush_timing(db_system* s) {
