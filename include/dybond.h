@@ -190,6 +190,21 @@ DB_API db_status db_commit(db_system* sys);
  * leave the state invalid (DB_ESTATE) until db_set_state. */
 DB_API db_status db_step(db_system* sys, uint64_t n_steps);
 
+/* Advance `count` committed systems on one device by n_steps each (batched
+ * replicas of a parameter sweep): one launch per chunk of up to 2000 steps, one workgroup
+ * per system running all of its steps with workgroup barriers between the
+ * phases of a step, each system's own device state and buffers.  The result
+ * is bitwise identical to db_step(systems[k], n_steps) on every system (same
+ * forces, integrator, random streams and greedy matching); positions may be
+ * numbered differently inside the library, which db_read_* never show.
+ * Meant for many small systems (one workgroup each; a system of N particles
+ * takes about N / 512 particle updates per thread per step).  Synchronous.
+ * Errors: DB_EINVAL (null or empty list, a system listed twice, systems on
+ * different devices), DB_ESTATE (a system not committed or invalid),
+ * DB_EDEVICE; per-system errors as db_step (the first in list order is
+ * returned, each system's own message is in its db_last_error). */
+DB_API db_status db_step_batch(db_system* const* systems, uint32_t count, uint64_t n_steps);
+
 /* One bonding sweep at the current positions with step key `step_key`
  * (random streams keyed as for a sweep at that step); particles do not move,
  * velocities are unchanged, the step counter is unchanged. */

@@ -1,0 +1,260 @@
+// Batched systems: one workgroup runs every step of one system.
+//
+// Parameter sweeps run many small, independent systems (replicas) whose
+// steps are far too short to fill the chip one launch at a time: a step of a
+// 2000-particle system is a few microseconds of work behind several kernel
+// launches.  Here one launch advances a whole batch: workgroup b owns system
+// b and runs its n steps with workgroup barriers in place of kernel
+// boundaries, reading and writing the system's own device state (the same
+// arrays, rotating buffers and counters as db_step).  Every decision and sum
+// uses the same device functions as the per-step kernels (fixed-point
+// forces, Philox streams keyed by tag, the greedy matching in key order), so
+// a batched run is bitwise identical to db_step on each system.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace dyb {
+
+// One system of a batch as the kernel sees it.
+struct BatchItem {
+    Params P;
+    Dev D;
+    unsigned long long t0;   // step of the system at the start of the launch
+    int cur_x, cur_list;     // current position buffer and cell list
+    int pad0, pad1;
+};
+
+constexpr int kBatchThreads = 512;
+
+// Workgroup-scope atomic add on global memory: only the owning workgroup
+// touches a system's arrays during a batch launch, so the add can complete
+// in the local L2 instead of the device-coherent point.
+__device__ __forceinline__ uint32_t wg_atomic_add(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void wg_atomic_min64(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void bin_particle_wg(const Params& P, const Dev& D, int lst, uint32_t i, float4 p) {
+    const int c = (cell_coord(p.z, P) * (int)P.nc + cell_coord(p.y, P)) * (int)P.nc + cell_coord(p.x, P);
+    const uint32_t slot = wg_atomic_add(&D.ccount[lst][c], 1u);
+    if (slot < P.cellcap)
+        D.cpos[lst][(size_t)c * P.cellcap + slot] = make_float4(p.x, p.y, p.z, __uint_as_float(i | (type_of(p) << 24)));
+    else atomicOr(&D.err[0], kErrOverflow);
+}
+
+// Total force on particle i at X (list + bonds), one thread, in 2^-32 fixed
+// point.  List entries are taken 8 at a time with all their loads in flight.
+__device__ __forceinline__ Force3 force_site(const Params& P, const StepTabs& T, const Dev& D,
+                                             const float4* __restrict__ X, uint32_t i, float4 pi) {
+    const size_t n = P.n;
+    const uint32_t ti = type_of(pi);
+    long long fx = 0, fy = 0, fz = 0;
+    const uint32_t m = D.nl_cnt[i];
+    for (uint32_t k0 = 0; k0 < m; k0 += 8) {
+        uint32_t nb[8];
+        float4 pj[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) nb[q] = D.nl[(size_t)min(k0 + (uint32_t)q, m - 1u) * n + i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pj[q] = X[nb[q]];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k0 + (uint32_t)q < m) pair_force_tab(P, T, D.err, pi, pj[q], ti, fx, fy, fz);
+    }
+    for (uint32_t b = 0; b < P.stat_max; ++b) {
+        const uint32_t w = D.stat[(size_t)b * n + i];
+        if (w != kEmpty) bond_force_tab(P, T, D, pi, X[w & kIdxMask], w >> 24, i, w & kIdxMask, fx, fy, fz);
+    }
+    const uint32_t cap = T.cap[ti];
+    for (uint32_t b = 0; b < cap; ++b) {
+        const uint32_t w = D.dyn[(size_t)b * n + i];
+        if (w != kEmpty)
+            bond_force_tab(P, T, D, pi, X[w & kIdxMask], T.rbt[(w >> 24) & 0x7Fu], i, w & kIdxMask, fx, fy, fz);
+    }
+    return fix_to_force(D, fx, fy, fz);
+}
+
+// Neighbour list of particle i at X from cell list `lst` of the same
+// positions (one thread): counts of the 27 stencil cells, then the first
+// particle of every cell in groups of 9 with their loads in flight, then
+// the rest of the fuller cells.
+__device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T, const Dev& D, int lst,
+                                              uint32_t i, float4 pi) {
+    const uint32_t* __restrict__ cnt = D.ccount[lst];
+    const float4* __restrict__ cp = D.cpos[lst];
+    const int nc = (int)P.nc;
+    const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
+    const float* rrow = T.rl2 + type_of(pi) * kMaxTypes;
+    uint32_t m = 0;
+    auto consider = [&](float4 q) {
+        const uint32_t j = slot_index(q);
+        if (j == i) return;
+        const float dx = mi_delta_f(pi.x, q.x, P), dy = mi_delta_f(pi.y, q.y, P), dz = mi_delta_f(pi.z, q.z, P);
+        if (dx * dx + dy * dy + dz * dz < rrow[slot_type(q)]) {
+            if (m < P.nlmax) D.nl[(size_t)m * P.n + i] = j;
+            ++m;
+        }
+    };
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {                 // z layer oz = g - 1
+        uint32_t cell[9], cn[9];
+        float4 f[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int ox = q % 3 - 1, oy = q / 3 - 1;
+            cell[q] = (uint32_t)((wrapc(cz + g - 1, nc) * nc + wrapc(cy + oy, nc)) * nc + wrapc(cx + ox, nc));
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) cn[q] = min(cnt[cell[q]], P.cellcap);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = cp[(size_t)cell[q] * P.cellcap];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            if (cn[q] == 0u) continue;
+            consider(f[q]);
+            for (uint32_t e = 1; e < cn[q]; ++e) consider(cp[(size_t)cell[q] * P.cellcap + e]);
+        }
+    }
+    if (m > P.nlmax) atomicOr(&D.err[0], kErrNlist);
+    D.nl_cnt[i] = m < P.nlmax ? m : P.nlmax;
+    D.xref[i] = pi;
+}
+
+// n steps of system blockIdx.x.  Per step, as db_step: forces at x_t + BAOAB
+// + binning of x_{t+1} (the list is rebuilt right after a step that moved
+// some particle by more than skin / 2), and the bonding sweep at s = t + 1
+// when s is a multiple of the sweep period.  In the sweep, the rounds of the
+// greedy matching alternate two key buffers: post keys at both sites of each
+// live proposal, claim the proposals that hold the minimum at both sites
+// (and try them, Eq. pon), drop the proposals that touch a claimed site.
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_batch(const BatchItem* __restrict__ items, uint32_t nsteps) {
+    const BatchItem& B = items[blockIdx.x];
+    const Params& P = B.P;
+    const Dev& D = B.D;
+    __shared__ StepTabs T;
+    __shared__ uint32_t flag[3];          // rebuild flags, one per step mod 3
+    __shared__ uint32_t more[3];          // live proposals left, one per matching round mod 3
+    const uint32_t tid = threadIdx.x, bs = blockDim.x;
+    const uint32_t n = P.n;
+    stage_tabs(D, T, tid);
+    if (tid < 3) flag[tid] = more[tid] = 0u;
+    __syncthreads();
+    int xin = B.cur_x, lcur = B.cur_list;
+    for (uint32_t k = 0; k < nsteps; ++k) {
+        const unsigned long long t = B.t0 + k, s = t + 1;
+        const int lnext = lcur == 2 ? 0 : lcur + 1, lclr = lnext == 2 ? 0 : lnext + 1;
+        const bool sweep = P.nrx > 0 && (s % P.period) == 0;
+        const int ake = (sweep && P.kt_kinetic) ? 1 : 0;
+        if (tid == 0) flag[(k + 1) % 3] = 0u;   // last read two steps ago
+        for (uint32_t c = tid; c < P.ncell; c += bs) D.ccount[lclr][c] = 0u;
+        const float4* __restrict__ X = D.x[xin];
+        unsigned long long ke = 0ull;
+        for (uint32_t i = tid; i < n; i += bs) {
+            const float4 pi = X[i];
+            const float4 ui = D.u[i];
+            const uint32_t tg = D.tag[i];
+            const float4 r = D.xref[i];
+            const Force3 F = force_site(P, T, D, X, i, pi);
+            float4 po;
+            ke += advance_particle(P, T, D, xin, i, pi, type_of(pi), F, ui, tg, s, ake, po);
+            bin_particle_wg(P, D, lnext, i, po);
+            const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
+            if (dx * dx + dy * dy + dz * dz > P.disp2) flag[k % 3] = 1u;
+        }
+        if (ake) {
+            for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
+            if (__lane_id() == 0 && ke)
+                __hip_atomic_fetch_add(D.ke_fix, ke, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+        xin ^= 1;
+        lcur = lnext;
+        if (flag[k % 3]) {
+            const float4* __restrict__ Xn = D.x[xin];
+            for (uint32_t i = tid; i < n; i += bs) nl_build_site(P, T, D, lcur, i, Xn[i]);
+            __syncthreads();
+        }
+        if (!sweep) continue;
+        const float4* __restrict__ Xs = D.x[xin];
+        unsigned long long* const B0 = D.best[0];
+        unsigned long long* const B1 = D.best[1];
+        for (int slot = 0; slot < (int)P.nrx; ++slot) {
+            const int a = reaction_at(P.seed, s, (int)P.nrx, slot);
+            for (uint32_t i = tid; i < n; i += bs) {
+                B0[i] = kNoKey;
+                B1[i] = kNoKey;
+                D.claimed[i] = 0;
+                D.estate[i] = kEdgeNone;
+                D.prop[i] = -1;
+            }
+            if (tid < 3) more[tid] = 0u;
+            __syncthreads();
+            for (uint32_t i = tid; i < n; i += bs) {
+                uint32_t tgi = 0;
+                const int j = propose_site<1, 4>(P, D, a, Xs, i, 0u, tgi);
+                if (j < 0) continue;
+                const unsigned long long key = match_key(P, a, s, tgi);
+                D.prop[i] = j;
+                D.key[i] = key;
+                D.estate[i] = kEdgeLive;
+                wg_atomic_min64(&B0[i], key);
+                wg_atomic_min64(&B0[(uint32_t)j], key);
+            }
+            uint32_t att = 0, form = 0;
+            for (uint32_t r = 0;; ++r) {
+                unsigned long long* const Bc = (r & 1u) ? B1 : B0;
+                unsigned long long* const Bn = (r & 1u) ? B0 : B1;
+                if (tid == 0) more[(r + 1) % 3] = 0u;
+                __syncthreads();
+                for (uint32_t i = tid; i < n; i += bs) {
+                    if (D.estate[i] != kEdgeLive) continue;
+                    const uint32_t j = (uint32_t)D.prop[i];
+                    const unsigned long long key = D.key[i];
+                    if (Bc[i] == key && Bc[j] == key) {
+                        D.estate[i] = kEdgeMatched;
+                        D.claimed[i] = 1;
+                        D.claimed[j] = 1;
+                        ++att;
+                        form += accept_pair(P, D, a, s, Xs, i, j) ? 1u : 0u;
+                    }
+                }
+                __syncthreads();
+                for (uint32_t i = tid; i < n; i += bs) {
+                    Bc[i] = kNoKey;
+                    if (D.estate[i] != kEdgeLive) continue;
+                    const uint32_t j = (uint32_t)D.prop[i];
+                    if (D.claimed[i] || D.claimed[j]) {
+                        D.estate[i] = kEdgeDead;
+                    } else {
+                        const unsigned long long key = D.key[i];
+                        wg_atomic_min64(&Bn[i], key);
+                        wg_atomic_min64(&Bn[j], key);
+                        more[r % 3] = 1u;
+                    }
+                }
+                __syncthreads();
+                if (!more[r % 3]) break;
+            }
+            count_add(D, a, kCtrAttempt, att);
+            count_add(D, a, kCtrForm, form);
+            uint32_t broke = 0;
+            for (uint32_t i = tid; i < n; i += bs) broke += break_site(P, D, a, s, i);
+            count_add(D, a, kCtrBreak, broke);
+            __syncthreads();
+        }
+        if (tid == 0) *D.ke_fix = 0ull;
+    }
+    // hand the state back in the form db_step leaves it: step slots, no list
+    // rebuild pending, round-1 key buffer clear
+    for (uint32_t i = tid; i < n; i += bs) D.best[1][i] = kNoKey;
+    if (tid == 0) {
+        D.stepv[0] = D.stepv[1] = B.t0 + nsteps;
+        D.rflag[0] = D.rflag[1] = D.rflag[2] = 0u;
+    }
+}
+
+}  // namespace dyb

@@ -152,8 +152,26 @@ struct PairTab {
     double pad0, pad1;
 };
 
+// Per-type and per-type-pair constants of the step kernel, built on the host
+// at commit and staged in LDS by every workgroup: the force loop indexes them
+// with lane-varying types, which from the kernel-argument block would be one
+// more dependent memory round trip per neighbour.
+struct alignas(16) StepTabs {
+    float rc2_pre[kMaxTypes * kMaxTypes], rc2_in[kMaxTypes * kMaxTypes];
+    float sig2f[kMaxTypes * kMaxTypes], eps24f[kMaxTypes * kMaxTypes];
+    float rl2[kMaxTypes * kMaxTypes];   // neighbour-list radius^2 of the type pair
+    PairTab pair[kMaxTypes * kMaxTypes];
+    double bk[kMaxBondTypes], br0[kMaxBondTypes], binvR02[kMaxBondTypes];
+    uint32_t bkind[kMaxBondTypes];
+    uint32_t rbt[kMaxRx];
+    float hm[kMaxTypes], noise_sd[kMaxTypes], mass[kMaxTypes];   // hm = (dt / 2) / m
+    uint32_t cap[kMaxTypes];
+};
+static_assert(sizeof(StepTabs) % 16 == 0, "staged in 16-byte words");
+
 struct Dev {
     const PairTab* pair;   // kMaxTypes x kMaxTypes
+    const StepTabs* tabs;  // the same constants for k_step
     float4* x[2];          // positions (xyz) + type bits (w), double-buffered
     float4* u;             // velocity before the closing half kick of the last step
     int32_t* img;          // image counters, 3 x n

@@ -17,6 +17,7 @@
 
 #include "../../include/dybond.h"
 #include "kernels.hpp"
+#include "batch.hpp"
 
 using namespace dyb;
 
@@ -878,6 +879,32 @@ static db_status commit_impl(db_system* s) {
         HIPCHK(s, hipMemcpyAsync(pt, s->pair_h.data(), s->pair_h.size() * sizeof(PairTab),
                                  hipMemcpyHostToDevice, s->stream));
         D.pair = pt;
+        // step tables: the same numbers k_step would read from the parameter
+        // block, laid out for one 16-byte copy per thread into LDS
+        StepTabs th{};
+        for (int k = 0; k < kMaxTypes * kMaxTypes; ++k) {
+            th.rc2_pre[k] = P.rc2_pre[k];
+            th.rc2_in[k] = P.rc2_in[k];
+            th.sig2f[k] = P.sig2f[k];
+            th.eps24f[k] = P.eps24f[k];
+            th.rl2[k] = P.rl2[k];
+            th.pair[k] = s->pair_h[k];
+        }
+        for (int k = 0; k < 8; ++k) {
+            th.bk[k] = P.bk[k];
+            th.br0[k] = P.br0[k];
+            th.binvR02[k] = P.binvR02[k];
+            th.bkind[k] = P.bkind[k];
+            th.rbt[k] = P.rbt[k];
+            th.hm[k] = P.h * P.inv_mass[k];
+            th.noise_sd[k] = P.noise_sd[k];
+            th.mass[k] = P.mass[k];
+            th.cap[k] = P.cap[k];
+        }
+        StepTabs* tt = nullptr;
+        DALLOC(s, tt, 1);
+        HIPCHK(s, hipMemcpy(tt, &th, sizeof th, hipMemcpyHostToDevice));
+        D.tabs = tt;
     }
     DALLOC(s, D.x[0], n);
     DALLOC(s, D.x[1], n);
@@ -958,6 +985,68 @@ db_status db_step(db_system* s, uint64_t nsteps) {
     st = run_steps(s, nsteps);
     if (st != DB_OK) return st;
     return check_errors(s);
+}
+
+db_status db_step_batch(db_system* const* systems, uint32_t count, uint64_t nsteps) {
+    if (!systems || count == 0) return DB_EINVAL;
+    for (uint32_t k = 0; k < count; ++k) {
+        db_status st = ready(systems[k]);
+        if (st != DB_OK) return st;
+        for (uint32_t q = 0; q < k; ++q)
+            if (systems[q] == systems[k]) return fail(systems[k], DB_EINVAL, "system listed twice in a batch");
+        if (systems[k]->device != systems[0]->device)
+            return fail(systems[k], DB_EINVAL, "batched systems must share one device");
+    }
+    db_system* s0 = systems[0];
+    HIPCHK(s0, hipSetDevice(s0->device));
+    for (uint32_t k = 0; k < count; ++k) HIPCHK(systems[k], hipStreamSynchronize(systems[k]->stream));
+    // largest systems first: their workgroups start in the first wave
+    std::vector<uint32_t> order(count);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return systems[a]->n > systems[b]->n; });
+    std::vector<BatchItem> items(count);
+    BatchItem* d_items = nullptr;
+    HIPCHK(s0, hipMalloc(&d_items, count * sizeof(BatchItem)));
+    constexpr uint64_t kChunk = 2000;     // steps per launch
+    db_status st = DB_OK;
+    for (uint64_t done = 0; done < nsteps && st == DB_OK;) {
+        const uint32_t chunk = (uint32_t)std::min<uint64_t>(kChunk, nsteps - done);
+        for (uint32_t k = 0; k < count; ++k) {
+            const db_system* s = systems[order[k]];
+            BatchItem& it = items[k];
+            it.P = s->P;
+            it.D = s->D;
+            it.t0 = s->step;
+            it.cur_x = s->cur_x;
+            it.cur_list = s->cur_list;
+            it.pad0 = it.pad1 = 0;
+        }
+        if (hipMemcpyAsync(d_items, items.data(), count * sizeof(BatchItem), hipMemcpyHostToDevice, s0->stream) !=
+            hipSuccess) { st = fail(s0, DB_EDEVICE, "batch upload failed"); break; }
+        LAUNCH(s0, k_batch, count, kBatchThreads, d_items, chunk);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s0->stream) != hipSuccess) {
+            st = fail(s0, DB_EDEVICE, "batch launch failed");
+            break;
+        }
+        for (uint32_t k = 0; k < count; ++k) {
+            db_system* s = systems[k];
+            s->step += chunk;
+            s->cur_x ^= (int)(chunk & 1u);
+            s->cur_list = (int)((s->cur_list + chunk) % 3);
+        }
+        done += chunk;
+    }
+    (void)hipFree(d_items);
+    if (st != DB_OK) {
+        for (uint32_t k = 0; k < count; ++k) systems[k]->dead = true;
+        return st;
+    }
+    flush_timing(s0);
+    for (uint32_t k = 0; k < count; ++k) {
+        const db_status e = check_errors(systems[k]);
+        if (e != DB_OK && st == DB_OK) st = e;
+    }
+    return st;
 }
 
 db_status db_sweep_frozen(db_system* s, uint64_t step_key) {

@@ -31,6 +31,7 @@ __device__ __forceinline__ void bond_force(const Params& P, const Dev& D, float4
                                            uint32_t bt, uint32_t i, uint32_t j,
                                            long long& fx, long long& fy, long long& fz,
                                            double* e) {
+#pragma clang fp contract(off)
     const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
     const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
     const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
@@ -65,6 +66,7 @@ __device__ __forceinline__ void bond_force(const Params& P, const Dev& D, float4
 // cutoff it is decided on r^2, within 1e-14 of it on the correctly rounded r.
 __device__ __forceinline__ void pair_force(const Params& P, const Dev& D, float4 pi, float4 pj, uint32_t ti,
                                            long long& fx, long long& fy, long long& fz, double* e) {
+#pragma clang fp contract(off)
     const int pt = (int)ti * kMaxTypes + (int)slot_type(pj);
     const float fdx = mi_delta_f(pi.x, pj.x, P);
     const float fdy = mi_delta_f(pi.y, pj.y, P);
@@ -283,19 +285,23 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
 // Rest of one BAOAB step for particle i once its force F at x_t is known:
 // closing half kick of step t-1 (B), opening half kick (B), half drift (A),
 // Ornstein-Uhlenbeck velocity update with Philox Gaussians (O), half drift
-// (A), wrap into [-L/2, L/2), then write x_{t+1} and bin it into `lnext`.
-// Returns m v^2 in 2^-32 fixed point when accum_ke is set.
+// (A), wrap into [-L/2, L/2), then write x_{t+1} (returned in po; the caller
+// bins it).  Returns m v^2 in 2^-32 fixed point when accum_ke is set.
 template <class Tabs>
 __device__ __forceinline__ unsigned long long advance_particle(const Params& P, const Tabs& T, const Dev& D, int xin,
-                                                               int lnext, uint32_t i, float4 pi, uint32_t ti,
+                                                               uint32_t i, float4 pi, uint32_t ti,
                                                                Force3 F, float4 u, uint32_t tag,
                                                                unsigned long long s, int accum_ke, float4& po) {
+    // The order of every rounding is written out (explicit fmaf, no implicit
+    // contraction), so that the step gives the same bits in every kernel that
+    // inlines it.
+#pragma clang fp contract(off)
     const float hm = T.hm[ti];
-    float vx = u.x + hm * F.x, vy = u.y + hm * F.y, vz = u.z + hm * F.z;
-    vx += hm * F.x;
-    vy += hm * F.y;
-    vz += hm * F.z;
-    float x = pi.x + P.h * vx, y = pi.y + P.h * vy, z = pi.z + P.h * vz;
+    float vx = fmaf(hm, F.x, u.x), vy = fmaf(hm, F.y, u.y), vz = fmaf(hm, F.z, u.z);
+    vx = fmaf(hm, F.x, vx);
+    vy = fmaf(hm, F.y, vy);
+    vz = fmaf(hm, F.z, vz);
+    float x = fmaf(P.h, vx, pi.x), y = fmaf(P.h, vy, pi.y), z = fmaf(P.h, vz, pi.z);
     const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), tag, 0u, P.seed, stream_k1(kThermo, 0, 0));
     // Box-Muller: u1 in (0, 1], u2 in [0, 1)
     const float u1a = ((float)w.w0 + 1.0f) * 0x1.0p-32f;
@@ -306,12 +312,12 @@ __device__ __forceinline__ unsigned long long advance_particle(const Params& P, 
     const float sa = __sinf(ta), ca = __cosf(ta);
     const float cb = __cosf(6.28318530717958647692f * ((float)w.w3 * 0x1.0p-32f));
     const float sd = T.noise_sd[ti];
-    vx = P.c1 * vx + sd * (ra * ca);
-    vy = P.c1 * vy + sd * (ra * sa);
-    vz = P.c1 * vz + sd * (rb * cb);
-    x += P.h * vx;
-    y += P.h * vy;
-    z += P.h * vz;
+    vx = fmaf(P.c1, vx, sd * (ra * ca));
+    vy = fmaf(P.c1, vy, sd * (ra * sa));
+    vz = fmaf(P.c1, vz, sd * (rb * cb));
+    x = fmaf(P.h, vx, x);
+    y = fmaf(P.h, vy, y);
+    z = fmaf(P.h, vz, z);
     int ix = 0, iy = 0, iz = 0;
     if (x < -P.halfLf) { x += P.Lf; --ix; }
     if (x >= P.halfLf) { x -= P.Lf; ++ix; }
@@ -327,7 +333,6 @@ __device__ __forceinline__ unsigned long long advance_particle(const Params& P, 
     po = make_float4(x, y, z, __uint_as_float(ti));
     D.x[xin ^ 1][i] = po;
     D.u[i] = make_float4(vx, vy, vz, 0.0f);
-    bin_particle(P, D, lnext, i, po);
     if (!accum_ke) return 0ull;
     const double v2 = ((double)vx * vx + (double)vy * vy) + (double)vz * vz;
     return (unsigned long long)rint((double)T.mass[ti] * v2 * 4294967296.0);
@@ -667,40 +672,12 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
     if (over) atomicOr(&D.err[0], kErrNlist);
 }
 
-// Per-type and per-type-pair constants of the step, staged in LDS once per
-// workgroup.  The force loop indexes them with lane-varying types; read from
-// the kernel-argument block each lookup would be one more dependent memory
-// round trip per neighbour.
-struct StepTabs {
-    float rc2_pre[kMaxTypes * kMaxTypes], rc2_in[kMaxTypes * kMaxTypes];
-    float sig2f[kMaxTypes * kMaxTypes], eps24f[kMaxTypes * kMaxTypes];
-    PairTab pair[kMaxTypes * kMaxTypes];
-    double bk[kMaxBondTypes], br0[kMaxBondTypes], binvR02[kMaxBondTypes];
-    uint32_t bkind[kMaxBondTypes];
-    uint32_t rbt[kMaxRx];
-    float hm[kMaxTypes], noise_sd[kMaxTypes], mass[kMaxTypes];
-    uint32_t cap[kMaxTypes];
-};
-
-__device__ __forceinline__ void stage_tabs(const Params& P, const Dev& D, StepTabs& T, uint32_t tid) {
-    if (tid < kMaxTypes * kMaxTypes) {
-        T.rc2_pre[tid] = P.rc2_pre[tid];
-        T.rc2_in[tid] = P.rc2_in[tid];
-        T.sig2f[tid] = P.sig2f[tid];
-        T.eps24f[tid] = P.eps24f[tid];
-        T.pair[tid] = D.pair[tid];
-    } else if (tid < kMaxTypes * kMaxTypes + 8) {
-        const uint32_t k = tid - kMaxTypes * kMaxTypes;
-        T.bk[k] = P.bk[k];
-        T.br0[k] = P.br0[k];
-        T.binvR02[k] = P.binvR02[k];
-        T.bkind[k] = P.bkind[k];
-        T.rbt[k] = P.rbt[k];
-        T.hm[k] = P.h * P.inv_mass[k];
-        T.noise_sd[k] = P.noise_sd[k];
-        T.mass[k] = P.mass[k];
-        T.cap[k] = P.cap[k];
-    }
+// Copy the step tables (built on the host at commit, kept in device memory)
+// into LDS, 16 bytes per thread.
+__device__ __forceinline__ void stage_tabs(const Dev& D, StepTabs& T, uint32_t tid) {
+    const uint4* __restrict__ src = reinterpret_cast<const uint4*>(D.tabs);
+    uint4* dst = reinterpret_cast<uint4*>(&T);
+    for (uint32_t k = tid; k < sizeof(StepTabs) / 16; k += blockDim.x) dst[k] = src[k];
 }
 
 // WCA force on pi from neighbour pj (type in the w bits), constants from LDS.
@@ -712,11 +689,12 @@ __device__ __forceinline__ void stage_tabs(const Params& P, const Dev& D, StepTa
 __device__ __forceinline__ void pair_force_tab(const Params& P, const StepTabs& T, uint32_t* err, float4 pi,
                                                float4 pj, uint32_t ti, long long& fx, long long& fy,
                                                long long& fz) {
+#pragma clang fp contract(off)
     const int pt = (int)ti * kMaxTypes + (int)type_of(pj);
     const float rc2p = T.rc2_pre[pt];
     float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
     if (fabsf(dx) <= P.halfLf && fabsf(dy) <= P.halfLf && fabsf(dz) <= P.halfLf) {
-        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         if (r2 >= rc2p) return;
         if (r2 < T.rc2_in[pt]) {
             const float ir2 = __builtin_amdgcn_rcpf(r2);
@@ -732,7 +710,7 @@ __device__ __forceinline__ void pair_force_tab(const Params& P, const StepTabs& 
         dx = mi_delta_f(pi.x, pj.x, P);
         dy = mi_delta_f(pi.y, pj.y, P);
         dz = mi_delta_f(pi.z, pj.z, P);
-        if (dx * dx + dy * dy + dz * dz >= rc2p) return;
+        if (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) >= rc2p) return;
     }
     const PairTab& pp = T.pair[pt];
     const double ex = mi_delta(pi.x, pj.x, P.L, P.invL);
@@ -759,6 +737,7 @@ __device__ __forceinline__ void pair_force_tab(const Params& P, const StepTabs& 
 __device__ __forceinline__ void bond_force_tab(const Params& P, const StepTabs& T, const Dev& D, float4 pi,
                                                float4 pj, uint32_t bt, uint32_t i, uint32_t j,
                                                long long& fx, long long& fy, long long& fz) {
+#pragma clang fp contract(off)
     const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
     const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
     const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
@@ -844,7 +823,7 @@ __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int x
             else if (b < nslot) bw[q] = D.dyn[(b - P.stat_max) * n + i];
         }
     }
-    stage_tabs(P, D, T, tid);
+    stage_tabs(D, T, tid);
     if (tid < PPB) fsum[0][tid] = fsum[1][tid] = fsum[2][tid] = 0ull;
     const unsigned long long s = D.stepv[sp] + 1ull;
     if (gtid == 0) {
@@ -906,7 +885,8 @@ __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int x
         const uint32_t t2 = type_of(p2);
         const Force3 F = fix_to_force(D, (long long)fsum[0][tid], (long long)fsum[1][tid], (long long)fsum[2][tid]);
         float4 po;
-        ke = advance_particle(P, T, D, xin, lnext, i2, p2, t2, F, u2, tag2, s, accum_ke, po);
+        ke = advance_particle(P, T, D, xin, i2, p2, t2, F, u2, tag2, s, accum_ke, po);
+        bin_particle(P, D, lnext, i2, po);
         const float4 r = r2;
         const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
         if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[f3 == 2 ? 0 : f3 + 1] = 1u;
@@ -1004,38 +984,34 @@ __device__ __forceinline__ int sweep_reaction(const Params& P, unsigned long lon
     return alpha;
 }
 
-// Proposal phase (Sec. 2.3, Fig. sweep a) fused with the first matching round.
-// TPP threads share a proposer: each scans every TPP-th neighbour-list entry
-// and the group keeps the lexicographic minimum of (|r - r0|, tag).  Sites
-// that cannot propose leave after loading their position and occupancy.  For
-// a proposer, the loads that need only i (the first Q list entries per
-// thread, the bond words) are issued together, then everything the
-// candidates need (position, occupancy, molecule, tag), so that it waits for
-// about four memory round trips.
-template <int TPP>
-__global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur, int sp) {
-    constexpr int Q = 16 / TPP > 1 ? 16 / TPP : 1;
-    const unsigned long long s = D.stepv[sp];
-    const int a = sweep_reaction(P, s, slot);
-    const uint32_t tg = xcd_block() * blockDim.x + threadIdx.x;
-    const uint32_t i = tg / TPP, lane = tg % TPP;
-    if (tg == 0) D.live_count[0] = 0u;
-    if (i >= P.n) return;
-    if (lane == 0) {
-        D.best[2][i] = kNoKey;
-        D.claimed[i] = 0;
-        D.estate[i] = kEdgeNone;
-        D.prop[i] = -1;
-    }
+// Matching priority of a proposal by site i (tag tgi): first Philox word of
+// the MATCH stream in the high half, the tag in the low half (unique keys).
+__device__ __forceinline__ unsigned long long match_key(const Params& P, int a, unsigned long long s, uint32_t tgi) {
+    const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), tgi, 0u, P.seed, stream_k1(kMatch, a, 0));
+    return ((unsigned long long)w.w0 << 32) | tgi;
+}
+
+// Proposal of site i for reaction a (Sec. 2.3, Fig. sweep a): TPP threads
+// share the site (`lane` = this thread's rank in the group); each scans every
+// TPP-th neighbour-list entry and the group keeps the lexicographic minimum of
+// (|r - r0|, tag).  Sites that cannot propose leave after loading their
+// position and occupancy.  For a proposer, the loads that need only i (the
+// first Q list entries per thread, the bond words) are issued together, then
+// everything the candidates need (position, occupancy, molecule, tag), so
+// that it waits for about four memory round trips.  Returns the chosen
+// partner (the same on every thread of the group) or -1; `tgi` receives the
+// site's tag.
+template <int TPP, int Q = (16 / TPP > 1 ? 16 / TPP : 1)>
+__device__ __forceinline__ int propose_site(const Params& P, const Dev& D, int a, const float4* __restrict__ X,
+                                            uint32_t i, uint32_t lane, uint32_t& tgi_out) {
     const size_t n = P.n;
-    const float4* __restrict__ X = D.x[xcur];
     // sites that cannot propose (wrong type, full valence) leave after one load
     const float4 pi = X[i];
     const uint32_t occ_i = D.occ[i];
     const uint32_t ti = type_of(pi);
     const uint32_t ta = P.ra[a], tb = P.rb[a];
-    if (ti != ta && ti != tb) return;
-    if (occ_i >= P.cap[ti]) return;
+    if (ti != ta && ti != tb) return -1;
+    if (occ_i >= P.cap[ti]) return -1;
     const uint32_t m = D.nl_cnt[i];
     uint32_t nb[Q];
 #pragma unroll
@@ -1120,14 +1096,36 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
             best_j = oj2;
         }
     }
+    tgi_out = tgi;
+    return best_j;
+}
+
+// Proposal phase fused with the first matching round: proposals and their
+// priority keys (Philox of the MATCH stream), posted with 64-bit atomicMin at
+// both sites for round 1.
+template <int TPP>
+__global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur, int sp) {
+    const unsigned long long s = D.stepv[sp];
+    const int a = sweep_reaction(P, s, slot);
+    const uint32_t tg = xcd_block() * blockDim.x + threadIdx.x;
+    const uint32_t i = tg / TPP, lane = tg % TPP;
+    if (tg == 0) D.live_count[0] = 0u;
+    if (i >= P.n) return;
+    if (lane == 0) {
+        D.best[2][i] = kNoKey;
+        D.claimed[i] = 0;
+        D.estate[i] = kEdgeNone;
+        D.prop[i] = -1;
+    }
+    uint32_t tgi = 0;
+    const int best_j = propose_site<TPP>(P, D, a, D.x[xcur], i, lane, tgi);
     if (lane != 0 || best_j < 0) return;
-    const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), tgi, 0u, P.seed, stream_k1(kMatch, a, 0));
-    const uint64_t key = ((uint64_t)w.w0 << 32) | tgi;
+    const unsigned long long key = match_key(P, a, s, tgi);
     D.prop[i] = best_j;
     D.key[i] = key;
     D.estate[i] = kEdgeLive;
-    atomicMin(&D.best[1][i], (unsigned long long)key);
-    atomicMin(&D.best[1][best_j], (unsigned long long)key);
+    atomicMin(&D.best[1][i], key);
+    atomicMin(&D.best[1][best_j], key);
 }
 
 // Acceptance of a claimed pair (Eq. pon): returns true when the bond forms,
@@ -1369,11 +1367,51 @@ __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, in
     }
 }
 
-// Breaking phase (Sec. 2.3, Fig. sweep d): bonds of reaction a present at the
-// start of the sweep break with P0_off; bonds formed in this sweep only lose
-// their "new" mark.  Each site edits its own slots; both ends draw the same
-// number.  Also resets best[1] for the next reaction's proposal round.  All
-// slot words are loaded at once, then the partners' tags.
+// Breaking at site i for reaction a (sweep at step s): bonds of reaction a
+// present at the start of the sweep break with P0_off; bonds formed in this
+// sweep only lose their "new" mark.  Each site edits its own slots; both ends
+// draw the same number.  All slot words are loaded at once, then the
+// partners' tags.  Returns the number of bonds broken with i as the lower tag.
+__device__ __forceinline__ uint32_t break_site(const Params& P, const Dev& D, int a, unsigned long long s,
+                                               uint32_t i) {
+    const size_t n = P.n;
+    uint32_t broke = 0;
+    uint32_t w[kMaxValence];
+    bool mine[kMaxValence];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < kMaxValence; ++k) {
+        w[k] = (uint32_t)k < P.cap_max ? D.dyn[(size_t)k * n + i] : kEmpty;
+        mine[k] = w[k] != kEmpty && ((w[k] >> 24) & 0x7Fu) == (uint32_t)a;
+        any |= mine[k];
+    }
+    if (!any) return 0u;
+    const uint32_t tgi = D.tag[i];
+    uint32_t tgj[kMaxValence];
+#pragma unroll
+    for (int k = 0; k < kMaxValence; ++k)     // unconditional (clamped) loads, issued together
+        tgj[k] = D.tag[mine[k] ? (w[k] & kIdxMask) : i];
+    uint32_t occ = D.occ[i];
+    const uint32_t occ0 = occ;
+#pragma unroll
+    for (int k = 0; k < kMaxValence; ++k) {
+        if (!mine[k]) continue;
+        uint32_t* sl = &D.dyn[(size_t)k * n + i];
+        if (w[k] & kNewBit) { *sl = w[k] & ~kNewBit; continue; }
+        const uint32_t lo = tgi < tgj[k] ? tgi : tgj[k], hi = tgi < tgj[k] ? tgj[k] : tgi;
+        const Word4 r = philox((uint32_t)s, (uint32_t)(s >> 32), lo, hi, P.seed, stream_k1(kOff, a, 0));
+        if (u53(r.w0, r.w1) < P.poff[a]) {
+            *sl = kEmpty;
+            --occ;
+            if (tgi < tgj[k]) ++broke;
+        }
+    }
+    if (occ != occ0) D.occ[i] = (uint8_t)occ;
+    return broke;
+}
+
+// Breaking phase (Sec. 2.3, Fig. sweep d), one thread per site (break_site).
+// Also resets best[1] for the next reaction's proposal round.
 __global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int slot, int xcur, int sp,
                                                int last) {
     const unsigned long long s = D.stepv[sp];
@@ -1382,40 +1420,8 @@ __global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int 
     if (last && i == 0) *D.ke_fix = 0ull;
     uint32_t broke = 0;
     if (i < P.n) {
-        const size_t n = P.n;
         D.best[1][i] = kNoKey;
-        uint32_t w[kMaxValence];
-        bool mine[kMaxValence];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < kMaxValence; ++k) {
-            w[k] = (uint32_t)k < P.cap_max ? D.dyn[(size_t)k * n + i] : kEmpty;
-            mine[k] = w[k] != kEmpty && ((w[k] >> 24) & 0x7Fu) == (uint32_t)a;
-            any |= mine[k];
-        }
-        if (any) {
-            const uint32_t tgi = D.tag[i];
-            uint32_t tgj[kMaxValence];
-#pragma unroll
-            for (int k = 0; k < kMaxValence; ++k)     // unconditional (clamped) loads, issued together
-                tgj[k] = D.tag[mine[k] ? (w[k] & kIdxMask) : i];
-            uint32_t occ = D.occ[i];
-            const uint32_t occ0 = occ;
-#pragma unroll
-            for (int k = 0; k < kMaxValence; ++k) {
-                if (!mine[k]) continue;
-                uint32_t* sl = &D.dyn[(size_t)k * n + i];
-                if (w[k] & kNewBit) { *sl = w[k] & ~kNewBit; continue; }
-                const uint32_t lo = tgi < tgj[k] ? tgi : tgj[k], hi = tgi < tgj[k] ? tgj[k] : tgi;
-                const Word4 r = philox((uint32_t)s, (uint32_t)(s >> 32), lo, hi, P.seed, stream_k1(kOff, a, 0));
-                if (u53(r.w0, r.w1) < P.poff[a]) {
-                    *sl = kEmpty;
-                    --occ;
-                    if (tgi < tgj[k]) ++broke;
-                }
-            }
-            if (occ != occ0) D.occ[i] = (uint8_t)occ;
-        }
+        broke = break_site(P, D, a, s, i);
     }
     count_add(D, a, kCtrBreak, broke);
 }

@@ -20,7 +20,10 @@ with ``numpy.random.default_rng(seed)``:
                  (sigma 1, valence 6), 50% B (sigma 0.5, valence 2), 30% C
                  (sigma 0.5, valence 1); A-B eps = 8 kT with P0_on = 1 and
                  A-C eps = 4 kT with P0_on = 0.25; bond rest length
-                 sigma_AB = 0.75, capture radius 1.3 r0.
+                 sigma_AB = 0.75, capture radius 1.3 r0;
+* ``replica_set`` parameter-sweep replicas (N log-uniform in [256, 8192],
+                 eps ~ U[2, 10], density ~ U[0.05, 0.4], B valence 1/2/4,
+                 monomers or telechelic chains), built by ``replica``.
 
 All use Langevin kT = 1, gamma = 1, dt = 0.005, sweeps every 10 steps.
 """
@@ -249,6 +252,100 @@ def gel(seed=1, n=200000, density=0.3, eps_ab=8.0, eps_ac=4.0):
                  k_on=math.nan, k_off=math.nan, epsilon=eps_ac, p_on0=0.25, self_avoid=0),
         ],
         steps=10000, seed=seed)
+
+
+def _snake_lattice(L, spacing_min):
+    """Sites of a simple cubic lattice filling the periodic box, listed along
+    a boustrophedon path (x fastest, direction reversed every row and every
+    plane), so that consecutive sites are lattice neighbours.  Spacing
+    a = L / floor(L / spacing_min) >= spacing_min."""
+    m = int(math.floor(L / spacing_min))
+    a = L / m
+    k = np.arange(m)
+    sites = []
+    for z in range(m):
+        ys = k if z % 2 == 0 else k[::-1]
+        for r, y in enumerate(ys):
+            xs = k if (z * m + r) % 2 == 0 else k[::-1]
+            sites.append(np.stack([xs, np.full(m, y), np.full(m, z)], axis=1))
+    sites = np.concatenate(sites).astype(np.float64)
+    return (sites + 0.5) * a - 0.5 * L, a
+
+
+def replica(seed, n, eps, density, cap_b, kind):
+    """One replica of the parameter sweep: A sites of valence 1 binding B
+    sites of valence cap_b (harmonic k = 100, r0 = 1, capture radius 1.3,
+    P0_on = 1), with as many B valences as A sites.
+
+    kind "mono": n A/B monomers.  kind "chains": telechelic chains of 10
+    beads (FENE k = 30, R0 = 1.5; ends A, middles M of valence 0) plus B
+    crosslinkers.  Particles sit on distinct sites of a lattice of spacing
+    >= 0.97 (chains on consecutive sites of a boustrophedon path, so every
+    FENE bond starts at the lattice spacing < R0 and no two beads overlap)."""
+    rng = np.random.default_rng(seed)
+    L = box_length(n, density)
+    sites, a = _snake_lattice(L, 0.97)
+    nsites = len(sites)
+    if kind == "mono":
+        n_a = int(round(n * cap_b / (cap_b + 1.0)))
+        n_b = n - n_a
+        types = [(1, 1.0, 1.0, 1.0), (cap_b, 1.0, 1.0, 1.0)]
+        pick = rng.choice(nsites, n, replace=False)
+        tid = np.array([0] * n_a + [1] * n_b, dtype=np.uint32)[rng.permutation(n)]
+        pos = sites[pick]
+        pairs = np.zeros((0, 2), dtype=np.uint32)
+        bond_types = [(HARMONIC, 100.0, 1.0)]
+        rx_bond, ta, tb = 0, 0, 1
+    elif kind == "chains":
+        chain_len = 10
+        # 2 ends per chain = cap_b valences per crosslinker
+        n_chains = max(1, int(round(n * cap_b / (chain_len * cap_b + 2.0))))
+        n_b = max(1, int(round(2.0 * n_chains / cap_b)))
+        n = n_chains * chain_len + n_b
+        L = box_length(n, density)
+        sites, a = _snake_lattice(L, 0.97)
+        nsites = len(sites)
+        nseg = nsites // chain_len
+        if nseg < n_chains + n_b:
+            raise RuntimeError("replica too dense for the lattice")
+        segs = rng.choice(nseg, n_chains + n_b, replace=False)
+        chain_sites = (segs[:n_chains, None] * chain_len + np.arange(chain_len)[None, :]).reshape(-1)
+        b_sites = segs[n_chains:] * chain_len + rng.integers(0, chain_len, n_b)
+        pos = np.concatenate([sites[chain_sites], sites[b_sites]])
+        tid = np.concatenate([np.tile(np.array([0] + [1] * (chain_len - 2) + [0], dtype=np.uint32), n_chains),
+                              np.full(n_b, 2, dtype=np.uint32)])
+        types = [(1, 1.0, 1.0, 1.0), (0, 1.0, 1.0, 1.0), (cap_b, 1.0, 1.0, 1.0)]
+        base = (np.arange(n_chains) * chain_len)[:, None]
+        pairs = np.stack([(base + np.arange(chain_len - 1)).reshape(-1),
+                          (base + np.arange(1, chain_len)).reshape(-1)], axis=1).astype(np.uint32)
+        bond_types = [(FENE, 30.0, 1.5), (HARMONIC, 100.0, 1.0)]
+        rx_bond, ta, tb = 1, 0, 2
+    else:
+        raise ValueError(kind)
+    masses = np.ones(n)
+    return Workload(
+        name=f"replica_{kind}", n=n, L=L, types=types, pos=_wrap32(pos, L),
+        vel=_velocities(n, masses, 1.0, rng), type_id=tid,
+        bond_types=bond_types, static_pairs=pairs,
+        static_types=np.zeros(len(pairs), dtype=np.uint32),
+        reactions=[dict(type_a=ta, type_b=tb, bond_type=rx_bond, r_min=0.0, r_max=1.3,
+                        k_on=math.nan, k_off=math.nan, epsilon=float(eps), p_on0=1.0, self_avoid=0)],
+        steps=20000, seed=seed,
+        extra=dict(eps=float(eps), density=float(density), cap_b=int(cap_b), kind=kind))
+
+
+def replica_set(seed=1, count=1024, n_min=256, n_max=8192):
+    """Parameter-sweep replicas: N log-uniform in [n_min, n_max], eps ~ U[2, 10],
+    density ~ U[0.05, 0.4], B valence in {1, 2, 4}, kind mono or chains with
+    probability 1/2 each; replica k is seeded with seed * 100003 + k."""
+    rng = np.random.default_rng(seed)
+    n = np.exp(rng.uniform(math.log(n_min), math.log(n_max), count)).astype(int)
+    eps = rng.uniform(2.0, 10.0, count)
+    rho = rng.uniform(0.05, 0.4, count)
+    cap = rng.choice([1, 2, 4], count)
+    kind = np.where(rng.random(count) < 0.5, "mono", "chains")
+    return [replica(seed * 100003 + k, int(n[k]), eps[k], rho[k], int(cap[k]), str(kind[k]))
+            for k in range(count)]
 
 
 WORKLOADS = {"small": small, "telechelic": telechelic, "gel": gel}

@@ -282,3 +282,57 @@ def test_edge_cases():
             s.set_state(0, w.pos, w.vel, [[0, 256], [0, 257]], [0, 0])
         s.set_state(0, w.pos, w.vel, [[0, 256]], [0])
         assert s.bonds().tolist() == [[0, 256, 0]]
+
+
+def _snapshot(s):
+    return s.positions(), s.velocities(), s.bonds(), counters(s)
+
+
+def _assert_same_state(p, b, label):
+    assert p.step_count == b.step_count, label
+    for name, x, y in zip(("positions", "velocities", "bonds", "counters"), _snapshot(p), _snapshot(b)):
+        assert x.shape == y.shape and np.array_equal(x, y), f"{label}: {name} differ"
+
+
+def test_batched_systems_match_plain_runs():
+    """db_step_batch on a mixed batch (sizes 300..8k, monomers and chains,
+    one kinetic-temperature system) is bitwise equal to db_step on each
+    system, and hands the state back so that plain steps continue equal."""
+    ws = [inputs.small(seed=6), inputs.small(seed=7, n=300, density=0.2)] + inputs.replica_set(seed=5, count=6)
+    kts = [db.DB_KT_SETPOINT] * len(ws) + [db.DB_KT_KINETIC]
+    ws = ws + [ws[0]]
+    log("case batch: sizes " + " ".join(str(w.n) for w in ws))
+    plain = [db.System.from_workload(w, kt_source=k) for w, k in zip(ws, kts)]
+    batch = [db.System.from_workload(w, kt_source=k) for w, k in zip(ws, kts)]
+    try:
+        for p in plain:
+            p.step(250)
+        db.db_step_batch([b.h for b in batch], 250)
+        for k, (p, b) in enumerate(zip(plain, batch)):
+            _assert_same_state(p, b, f"system {k} after 250 steps")
+            assert counters(p).sum() > 0
+        for p, b in zip(plain, batch):
+            p.step(37)
+            b.step(37)
+        for k, (p, b) in enumerate(zip(plain, batch)):
+            _assert_same_state(p, b, f"system {k} after 37 more plain steps")
+    finally:
+        for x in plain + batch:
+            x.close()
+
+
+def test_batched_run_across_launch_chunks():
+    """A batched run longer than one launch (2000 steps) equals db_step."""
+    ws = [inputs.small(seed=8), inputs.replica_set(seed=9, count=1)[0]]
+    log("case batch chunks: sizes " + " ".join(str(w.n) for w in ws))
+    plain = [db.System.from_workload(w) for w in ws]
+    batch = [db.System.from_workload(w) for w in ws]
+    try:
+        for p in plain:
+            p.step(2013)
+        db.db_step_batch([b.h for b in batch], 2013)
+        for k, (p, b) in enumerate(zip(plain, batch)):
+            _assert_same_state(p, b, f"system {k} after 2013 steps")
+    finally:
+        for x in plain + batch:
+            x.close()

@@ -49,6 +49,46 @@ def test_validation_accepts_the_workloads():
         s.close()
 
 
+def test_replica_set_is_valid_and_balanced():
+    """Sweep replicas: sizes in range, no two particles closer than the
+    lattice spacing, as many B valences as A sites, every FENE bond shorter
+    than R0, and each replica passes host validation."""
+    from scipy.spatial import cKDTree
+    reps = inputs.replica_set(seed=3, count=24)
+    assert {r.extra["kind"] for r in reps} == {"mono", "chains"}
+    for w in reps:
+        assert 200 <= w.n <= 8400
+        p = (w.pos.astype(np.float64) + 0.5 * w.L) % w.L
+        d, _ = cKDTree(p, boxsize=w.L).query(p, k=2)
+        assert d[:, 1].min() >= 0.969
+        val = np.array([t[0] for t in w.types])[w.type_id]
+        a_sites = np.sum(w.type_id == 0)
+        b_val = np.sum(val[w.type_id == len(w.types) - 1])
+        assert abs(int(b_val) - int(a_sites)) <= w.extra["cap_b"] + 2
+        if len(w.static_pairs):
+            dd = p[w.static_pairs[:, 0]] - p[w.static_pairs[:, 1]]
+            dd -= w.L * np.round(dd / w.L)
+            assert np.linalg.norm(dd, axis=1).max() < 1.5
+        s = _configured(w)
+        db.db_validate(s.h)
+        s.close()
+
+
+def test_batch_entry_point_checks_its_arguments():
+    with pytest.raises(db.DybondError) as e:
+        db.db_step_batch([], 10)
+    assert e.value.name == "DB_EINVAL"
+    w = inputs.small(seed=1)
+    a, b = _configured(w), _configured(w)
+    try:
+        with pytest.raises(db.DybondError) as e:
+            db.db_step_batch([a.h, b.h], 10)          # not committed
+        assert e.value.name == "DB_ESTATE"
+    finally:
+        a.close()
+        b.close()
+
+
 def test_rate_closure_matches_oracle_bit_for_bit():
     w = inputs.small(seed=1)
     cases = [dict(epsilon=5.0, p_on0=1.0), dict(k_on=3.0, k_off=0.5), dict(k_on=1.5, epsilon=2.0),
