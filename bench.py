@@ -5,8 +5,9 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload gel|telechelic|s
 Prints one JSON line: particle-timesteps/s of db_step (bonding sweeps
 included) on a synthetic workload already resident on the GPU, the roofline
 position of the dominant kernel (k_step, timed with HIP events on the stream
-it runs on), and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+it runs on), replicas/hour of a parameter-sweep batch run by db_step_batch
+against the same replicas run one by one with db_step, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
 """
 
 import argparse
@@ -36,6 +37,12 @@ def parse():
     p.add_argument("--cpu-steps", type=int, default=20)
     p.add_argument("--profile-steps", type=int, default=2000)
     p.add_argument("--skin", type=float, default=None, help="neighbour-list skin (default: the library's)")
+    p.add_argument("--replicas", type=int, default=1024,
+                   help="replicas of the parameter-sweep batch (0 skips the batched-vs-plain measurement)")
+    p.add_argument("--replica-steps", type=int, default=20000)
+    p.add_argument("--plain-sample", type=int, default=32,
+                   help="replicas (spread over the size range) timed one after another with db_step")
+    p.add_argument("--plain-steps", type=int, default=2000)
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="first run one plain device-to-device copy of this many MiB (the reference "
                         "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
@@ -94,6 +101,49 @@ def cpu_baseline(w, steps):
                       f"{steps // w.period} bonding sweeps) from its initial state, {dt:.1f} s"}
 
 
+def batch_vs_plain(a, db, inputs, torch):
+    """Replicas/hour of the parameter-sweep batch run by db_step_batch (one
+    launch per 2000 steps, all replicas together) against the same replicas
+    run one after another with db_step.  The plain cost is measured on a
+    sample spread over the size range and scaled to the whole set."""
+    reps = inputs.replica_set(seed=a.seed, count=a.replicas)
+    n_tot = sum(w.n for w in reps)
+    systems = [db.System.from_workload(w) for w in reps]
+    try:
+        db.db_step_batch([s.h for s in systems], 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        db.db_step_batch([s.h for s in systems], a.replica_steps)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        by_size = sorted(range(len(reps)), key=lambda k: reps[k].n)
+        stride = max(1, len(reps) // max(1, a.plain_sample))
+        sample = by_size[stride // 2::stride][:a.plain_sample]
+        for k in sample:
+            systems[k].step(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in sample:
+            systems[k].step(a.plain_steps)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+    finally:
+        for s in systems:
+            s.close()
+    plain_total = tp / len(sample) * len(reps) * (a.replica_steps / a.plain_steps)
+    return {
+        "replicas": len(reps), "particles": n_tot, "steps": a.replica_steps,
+        "batched_s": tb, "batched_replicas_per_hour": len(reps) * 3600.0 / tb,
+        "batched_ptps": n_tot * a.replica_steps / tb,
+        "plain_sample": len(sample), "plain_sample_steps": a.plain_steps, "plain_sample_s": tp,
+        "plain_s_estimated": plain_total, "plain_replicas_per_hour": len(reps) * 3600.0 / plain_total,
+        "speedup": plain_total / tb,
+        "equal_accuracy": "bitwise equal to db_step (tests/test_gpu_parity.py::test_batched_systems_match_plain_runs)",
+        "workload": "parameter-sweep replicas: N log-uniform in [256, 8192], eps ~ U[2, 10], density ~ U[0.05, 0.4], "
+                    "B valence 1/2/4, monomers or telechelic chains",
+    }
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -149,7 +199,7 @@ def main():
     achieved = bpp * w.n / (step_us * 1e-6) / 1e9
     traffic = measured_traffic(tag)
     line = {
-        "metric": "particle-timesteps/sec with bonding (1 GPU)",
+        "metric": "particle-timesteps/sec with bonding (1 GPU); batched vs plain replicas/hour",
         "value": value,
         "unit": "particle-timesteps/s",
         "n_gpus": 1,
@@ -174,6 +224,8 @@ def main():
         "state": {"bonds": obs["n_bonds"].tolist(), "bonded_fraction": obs["bonded_fraction"].tolist(),
                   "T_kin": obs["T_kin"]},
     }
+    if a.replicas > 0:
+        line["batch"] = batch_vs_plain(a, db, inputs, torch)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(line), flush=True)

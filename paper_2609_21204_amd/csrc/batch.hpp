@@ -25,7 +25,7 @@ struct BatchItem {
     int pad0, pad1;
 };
 
-constexpr int kBatchThreads = 512;
+constexpr int kBatchThreads = 1024;
 
 // Workgroup-scope atomic add on global memory: only the owning workgroup
 // touches a system's arrays during a batch launch, so the add can complete

@@ -306,11 +306,13 @@ def replica(seed, n, eps, density, cap_b, kind):
         sites, a = _snake_lattice(L, 0.97)
         nsites = len(sites)
         nseg = nsites // chain_len
-        if nseg < n_chains + n_b:
+        if nseg < n_chains or nsites - n_chains * chain_len < n_b:
             raise RuntimeError("replica too dense for the lattice")
-        segs = rng.choice(nseg, n_chains + n_b, replace=False)
-        chain_sites = (segs[:n_chains, None] * chain_len + np.arange(chain_len)[None, :]).reshape(-1)
-        b_sites = segs[n_chains:] * chain_len + rng.integers(0, chain_len, n_b)
+        segs = rng.choice(nseg, n_chains, replace=False)
+        chain_sites = (segs[:, None] * chain_len + np.arange(chain_len)[None, :]).reshape(-1)
+        free = np.ones(nsites, dtype=bool)
+        free[chain_sites] = False
+        b_sites = rng.choice(np.flatnonzero(free), n_b, replace=False)
         pos = np.concatenate([sites[chain_sites], sites[b_sites]])
         tid = np.concatenate([np.tile(np.array([0] + [1] * (chain_len - 2) + [0], dtype=np.uint32), n_chains),
                               np.full(n_b, 2, dtype=np.uint32)])
