@@ -1,4 +1,5 @@
-"""Build the HIP library (libdybond.so) for gfx950 with hipcc."""
+"""Build the HIP library (libdybond.so: the MD step and the surrogate
+network) for gfx950 with hipcc."""
 
 import os
 import subprocess
@@ -6,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "dybond.hip")
+SRCS = [os.path.join(HERE, "csrc", "dybond.hip"), os.path.join(HERE, "csrc", "mlp.hip")]
 OUT = os.path.join(HERE, "libdybond.so")
 
 FLAGS = [
@@ -17,7 +18,7 @@ FLAGS = [
 
 
 def build(verbose=False):
-    cmd = ["hipcc", *FLAGS, "-I", os.path.join(ROOT, "include"), SRC, "-o", OUT + ".tmp"]
+    cmd = ["hipcc", *FLAGS, "-I", os.path.join(ROOT, "include"), *SRCS, "-o", OUT + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     msgs = [ln for ln in (res.stdout + res.stderr).splitlines()
             if "packed-fp32-ops" not in ln]

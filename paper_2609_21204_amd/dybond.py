@@ -85,7 +85,18 @@ _SIGS = {
     "db_set_stream": (_I, [_P, _P]),
     "db_kernel_timing": (_I, [_P, _I]),
     "db_read_kernel_time": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_U64), ctypes.POINTER(_D)]),
+    # surrogate network (include/dybond_mlp.h)
+    "db_mlp_create": (_I, [_U32, _I, ctypes.POINTER(_P)]),
+    "db_mlp_destroy": (None, [_P]),
+    "db_mlp_set_params": (_I, [_P, _P, _U64]),
+    "db_mlp_get_params": (_I, [_P, _P, _U64]),
+    "db_mlp_predict": (_I, [_P, _P, _U64, _P]),
+    "db_mlp_loss_grad": (_I, [_P, _P, _P, _U32, ctypes.POINTER(ctypes.c_float), _P]),
+    "db_mlp_train": (_I, [_P, _P, _P, _U64, _U32, _U32, ctypes.c_float, _U64, ctypes.POINTER(ctypes.c_float)]),
+    "db_mlp_last_error": (ctypes.c_char_p, [_P]),
 }
+
+MLP_PARAMS = 17410
 
 _lib = None
 
@@ -294,6 +305,68 @@ def db_read_kernel_time(h, kernel):
     n, ms = _U64(), _D()
     _check(h, load().db_read_kernel_time(h, kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+# ---------------------------------------------------------------- surrogate network
+def _mcheck(net, status):
+    if status != DB_OK:
+        msg = load().db_mlp_last_error(net)
+        raise DybondError(status, msg.decode() if msg else "")
+
+
+def _f32(a, cols):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(-1, cols))
+
+
+def db_mlp_create(batch_max, device=0):
+    h = _P()
+    st = load().db_mlp_create(batch_max, device, ctypes.byref(h))
+    if st != DB_OK:
+        raise DybondError(st, "db_mlp_create")
+    return h.value
+
+
+def db_mlp_destroy(net):
+    load().db_mlp_destroy(net)
+
+
+def db_mlp_set_params(net, params):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+    _mcheck(net, load().db_mlp_set_params(net, p.ctypes.data, p.size))
+
+
+def db_mlp_get_params(net):
+    p = np.zeros(MLP_PARAMS, dtype=np.float32)
+    _mcheck(net, load().db_mlp_get_params(net, p.ctypes.data, p.size))
+    return p
+
+
+def db_mlp_predict(net, x):
+    x = _f32(x, 4)
+    y = np.zeros((len(x), 2), dtype=np.float32)
+    _mcheck(net, load().db_mlp_predict(net, x.ctypes.data, len(x), y.ctypes.data))
+    return y
+
+
+def db_mlp_loss_grad(net, x, t):
+    x, t = _f32(x, 4), _f32(t, 2)
+    loss = ctypes.c_float()
+    g = np.zeros(MLP_PARAMS, dtype=np.float32)
+    _mcheck(net, load().db_mlp_loss_grad(net, x.ctypes.data, t.ctypes.data, len(x), ctypes.byref(loss), g.ctypes.data))
+    return float(loss.value), g
+
+
+def db_mlp_train(net, x, t, batch, epochs, lr, seed=1):
+    x, t = _f32(x, 4), _f32(t, 2)
+    loss = ctypes.c_float()
+    _mcheck(net, load().db_mlp_train(net, x.ctypes.data, t.ctypes.data, len(x), batch, epochs, lr, seed,
+                                     ctypes.byref(loss)))
+    return float(loss.value)
+
+
+def db_mlp_last_error(net):
+    msg = load().db_mlp_last_error(net)
+    return msg.decode() if msg else ""
 
 
 # ---------------------------------------------------------------- convenience
