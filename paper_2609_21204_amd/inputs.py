@@ -272,10 +272,11 @@ def _snake_lattice(L, spacing_min):
     return (sites + 0.5) * a - 0.5 * L, a
 
 
-def replica(seed, n, eps, density, cap_b, kind):
+def replica(seed, n, eps, density, cap_b, kind, kT=1.0):
     """One replica of the parameter sweep: A sites of valence 1 binding B
     sites of valence cap_b (harmonic k = 100, r0 = 1, capture radius 1.3,
-    P0_on = 1), with as many B valences as A sites.
+    P0_on = 1, bond free energy eps in units of kT), with as many B valences
+    as A sites, thermostatted at kT (velocities drawn at kT).
 
     kind "mono": n A/B monomers.  kind "chains": telechelic chains of 10
     beads (FENE k = 30, R0 = 1.5; ends A, middles M of valence 0) plus B
@@ -327,13 +328,13 @@ def replica(seed, n, eps, density, cap_b, kind):
     masses = np.ones(n)
     return Workload(
         name=f"replica_{kind}", n=n, L=L, types=types, pos=_wrap32(pos, L),
-        vel=_velocities(n, masses, 1.0, rng), type_id=tid,
+        vel=_velocities(n, masses, kT, rng), type_id=tid,
         bond_types=bond_types, static_pairs=pairs,
         static_types=np.zeros(len(pairs), dtype=np.uint32),
         reactions=[dict(type_a=ta, type_b=tb, bond_type=rx_bond, r_min=0.0, r_max=1.3,
                         k_on=math.nan, k_off=math.nan, epsilon=float(eps), p_on0=1.0, self_avoid=0)],
-        steps=20000, seed=seed,
-        extra=dict(eps=float(eps), density=float(density), cap_b=int(cap_b), kind=kind))
+        kT=float(kT), steps=20000, seed=seed,
+        extra=dict(eps=float(eps), density=float(density), cap_b=int(cap_b), kind=kind, kT=float(kT)))
 
 
 def replica_set(seed=1, count=1024, n_min=256, n_max=8192):
