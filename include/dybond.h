@@ -190,20 +190,64 @@ DB_API db_status db_commit(db_system* sys);
  * leave the state invalid (DB_ESTATE) until db_set_state. */
 DB_API db_status db_step(db_system* sys, uint64_t n_steps);
 
+/* Launch plan of a batch (db_step_batch): the systems fall into size
+ * classes, class k holding those with n <= n_max[k] that no earlier class
+ * holds (the last class also takes every larger system), and every system
+ * of class k runs in one workgroup of threads[k] threads.  n_max ascending;
+ * threads a multiple of 64 in [64, 1024].  The plan changes only the speed:
+ * results are bitwise the same under any plan. */
+#define DB_BATCH_MAX_CLASSES 8
+typedef struct {
+    uint32_t n_classes;                        /* 1..DB_BATCH_MAX_CLASSES */
+    uint32_t n_max[DB_BATCH_MAX_CLASSES];
+    uint32_t threads[DB_BATCH_MAX_CLASSES];
+} db_batch_plan;
+
 /* Advance `count` committed systems on one device by n_steps each (batched
- * replicas of a parameter sweep): one launch per chunk of up to 2000 steps, one workgroup
- * per system running all of its steps with workgroup barriers between the
- * phases of a step, each system's own device state and buffers.  The result
- * is bitwise identical to db_step(systems[k], n_steps) on every system (same
- * forces, integrator, random streams and greedy matching); positions may be
- * numbered differently inside the library, which db_read_* never show.
- * Meant for many small systems (one workgroup each; a system of N particles
- * takes about N / 512 particle updates per thread per step).  Synchronous.
- * Errors: DB_EINVAL (null or empty list, a system listed twice, systems on
- * different devices), DB_ESTATE (a system not committed or invalid),
- * DB_EDEVICE; per-system errors as db_step (the first in list order is
- * returned, each system's own message is in its db_last_error). */
+ * replicas of a parameter sweep) under the plan stored for the device
+ * (db_set_batch_plan, db_batch_autotune; by default one class of
+ * 1024-thread workgroups).  One workgroup per system runs all of its steps,
+ * with workgroup barriers between the phases of a step and the system's own
+ * device state and buffers.  All launches of a call form one HIP graph: each
+ * occupied size class is a branch of its own (the classes run concurrently),
+ * a chain of launches of at most 2000 steps each (a bound on how long one
+ * kernel runs) that hand each system's step and buffer indices on in device
+ * memory.  The result is bitwise identical to db_step(systems[k], n_steps)
+ * on every system (same forces, integrator, random streams and greedy
+ * matching); positions may be numbered differently inside the library,
+ * which db_read_* never show.  Synchronous.  Errors: DB_EINVAL (null or
+ * empty list, a system listed twice, systems on different devices),
+ * DB_ESTATE (a system not committed or invalid), DB_EDEVICE; per-system
+ * errors as db_step (the first in list order is returned, each system's own
+ * message is in its db_last_error). */
 DB_API db_status db_step_batch(db_system* const* systems, uint32_t count, uint64_t n_steps);
+
+/* db_step_batch under an explicit plan (not stored).  Errors as
+ * db_step_batch, and DB_EINVAL for a malformed plan (message in the first
+ * system's db_last_error). */
+DB_API db_status db_step_batch_plan(db_system* const* systems, uint32_t count, uint64_t n_steps,
+                                    const db_batch_plan* plan);
+
+/* Store the plan db_step_batch uses on HIP device `device` (NULL restores
+ * the default); read it back with db_get_batch_plan.  Thread-safe.  Errors:
+ * DB_EINVAL (malformed plan), DB_EDEVICE (no such device). */
+DB_API db_status db_set_batch_plan(int device, const db_batch_plan* plan);
+DB_API db_status db_get_batch_plan(int device, db_batch_plan* plan);
+
+/* Autotuner of the batch launch.  Size classes are the octaves of n (n <=
+ * 512, <= 1024, <= 2048, <= 4096, larger).  Starting from 1024 threads in
+ * every class, each occupied class in turn, smallest first, tries 256 and
+ * 512 threads, and keeps a size when the whole batch then runs at least 2 %
+ * faster (device time of trial_steps steps, after one untimed trial).  Every
+ * trial advances all systems by trial_steps (1..2000): since results do not
+ * depend on the plan, the trials are ordinary steps of the run, and
+ * *steps_done (may be NULL) receives their number.  The chosen plan is
+ * stored for the device and copied to *best (may be NULL); trial_ms (may be
+ * NULL) receives the time of each timed trial in order, at most trial_len
+ * values.  Errors as db_step_batch. */
+DB_API db_status db_batch_autotune(db_system* const* systems, uint32_t count, uint32_t trial_steps,
+                                   db_batch_plan* best, uint64_t* steps_done, double* trial_ms,
+                                   uint32_t trial_len);
 
 /* One bonding sweep at the current positions with step key `step_key`
  * (random streams keyed as for a sweep at that step); particles do not move,

@@ -16,16 +16,20 @@
 
 namespace dyb {
 
-// One system of a batch as the kernel sees it.
+// One system of a batch as the kernel sees it (read only).
 struct BatchItem {
     Params P;
     Dev D;
-    unsigned long long t0;   // step of the system at the start of the launch
-    int cur_x, cur_list;     // current position buffer and cell list
-    int pad0, pad1;
 };
 
-constexpr int kBatchThreads = 1024;
+// Where a system's run stands: read at the start of a launch, written back
+// at its end, so consecutive launches of a batch chain on the device alone.
+struct BatchState {
+    unsigned long long t;    // step of the system
+    int cur_x, cur_list;     // current position buffer and cell list
+};
+
+constexpr int kBatchMaxThreads = 1024;
 
 // Workgroup-scope atomic add on global memory: only the owning workgroup
 // touches a system's arrays during a batch launch, so the add can complete
@@ -130,11 +134,16 @@ __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T
 // greedy matching alternate two key buffers: post keys at both sites of each
 // live proposal, claim the proposals that hold the minimum at both sites
 // (and try them, Eq. pon), drop the proposals that touch a claimed site.
-__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
-void k_batch(const BatchItem* __restrict__ items, uint32_t nsteps) {
+// Any workgroup size that is a multiple of 64 up to kBatchMaxThreads gives
+// the same result: particles are dealt out round robin over the threads and
+// every sum is exact.
+__global__ __launch_bounds__(kBatchMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state, uint32_t nsteps) {
     const BatchItem& B = items[blockIdx.x];
     const Params& P = B.P;
     const Dev& D = B.D;
+    const BatchState st0 = state[blockIdx.x];
+    const unsigned long long t0 = st0.t;
     __shared__ StepTabs T;
     __shared__ uint32_t flag[3];          // rebuild flags, one per step mod 3
     __shared__ uint32_t more[3];          // live proposals left, one per matching round mod 3
@@ -143,9 +152,9 @@ void k_batch(const BatchItem* __restrict__ items, uint32_t nsteps) {
     stage_tabs(D, T, tid);
     if (tid < 3) flag[tid] = more[tid] = 0u;
     __syncthreads();
-    int xin = B.cur_x, lcur = B.cur_list;
+    int xin = st0.cur_x, lcur = st0.cur_list;
     for (uint32_t k = 0; k < nsteps; ++k) {
-        const unsigned long long t = B.t0 + k, s = t + 1;
+        const unsigned long long t = t0 + k, s = t + 1;
         const int lnext = lcur == 2 ? 0 : lcur + 1, lclr = lnext == 2 ? 0 : lnext + 1;
         const bool sweep = P.nrx > 0 && (s % P.period) == 0;
         const int ake = (sweep && P.kt_kinetic) ? 1 : 0;
@@ -252,8 +261,13 @@ void k_batch(const BatchItem* __restrict__ items, uint32_t nsteps) {
     // rebuild pending, round-1 key buffer clear
     for (uint32_t i = tid; i < n; i += bs) D.best[1][i] = kNoKey;
     if (tid == 0) {
-        D.stepv[0] = D.stepv[1] = B.t0 + nsteps;
+        D.stepv[0] = D.stepv[1] = t0 + nsteps;
         D.rflag[0] = D.rflag[1] = D.rflag[2] = 0u;
+        BatchState st;
+        st.t = t0 + nsteps;
+        st.cur_x = xin;
+        st.cur_list = lcur;
+        state[blockIdx.x] = st;
     }
 }
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -987,7 +988,49 @@ db_status db_step(db_system* s, uint64_t nsteps) {
     return check_errors(s);
 }
 
-db_status db_step_batch(db_system* const* systems, uint32_t count, uint64_t nsteps) {
+}  // extern "C"
+
+namespace {
+
+// launch plans of db_step_batch stored per device
+std::mutex g_plan_mu;
+std::map<int, db_batch_plan> g_plans;
+
+db_batch_plan default_plan() {
+    db_batch_plan p{};
+    p.n_classes = 1;
+    p.n_max[0] = 0xFFFFFFFFu;
+    p.threads[0] = (uint32_t)kBatchMaxThreads;
+    return p;
+}
+
+const char* plan_error(const db_batch_plan* p) {
+    if (!p) return "null plan";
+    if (p->n_classes < 1 || p->n_classes > DB_BATCH_MAX_CLASSES) return "plan: n_classes must be in [1, 8]";
+    for (uint32_t k = 0; k < p->n_classes; ++k) {
+        if (p->threads[k] < 64 || p->threads[k] > (uint32_t)kBatchMaxThreads || p->threads[k] % 64u)
+            return "plan: threads must be a multiple of 64 in [64, 1024]";
+        if (k && p->n_max[k] <= p->n_max[k - 1]) return "plan: n_max must ascend";
+    }
+    return nullptr;
+}
+
+uint32_t class_of(const db_batch_plan& p, uint32_t n) {
+    for (uint32_t k = 0; k + 1 < p.n_classes; ++k)
+        if (n <= p.n_max[k]) return k;
+    return p.n_classes - 1;
+}
+
+bool device_ok(int device) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return device >= 0 && device < ndev;
+}
+
+db_status batch_check(db_system* const* systems, uint32_t count) {
     if (!systems || count == 0) return DB_EINVAL;
     for (uint32_t k = 0; k < count; ++k) {
         db_status st = ready(systems[k]);
@@ -997,56 +1040,238 @@ db_status db_step_batch(db_system* const* systems, uint32_t count, uint64_t nste
         if (systems[k]->device != systems[0]->device)
             return fail(systems[k], DB_EINVAL, "batched systems must share one device");
     }
+    return DB_OK;
+}
+
+// Device buffers, streams, events and graph of one batch run, released on
+// every exit path.
+struct BatchRun {
+    BatchItem* items = nullptr;
+    BatchState* state = nullptr;
+    std::vector<hipStream_t> streams;      // extra streams of the 2nd, 3rd ... occupied class
+    std::vector<hipEvent_t> events;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchRun() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipStream_t q : streams) (void)hipStreamDestroy(q);
+        if (items) (void)hipFree(items);
+        if (state) (void)hipFree(state);
+    }
+    hipEvent_t event() {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        events.push_back(e);
+        return e;
+    }
+};
+
+constexpr uint32_t kBatchChunk = 2000;     // steps per launch
+
+// Every system advanced by nsteps under `plan`; *ms (may be null) receives
+// the device time of the graph.  On a device error every system is marked
+// dead; per-system errors are checked afterwards.
+db_status run_batch(db_system* const* systems, uint32_t count, uint64_t nsteps, const db_batch_plan& plan,
+                    float* ms) {
     db_system* s0 = systems[0];
+    if (ms) *ms = 0.0f;
     HIPCHK(s0, hipSetDevice(s0->device));
     for (uint32_t k = 0; k < count; ++k) HIPCHK(systems[k], hipStreamSynchronize(systems[k]->stream));
-    // largest systems first: their workgroups start in the first wave
-    std::vector<uint32_t> order(count);
-    std::iota(order.begin(), order.end(), 0u);
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return systems[a]->n > systems[b]->n; });
+    if (nsteps == 0) return DB_OK;
+    // classes in plan order; largest systems first inside a class, so that
+    // their workgroups start in the first wave
+    std::vector<std::vector<uint32_t>> groups(plan.n_classes);
+    for (uint32_t k = 0; k < count; ++k) groups[class_of(plan, systems[k]->n)].push_back(k);
+    std::vector<uint32_t> order;
+    std::vector<std::pair<uint32_t, uint32_t>> spans;    // (offset, size) of each occupied class
+    std::vector<uint32_t> threads;
+    for (uint32_t g = 0; g < plan.n_classes; ++g) {
+        auto& v = groups[g];
+        if (v.empty()) continue;
+        std::stable_sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) { return systems[a]->n > systems[b]->n; });
+        spans.emplace_back((uint32_t)order.size(), (uint32_t)v.size());
+        threads.push_back(plan.threads[g]);
+        order.insert(order.end(), v.begin(), v.end());
+    }
     std::vector<BatchItem> items(count);
-    BatchItem* d_items = nullptr;
-    HIPCHK(s0, hipMalloc(&d_items, count * sizeof(BatchItem)));
-    constexpr uint64_t kChunk = 2000;     // steps per launch
+    std::vector<BatchState> state(count);
+    for (uint32_t k = 0; k < count; ++k) {
+        const db_system* s = systems[order[k]];
+        items[k].P = s->P;
+        items[k].D = s->D;
+        state[k].t = s->step;
+        state[k].cur_x = s->cur_x;
+        state[k].cur_list = s->cur_list;
+    }
     db_status st = DB_OK;
-    for (uint64_t done = 0; done < nsteps && st == DB_OK;) {
-        const uint32_t chunk = (uint32_t)std::min<uint64_t>(kChunk, nsteps - done);
-        for (uint32_t k = 0; k < count; ++k) {
-            const db_system* s = systems[order[k]];
-            BatchItem& it = items[k];
-            it.P = s->P;
-            it.D = s->D;
-            it.t0 = s->step;
-            it.cur_x = s->cur_x;
-            it.cur_list = s->cur_list;
-            it.pad0 = it.pad1 = 0;
+    {
+        BatchRun R;
+        auto dev_fail = [&](const char* what) {
+            for (uint32_t k = 0; k < count; ++k) systems[k]->dead = true;
+            return fail(s0, DB_EDEVICE, "batch: %s", what);
+        };
+        if (hipMalloc(&R.items, count * sizeof(BatchItem)) != hipSuccess ||
+            hipMalloc(&R.state, count * sizeof(BatchState)) != hipSuccess)
+            return fail(s0, DB_ENOMEM, "batch: device allocation failed");
+        if (hipMemcpyAsync(R.items, items.data(), count * sizeof(BatchItem), hipMemcpyHostToDevice, s0->stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(R.state, state.data(), count * sizeof(BatchState), hipMemcpyHostToDevice, s0->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(s0->stream) != hipSuccess)
+            return dev_fail("upload failed");
+        for (size_t g = 1; g < spans.size(); ++g) {
+            hipStream_t q = nullptr;
+            if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) return dev_fail("stream creation failed");
+            R.streams.push_back(q);
         }
-        if (hipMemcpyAsync(d_items, items.data(), count * sizeof(BatchItem), hipMemcpyHostToDevice, s0->stream) !=
-            hipSuccess) { st = fail(s0, DB_EDEVICE, "batch upload failed"); break; }
-        LAUNCH(s0, k_batch, count, kBatchThreads, d_items, chunk);
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s0->stream) != hipSuccess) {
-            st = fail(s0, DB_EDEVICE, "batch launch failed");
-            break;
+        hipEvent_t fork = R.event(), t_a = R.event(), t_b = R.event();
+        std::vector<hipEvent_t> join;
+        for (size_t g = 1; g < spans.size(); ++g) join.push_back(R.event());
+        if (!fork || !t_a || !t_b || std::find(join.begin(), join.end(), nullptr) != join.end())
+            return dev_fail("event creation failed");
+        // capture: one branch per occupied class, a chain of launches each
+        bool ok = hipStreamBeginCapture(s0->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            ok = hipEventRecord(fork, s0->stream) == hipSuccess;
+            for (size_t g = 1; ok && g < spans.size(); ++g) ok = hipStreamWaitEvent(R.streams[g - 1], fork, 0) == hipSuccess;
+            for (size_t g = 0; ok && g < spans.size(); ++g) {
+                hipStream_t q = g ? R.streams[g - 1] : s0->stream;
+                for (uint64_t done = 0; ok && done < nsteps;) {
+                    const uint32_t chunk = (uint32_t)std::min<uint64_t>(kBatchChunk, nsteps - done);
+                    hipLaunchKernelGGL(k_batch, dim3(spans[g].second), dim3(threads[g]), 0, q,
+                                       (const BatchItem*)(R.items + spans[g].first), R.state + spans[g].first, chunk);
+                    ok = hipGetLastError() == hipSuccess;
+                    done += chunk;
+                }
+            }
+            for (size_t g = 1; ok && g < spans.size(); ++g)
+                ok = hipEventRecord(join[g - 1], R.streams[g - 1]) == hipSuccess &&
+                     hipStreamWaitEvent(s0->stream, join[g - 1], 0) == hipSuccess;
+            hipGraph_t graph = nullptr;
+            const bool ended = hipStreamEndCapture(s0->stream, &graph) == hipSuccess;
+            R.graph = graph;
+            ok = ok && ended && graph;
         }
-        for (uint32_t k = 0; k < count; ++k) {
-            db_system* s = systems[k];
-            s->step += chunk;
-            s->cur_x ^= (int)(chunk & 1u);
-            s->cur_list = (int)((s->cur_list + chunk) % 3);
+        if (!ok) {
+            (void)hipGetLastError();
+            return dev_fail("graph capture failed");
         }
-        done += chunk;
+        if (hipGraphInstantiate(&R.exec, R.graph, nullptr, nullptr, 0) != hipSuccess) return dev_fail("graph instantiation failed");
+        if (hipEventRecord(t_a, s0->stream) != hipSuccess || hipGraphLaunch(R.exec, s0->stream) != hipSuccess ||
+            hipEventRecord(t_b, s0->stream) != hipSuccess || hipStreamSynchronize(s0->stream) != hipSuccess)
+            return dev_fail("launch failed");
+        if (ms) (void)hipEventElapsedTime(ms, t_a, t_b);
     }
-    (void)hipFree(d_items);
-    if (st != DB_OK) {
-        for (uint32_t k = 0; k < count; ++k) systems[k]->dead = true;
-        return st;
+    for (uint32_t k = 0; k < count; ++k) {
+        db_system* s = systems[k];
+        s->step += nsteps;
+        s->cur_x ^= (int)(nsteps & 1u);
+        s->cur_list = (int)((s->cur_list + nsteps) % 3);
     }
-    flush_timing(s0);
     for (uint32_t k = 0; k < count; ++k) {
         const db_status e = check_errors(systems[k]);
         if (e != DB_OK && st == DB_OK) st = e;
     }
     return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+db_status db_step_batch_plan(db_system* const* systems, uint32_t count, uint64_t nsteps, const db_batch_plan* plan) {
+    db_status st = batch_check(systems, count);
+    if (st != DB_OK) return st;
+    if (const char* why = plan_error(plan)) return fail(systems[0], DB_EINVAL, "%s", why);
+    return run_batch(systems, count, nsteps, *plan, nullptr);
+}
+
+db_status db_step_batch(db_system* const* systems, uint32_t count, uint64_t nsteps) {
+    db_status st = batch_check(systems, count);
+    if (st != DB_OK) return st;
+    db_batch_plan plan = default_plan();
+    {
+        std::lock_guard<std::mutex> lock(g_plan_mu);
+        auto it = g_plans.find(systems[0]->device);
+        if (it != g_plans.end()) plan = it->second;
+    }
+    return run_batch(systems, count, nsteps, plan, nullptr);
+}
+
+db_status db_set_batch_plan(int device, const db_batch_plan* plan) {
+    if (plan && plan_error(plan)) return DB_EINVAL;
+    if (!device_ok(device)) return DB_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    if (plan) g_plans[device] = *plan;
+    else g_plans.erase(device);
+    return DB_OK;
+}
+
+db_status db_get_batch_plan(int device, db_batch_plan* plan) {
+    if (!plan) return DB_EINVAL;
+    if (!device_ok(device)) return DB_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    auto it = g_plans.find(device);
+    *plan = it != g_plans.end() ? it->second : default_plan();
+    return DB_OK;
+}
+
+db_status db_batch_autotune(db_system* const* systems, uint32_t count, uint32_t trial_steps, db_batch_plan* best,
+                            uint64_t* steps_done, double* trial_ms, uint32_t trial_len) {
+    if (steps_done) *steps_done = 0;
+    db_status st = batch_check(systems, count);
+    if (st != DB_OK) return st;
+    if (trial_steps < 1 || trial_steps > kBatchChunk)
+        return fail(systems[0], DB_EINVAL, "trial_steps must be in [1, %u]", kBatchChunk);
+    db_batch_plan p{};
+    p.n_classes = 5;
+    const uint32_t bounds[5] = {512u, 1024u, 2048u, 4096u, 0xFFFFFFFFu};
+    for (uint32_t c = 0; c < 5; ++c) {
+        p.n_max[c] = bounds[c];
+        p.threads[c] = (uint32_t)kBatchMaxThreads;
+    }
+    bool occupied[5] = {};
+    for (uint32_t k = 0; k < count; ++k) occupied[class_of(p, systems[k]->n)] = true;
+    uint64_t done = 0;
+    uint32_t nt = 0;
+    auto trial = [&](const db_batch_plan& q, bool timed, float& ms) {
+        const db_status e = run_batch(systems, count, trial_steps, q, timed ? &ms : nullptr);
+        if (e == DB_OK || !systems[0]->dead) done += trial_steps;
+        if (e == DB_OK && timed && trial_ms && nt < trial_len) trial_ms[nt] = ms;
+        if (e == DB_OK && timed) ++nt;
+        return e;
+    };
+    float t_best = 0.0f, ms = 0.0f;
+    st = trial(p, false, ms);                    // first run: code and caches warm up
+    if (st == DB_OK) st = trial(p, true, t_best);
+    const uint32_t cand[2] = {256u, 512u};
+    for (uint32_t c = 0; c < 5 && st == DB_OK; ++c) {
+        if (!occupied[c]) continue;
+        db_batch_plan keep = p;
+        float t_keep = t_best;
+        for (uint32_t b : cand) {
+            db_batch_plan q = p;
+            q.threads[c] = b;
+            st = trial(q, true, ms);
+            if (st != DB_OK) break;
+            if (ms < 0.98f * t_keep) {
+                keep = q;
+                t_keep = ms;
+            }
+        }
+        p = keep;
+        t_best = t_keep;
+    }
+    if (steps_done) *steps_done = done;
+    if (st != DB_OK) return st;
+    {
+        std::lock_guard<std::mutex> lock(g_plan_mu);
+        g_plans[systems[0]->device] = p;
+    }
+    if (best) *best = p;
+    return DB_OK;
 }
 
 db_status db_sweep_frozen(db_system* s, uint64_t step_key) {

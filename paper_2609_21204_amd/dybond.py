@@ -56,6 +56,14 @@ _U32 = ctypes.c_uint32
 _U64 = ctypes.c_uint64
 _D = ctypes.c_double
 _I = ctypes.c_int
+BATCH_MAX_CLASSES = 8
+
+
+class BatchPlan(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_uint32), ("n_max", ctypes.c_uint32 * BATCH_MAX_CLASSES),
+                ("threads", ctypes.c_uint32 * BATCH_MAX_CLASSES)]
+
+
 _SIGS = {
     "db_create": (_I, [_U32, _U32, _D, _U32, _I, ctypes.POINTER(_P)]),
     "db_destroy": (None, [_P]),
@@ -73,6 +81,10 @@ _SIGS = {
     "db_commit": (_I, [_P]),
     "db_step": (_I, [_P, _U64]),
     "db_step_batch": (_I, [_P, _U32, _U64]),
+    "db_step_batch_plan": (_I, [_P, _U32, _U64, ctypes.POINTER(BatchPlan)]),
+    "db_set_batch_plan": (_I, [_I, ctypes.POINTER(BatchPlan)]),
+    "db_get_batch_plan": (_I, [_I, ctypes.POINTER(BatchPlan)]),
+    "db_batch_autotune": (_I, [_P, _U32, _U32, ctypes.POINTER(BatchPlan), ctypes.POINTER(_U64), _P, _U32]),
     "db_sweep_frozen": (_I, [_P, _U64]),
     "db_set_state": (_I, [_P, _U64, _P, _P, _P, _P, _U64]),
     "db_read_positions": (_I, [_P, _P, _P]),
@@ -209,19 +221,80 @@ def db_step(h, n_steps):
     _check(h, load().db_step(h, n_steps))
 
 
+def _batch_raise(st, hs):
+    # the failing system's message is in its own handle; report the first one
+    for h in hs:
+        msg = load().db_last_error(h)
+        if msg:
+            raise DybondError(st, msg.decode())
+    raise DybondError(st, "")
+
+
+def _plan_struct(plan):
+    """A plan given as a list of (n_max, threads) classes, ascending n_max."""
+    p = BatchPlan()
+    p.n_classes = len(plan)                 # more than BATCH_MAX_CLASSES: the library rejects it
+    for k, (n_max, threads) in enumerate(plan[:BATCH_MAX_CLASSES]):
+        p.n_max[k] = min(int(n_max), 0xFFFFFFFF)
+        p.threads[k] = int(threads)
+    return p
+
+
+def _plan_list(p):
+    return [(int(p.n_max[k]), int(p.threads[k])) for k in range(p.n_classes)]
+
+
 def db_step_batch(handles, n_steps):
     """Advance several committed systems (handles) by n_steps each in one
-    batched launch per chunk of steps; bitwise equal to db_step on each."""
+    graph of batched launches, under the device's stored plan; bitwise equal
+    to db_step on each."""
     hs = list(handles)
     arr = (ctypes.c_void_p * len(hs))(*hs)
     st = load().db_step_batch(arr, len(hs), n_steps)
     if st != 0:
-        # the failing system's message is in its own handle; report the first one
-        for h in hs:
-            msg = load().db_last_error(h)
-            if msg:
-                raise DybondError(st, msg.decode())
-        raise DybondError(st, "")
+        _batch_raise(st, hs)
+
+
+def db_step_batch_plan(handles, n_steps, plan):
+    """db_step_batch under an explicit plan [(n_max, threads), ...]."""
+    hs = list(handles)
+    arr = (ctypes.c_void_p * len(hs))(*hs)
+    p = _plan_struct(plan)
+    st = load().db_step_batch_plan(arr, len(hs), n_steps, ctypes.byref(p))
+    if st != 0:
+        _batch_raise(st, hs)
+
+
+def db_set_batch_plan(device, plan):
+    """Store the device's batch plan (None restores the default)."""
+    p = None if plan is None else ctypes.byref(_plan_struct(plan))
+    st = load().db_set_batch_plan(device, p)
+    if st != 0:
+        raise DybondError(st, "db_set_batch_plan")
+
+
+def db_get_batch_plan(device):
+    p = BatchPlan()
+    st = load().db_get_batch_plan(device, ctypes.byref(p))
+    if st != 0:
+        raise DybondError(st, "db_get_batch_plan")
+    return _plan_list(p)
+
+
+def db_batch_autotune(handles, trial_steps):
+    """Tune the device's batch plan on these systems; returns (plan,
+    steps_done, trial times in ms).  The systems advance by steps_done."""
+    hs = list(handles)
+    arr = (ctypes.c_void_p * len(hs))(*hs)
+    p = BatchPlan()
+    done = _U64(0)
+    ms = np.zeros(16, dtype=np.float64)
+    st = load().db_batch_autotune(arr, len(hs), trial_steps, ctypes.byref(p), ctypes.byref(done), ms.ctypes.data,
+                                  len(ms))
+    if st != 0:
+        _batch_raise(st, hs)
+    n_timed = int(done.value) // trial_steps - 1          # every trial but the first is timed
+    return _plan_list(p), int(done.value), ms[:max(0, n_timed)].tolist()
 
 
 def db_sweep_frozen(h, step_key):

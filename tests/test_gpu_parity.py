@@ -294,20 +294,31 @@ def _assert_same_state(p, b, label):
         assert x.shape == y.shape and np.array_equal(x, y), f"{label}: {name} differ"
 
 
-def test_batched_systems_match_plain_runs():
+_TOP = 2 ** 32 - 1
+# launch plans: the stored default (one class, 1024 threads), three classes
+# run as concurrent graph branches, and one wave per system
+_PLANS = {"default": None, "three-classes": [(600, 256), (2048, 512), (_TOP, 1024)], "one-wave": [(_TOP, 64)]}
+
+
+@pytest.mark.parametrize("plan", list(_PLANS))
+def test_batched_systems_match_plain_runs(plan):
     """db_step_batch on a mixed batch (sizes 300..8k, monomers and chains,
     one kinetic-temperature system) is bitwise equal to db_step on each
-    system, and hands the state back so that plain steps continue equal."""
+    system under any launch plan, and hands the state back so that plain
+    steps continue equal."""
     ws = [inputs.small(seed=6), inputs.small(seed=7, n=300, density=0.2)] + inputs.replica_set(seed=5, count=6)
     kts = [db.DB_KT_SETPOINT] * len(ws) + [db.DB_KT_KINETIC]
     ws = ws + [ws[0]]
-    log("case batch: sizes " + " ".join(str(w.n) for w in ws))
+    log(f"case batch ({plan}): sizes " + " ".join(str(w.n) for w in ws))
     plain = [db.System.from_workload(w, kt_source=k) for w, k in zip(ws, kts)]
     batch = [db.System.from_workload(w, kt_source=k) for w, k in zip(ws, kts)]
     try:
         for p in plain:
             p.step(250)
-        db.db_step_batch([b.h for b in batch], 250)
+        if _PLANS[plan] is None:
+            db.db_step_batch([b.h for b in batch], 250)
+        else:
+            db.db_step_batch_plan([b.h for b in batch], 250, _PLANS[plan])
         for k, (p, b) in enumerate(zip(plain, batch)):
             _assert_same_state(p, b, f"system {k} after 250 steps")
             assert counters(p).sum() > 0
@@ -322,7 +333,8 @@ def test_batched_systems_match_plain_runs():
 
 
 def test_batched_run_across_launch_chunks():
-    """A batched run longer than one launch (2000 steps) equals db_step."""
+    """A batched run longer than one launch (2000 steps), in two graph
+    branches, equals db_step."""
     ws = [inputs.small(seed=8), inputs.replica_set(seed=9, count=1)[0]]
     log("case batch chunks: sizes " + " ".join(str(w.n) for w in ws))
     plain = [db.System.from_workload(w) for w in ws]
@@ -330,9 +342,36 @@ def test_batched_run_across_launch_chunks():
     try:
         for p in plain:
             p.step(2013)
-        db.db_step_batch([b.h for b in batch], 2013)
+        db.db_step_batch_plan([b.h for b in batch], 2013, [(min(w.n for w in ws), 256), (_TOP, 1024)])
         for k, (p, b) in enumerate(zip(plain, batch)):
             _assert_same_state(p, b, f"system {k} after 2013 steps")
     finally:
         for x in plain + batch:
             x.close()
+
+
+def test_batch_autotuner_keeps_results_and_stores_its_plan():
+    """The autotuner's trials are ordinary steps: afterwards every system
+    equals a plain run of as many steps; the plan it picks is stored for
+    the device and used by db_step_batch."""
+    ws = inputs.replica_set(seed=11, count=10)
+    log("case autotune: sizes " + " ".join(str(w.n) for w in ws))
+    plain = [db.System.from_workload(w) for w in ws]
+    batch = [db.System.from_workload(w) for w in ws]
+    try:
+        plan, done, ms = db.db_batch_autotune([b.h for b in batch], 40)
+        occupied = len({min(k for k, m in enumerate((512, 1024, 2048, 4096, _TOP)) if w.n <= m) for w in ws})
+        assert done == 40 * (2 + 2 * occupied) and len(ms) == 1 + 2 * occupied and min(ms) > 0
+        assert [m for m, _ in plan] == [512, 1024, 2048, 4096, _TOP]
+        assert all(t in (256, 512, 1024) for _, t in plan)
+        assert db.db_get_batch_plan(0) == plan
+        db.db_step_batch([b.h for b in batch], 25)
+        for p in plain:
+            p.step(done + 25)
+        for k, (p, b) in enumerate(zip(plain, batch)):
+            _assert_same_state(p, b, f"system {k} after autotuning")
+    finally:
+        db.db_set_batch_plan(0, None)
+        for x in plain + batch:
+            x.close()
+    assert db.db_get_batch_plan(0) == [(_TOP, 1024)]

@@ -90,6 +90,31 @@ def test_batch_entry_point_checks_its_arguments():
         b.close()
 
 
+def test_batch_plans_are_validated_before_any_device_call():
+    top = 2 ** 32 - 1
+    bad = [[], [(100 * (k + 1), 256) for k in range(9)], [(top, 100)], [(top, 2048)], [(top, 0)],
+           [(1024, 256), (512, 512)], [(512, 256), (512, 512)]]
+    for plan in bad:
+        with pytest.raises(db.DybondError) as e:
+            db.db_set_batch_plan(0, plan)
+        assert e.value.name == "DB_EINVAL", plan
+    # a well-formed plan passes and then needs a device
+    with pytest.raises(db.DybondError) as e:
+        db.db_set_batch_plan(0, [(512, 256), (top, 1024)])
+    assert e.value.name == "DB_EDEVICE"
+    with pytest.raises(db.DybondError) as e:
+        db.db_batch_autotune([], 100)
+    assert e.value.name == "DB_EINVAL"
+    w = inputs.small(seed=1)
+    a = _configured(w)
+    try:
+        with pytest.raises(db.DybondError) as e:
+            db.db_step_batch_plan([a.h], 10, [(top, 256)])     # not committed
+        assert e.value.name == "DB_ESTATE"
+    finally:
+        a.close()
+
+
 def test_rate_closure_matches_oracle_bit_for_bit():
     w = inputs.small(seed=1)
     cases = [dict(epsilon=5.0, p_on0=1.0), dict(k_on=3.0, k_off=0.5), dict(k_on=1.5, epsilon=2.0),
