@@ -37,6 +37,10 @@ def parse():
     p.add_argument("--cpu-steps", type=int, default=20)
     p.add_argument("--profile-steps", type=int, default=2000)
     p.add_argument("--skin", type=float, default=None, help="neighbour-list skin (default: the library's)")
+    p.add_argument("--step-threads", type=int, default=0,
+                   help="threads per particle in the step kernel (0: the library's choice)")
+    p.add_argument("--list-batch", type=int, default=0,
+                   help="list entries per thread loaded up front in the step kernel (0: the library's choice)")
     p.add_argument("--replicas", type=int, default=1024,
                    help="replicas of the parameter-sweep batch (0 skips the batched-vs-plain measurement)")
     p.add_argument("--replica-steps", type=int, default=20000)
@@ -172,6 +176,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     s = db.System.from_workload(w, device=0, skin=a.skin)
+    if a.step_threads or a.list_batch:
+        db.db_set_step_shape(s.h, a.step_threads, a.list_batch)
     s.step(a.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -192,6 +198,7 @@ def main():
             kern[name] = {"launches": cnt, "avg_us": 1000.0 * ms / cnt}
     db.db_kernel_timing(s.h, 0)
     obs = s.observables()
+    tpp, qb = db.db_get_step_shape(s.h)
     s.close()
 
     bpp, slots = algorithmic_bytes_per_particle(w)
@@ -218,7 +225,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_step", "kernel_avg_us": step_us,
+                     "kernel": "k_step", "kernel_avg_us": step_us, "threads_per_particle": tpp, "list_batch": qb,
                      "alg_bytes_per_particle": bpp, "bond_slots_per_particle": slots},
         "kernels": kern,
         "state": {"bonds": obs["n_bonds"].tolist(), "bonded_fraction": obs["bonded_fraction"].tolist(),

@@ -167,6 +167,19 @@ DB_API db_status db_set_neighbor_list(db_system* sys, double skin, uint32_t max_
  * Before db_commit only (DB_ESTATE after); DB_EINVAL out of range. */
 DB_API db_status db_set_matching(db_system* sys, uint32_t grid_rounds, uint32_t lds_limit);
 
+/* Launch shape of the step kernel and the proposal kernel of the sweep:
+ * threads that share one particle (1, 2, 4, 8, 16 or 32; 0 = automatic: 4,
+ * or more for small systems so that a launch fills the GPU) and, with 4
+ * threads per particle, how many neighbour-list entries each thread loads
+ * before its first gather (1, 2 or 4; 0 = automatic: 4; longer lists are
+ * then taken in further rounds).  Any shape gives the same result bit for
+ * bit (forces are summed exactly); it changes only the speed.  May be
+ * called before or after db_commit.  Errors: DB_EINVAL, DB_EDEVICE. */
+DB_API db_status db_set_step_shape(db_system* sys, uint32_t threads_per_particle, uint32_t list_batch);
+/* The shape in use (after commit; list_batch as resolved) or requested
+ * (before; 0 = automatic). */
+DB_API db_status db_get_step_shape(const db_system* sys, uint32_t* threads_per_particle, uint32_t* list_batch);
+
 /* Validate the configuration and close the rate parameters of every reaction
  * (Eq. epsilon, Eq. probs) without touching a GPU.  Errors: DB_EINVAL (bad
  * or missing parameter, under-determined or inconsistent rates, box smaller

@@ -79,6 +79,8 @@ struct db_system {
     uint32_t cellcap_user = 0;             // 0 = automatic
     double skin = 0.4;                     // neighbour-list skin
     uint32_t nlmax_user = 0;               // neighbour-list slots per particle, 0 = automatic
+    uint32_t tpp_user = 0;                 // threads per particle in k_step and k_propose, 0 = automatic
+    uint32_t qb_user = 0;                  // list entries per thread issued up front in k_step, 0 = automatic
     uint32_t match_rounds = 1;             // full-grid matching rounds before the one-workgroup finish
     uint32_t finish_lds = kFinishLds;      // largest live list the finish matches in LDS
     bool tags_dirty = false;               // device tag/rtag changed since the host mirrors were read
@@ -139,9 +141,11 @@ struct TimerScope {
 // With timing on, the launch carries a start and a stop event that the
 // runtime stamps when the kernel itself begins and ends (not when the stream
 // reaches the launch), so the per-kernel times are kernel execution times.
-#define LAUNCH(sys, kern, grid, block, ...)                                                      \
+#define LAUNCH(sys, kern, grid, block, ...) LAUNCH_AS(sys, #kern, kern, grid, block, __VA_ARGS__)
+// the same, with the name the kernel is timed under given explicitly
+#define LAUNCH_AS(sys, tname, kern, grid, block, ...)                                            \
     do {                                                                                         \
-        TimerScope ts_((sys), #kern);                                                            \
+        TimerScope ts_((sys), tname);                                                            \
         if (ts_.a)                                                                               \
             hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (sys)->stream, ts_.a, ts_.b, \
                                   0u, __VA_ARGS__);                                              \
@@ -349,6 +353,14 @@ void choose_tiles(const db_system* s, Params& P) {
     }
 }
 
+// threads per particle: 4, or more for small systems so that a launch has
+// at least 2^19 threads
+uint32_t auto_tpp(uint32_t n) {
+    uint32_t t = 4;
+    while (t < 32 && (uint64_t)n * t < 524288ull) t *= 2;
+    return t;
+}
+
 void fill_params(db_system* s) {
     Params& P = s->P;
     P = Params{};
@@ -430,8 +442,10 @@ void fill_params(db_system* s) {
             const double rl = need > 0.0 ? need + skin : 0.0;
             P.rl2[a * kMaxTypes + b] = (float)(rl * rl * (1.0 + 1e-4));
         }
-    P.tpp = 4;
-    while (P.tpp < 32 && (uint64_t)s->n * P.tpp < 524288ull) P.tpp *= 2;
+    P.tpp = auto_tpp(s->n);
+    if (s->tpp_user) P.tpp = s->tpp_user;
+    P.tpp_step = P.tpp;
+    P.qb_step = P.tpp_step == 4 ? s->qb_user : 0u;
     P.disp2 = (float)std::max(0.0, (0.5 * skin - 1e-4) * (0.5 * skin - 1e-4));
     // neighbour slots: room for 2.5x the mean count of an ideal gas at this
     // density plus 32, at least 64 (or exactly what the caller asked for)
@@ -568,6 +582,8 @@ void launch_sweep(db_system* s, int xcur, int sp) {
     for (int slot = 0; slot < (int)P.nrx; ++slot) {
         const unsigned gp = (unsigned)(((uint64_t)P.n * P.tpp + kBlock - 1) / kBlock);
         switch (P.tpp) {
+            case 1: LAUNCH(s, k_propose<1>, gp, kBlock, P, s->D, slot, xcur, sp); break;
+            case 2: LAUNCH(s, k_propose<2>, gp, kBlock, P, s->D, slot, xcur, sp); break;
             case 4: LAUNCH(s, k_propose<4>, gp, kBlock, P, s->D, slot, xcur, sp); break;
             case 8: LAUNCH(s, k_propose<8>, gp, kBlock, P, s->D, slot, xcur, sp); break;
             case 16: LAUNCH(s, k_propose<16>, gp, kBlock, P, s->D, slot, xcur, sp); break;
@@ -611,9 +627,17 @@ void launch_step(db_system* s) {
     const int sp = (int)(t & 1);
     const bool sweep = P.nrx > 0 && ((t + 1) % P.period == 0);
     const int ake = (sweep && P.kt_kinetic) ? 1 : 0;
-    const unsigned gs = (unsigned)(((uint64_t)P.n * P.tpp + kBlock - 1) / kBlock);
-    switch (P.tpp) {
-        case 4: LAUNCH(s, k_step<4>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
+    const unsigned gs = (unsigned)(((uint64_t)P.n * P.tpp_step + kBlock - 1) / kBlock);
+    switch (P.tpp_step) {
+        case 1: LAUNCH_AS(s, "k_step", k_step1, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
+        case 2: LAUNCH(s, k_step<2>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
+        case 4:
+            if (P.qb_step == 1)
+                LAUNCH_AS(s, "k_step", (k_step<4, 1>), gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake);
+            else if (P.qb_step == 2)
+                LAUNCH_AS(s, "k_step", (k_step<4, 2>), gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake);
+            else LAUNCH(s, k_step<4>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake);
+            break;
         case 8: LAUNCH(s, k_step<8>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
         case 16: LAUNCH(s, k_step<16>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
         default: LAUNCH(s, k_step<32>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
@@ -824,6 +848,33 @@ db_status db_set_matching(db_system* s, uint32_t grid_rounds, uint32_t lds_limit
     if (lds_limit > kFinishLds) return fail(s, DB_EINVAL, "lds_limit above %u", kFinishLds);
     s->match_rounds = grid_rounds;
     s->finish_lds = lds_limit;
+    return DB_OK;
+}
+
+db_status db_set_step_shape(db_system* s, uint32_t tpp, uint32_t list_batch) {
+    if (!s) return DB_EINVAL;
+    if (tpp != 0 && tpp != 1 && tpp != 2 && tpp != 4 && tpp != 8 && tpp != 16 && tpp != 32)
+        return fail(s, DB_EINVAL, "threads per particle must be 0 (automatic), 1, 2, 4, 8, 16 or 32");
+    if (list_batch != 0 && list_batch != 1 && list_batch != 2 && list_batch != 4)
+        return fail(s, DB_EINVAL, "list batch must be 0 (automatic), 1, 2 or 4");
+    if (s->dead) return fail(s, DB_EDEVICE, "device error earlier on this handle");
+    s->tpp_user = tpp;
+    s->qb_user = list_batch;
+    if (s->committed) {
+        HIPCHK(s, hipSetDevice(s->device));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        destroy_graphs(s);
+        s->P.tpp = s->P.tpp_step = tpp ? tpp : auto_tpp(s->n);
+        s->P.qb_step = s->P.tpp_step == 4 ? list_batch : 0u;
+    }
+    return DB_OK;
+}
+
+db_status db_get_step_shape(const db_system* s, uint32_t* tpp, uint32_t* list_batch) {
+    if (!s || !tpp || !list_batch) return DB_EINVAL;
+    *tpp = s->committed ? s->P.tpp_step : s->tpp_user;
+    *list_batch = s->committed ? (s->P.qb_step ? s->P.qb_step : (s->P.tpp_step < 4 ? 4u : std::max(1u, 16u / s->P.tpp_step)))
+                               : s->qb_user;
     return DB_OK;
 }
 

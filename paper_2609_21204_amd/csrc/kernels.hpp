@@ -783,13 +783,14 @@ __device__ __forceinline__ void bond_force_tab(const Params& P, const StepTabs& 
 // integration.
 //   xin = buffer of x_t, lnext = cell list receiving x_{t+1}, lclr = list
 //   cleared for the step after, sp = t mod 2, f3 = t mod 3.
-template <int TPP>
+//   QB (if not 0) = list entries per thread issued up front.
+template <int TPP, int QB = 0>
 __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
                                               int f3, int accum_ke) {
     static_assert(TPP >= 1 && TPP <= 64, "256 threads per workgroup");
     constexpr int PPB = 256 / TPP;                       // particles per workgroup
     constexpr uint32_t kIntThreads = PPB > 64 ? PPB : 64;   // whole waves that integrate
-    constexpr int Q = 16 / TPP > 1 ? 16 / TPP : 1;      // list entries per thread issued up front
+    constexpr int Q = QB ? QB : (TPP < 4 ? 4 : (16 / TPP > 1 ? 16 / TPP : 1));   // list entries per thread issued up front
     constexpr int BQ = 8 / TPP > 1 ? 8 / TPP : 1;       // bond slots per thread issued up front
     __shared__ StepTabs T;
     __shared__ unsigned long long fsum[3][PPB];
@@ -889,6 +890,102 @@ __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int x
         bin_particle(P, D, lnext, i2, po);
         const float4 r = r2;
         const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
+        if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[f3 == 2 ? 0 : f3 + 1] = 1u;
+    }
+    if (accum_ke) {
+        for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
+        if (__lane_id() == 0 && ke) atomicAdd(D.ke_fix, ke);
+    }
+}
+
+// One BAOAB step t -> s = t + 1 with one thread per particle, for short
+// neighbour lists: the thread issues its particle's loads (position,
+// velocity, list position, tag, list length, the first 4 list entries and 4
+// bond words) together, then the 4 neighbour and 4 partner positions
+// together, takes further list entries 4 at a time the same way, and goes
+// on to the integration with its force in registers (no LDS reduction, one
+// barrier).  Same arguments and the same result bit for bit as k_step<TPP>.
+__global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
+                                               int f3, int accum_ke) {
+    constexpr int Q = 4, BQ = 4;
+    __shared__ StepTabs T;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t i = xcd_block() * 256u + tid;
+    const uint32_t gtid = blockIdx.x * blockDim.x + tid;
+    const size_t n = P.n;
+    const float4* __restrict__ X = D.x[xin];
+    const uint32_t nslot = P.stat_max + P.cap_max;
+    const bool live = i < P.n;
+    float4 pi = make_float4(0.f, 0.f, 0.f, 0.f), ui = pi, ri = pi;
+    uint32_t tg = 0, m = 0;
+    uint32_t nb[Q], bw[BQ];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) nb[q] = 0u;
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) bw[q] = kEmpty;
+    if (live) {
+        pi = X[i];
+        ui = D.u[i];
+        ri = D.xref[i];
+        tg = D.tag[i];
+        m = D.nl_cnt[i];
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if ((uint32_t)q < P.nlmax) nb[q] = D.nl[(size_t)q * n + i];
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
+            const uint32_t b = (uint32_t)q;
+            if (b < P.stat_max) bw[q] = D.stat[b * n + i];
+            else if (b < nslot) bw[q] = D.dyn[(b - P.stat_max) * n + i];
+        }
+    }
+    stage_tabs(D, T, tid);
+    const unsigned long long s = D.stepv[sp] + 1ull;
+    if (gtid == 0) {
+        D.stepv[sp ^ 1] = s;
+        D.rflag[f3] = 0u;               // consumed by the k_nlist of step t
+    }
+    for (uint32_t c = gtid; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
+    __syncthreads();
+    unsigned long long ke = 0ull;
+    if (live) {
+        const uint32_t ti = type_of(pi);
+        float4 pj[Q], pb[BQ];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) pj[q] = X[(uint32_t)q < m ? nb[q] : i];
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) pb[q] = X[bw[q] != kEmpty ? (bw[q] & kIdxMask) : i];
+        long long fx = 0, fy = 0, fz = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if ((uint32_t)q < m) pair_force_tab(P, T, D.err, pi, pj[q], ti, fx, fy, fz);
+        for (uint32_t k0 = Q; k0 < m; k0 += Q) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) nb[q] = D.nl[(size_t)min(k0 + (uint32_t)q, m - 1u) * n + i];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) pj[q] = X[nb[q]];
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (k0 + (uint32_t)q < m) pair_force_tab(P, T, D.err, pi, pj[q], ti, fx, fy, fz);
+        }
+        auto bond = [&](uint32_t b, uint32_t w, float4 pw) {
+            const uint32_t j = w & kIdxMask;
+            if (b < P.stat_max) bond_force_tab(P, T, D, pi, pw, w >> 24, i, j, fx, fy, fz);
+            else if (b - P.stat_max < T.cap[ti])
+                bond_force_tab(P, T, D, pi, pw, T.rbt[(w >> 24) & 0x7Fu], i, j, fx, fy, fz);
+        };
+#pragma unroll
+        for (int q = 0; q < BQ; ++q)
+            if (bw[q] != kEmpty) bond((uint32_t)q, bw[q], pb[q]);
+        for (uint32_t b = BQ; b < nslot; ++b) {
+            const uint32_t w = b < P.stat_max ? D.stat[b * n + i] : D.dyn[(b - P.stat_max) * n + i];
+            if (w != kEmpty) bond(b, w, X[w & kIdxMask]);
+        }
+        const Force3 F = fix_to_force(D, fx, fy, fz);
+        float4 po;
+        ke = advance_particle(P, T, D, xin, i, pi, ti, F, ui, tg, s, accum_ke, po);
+        bin_particle(P, D, lnext, i, po);
+        const float dx = mi_delta_f(ri.x, po.x, P), dy = mi_delta_f(ri.y, po.y, P), dz = mi_delta_f(ri.z, po.z, P);
         if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[f3 == 2 ? 0 : f3 + 1] = 1u;
     }
     if (accum_ke) {
@@ -1001,7 +1098,7 @@ __device__ __forceinline__ unsigned long long match_key(const Params& P, int a, 
 // that it waits for about four memory round trips.  Returns the chosen
 // partner (the same on every thread of the group) or -1; `tgi` receives the
 // site's tag.
-template <int TPP, int Q = (16 / TPP > 1 ? 16 / TPP : 1)>
+template <int TPP, int Q = (TPP < 4 ? 4 : (16 / TPP > 1 ? 16 / TPP : 1))>
 __device__ __forceinline__ int propose_site(const Params& P, const Dev& D, int a, const float4* __restrict__ X,
                                             uint32_t i, uint32_t lane, uint32_t& tgi_out) {
     const size_t n = P.n;

@@ -76,6 +76,8 @@ _SIGS = {
     "db_set_cell_capacity": (_I, [_P, _U32]),
     "db_set_neighbor_list": (_I, [_P, _D, _U32]),
     "db_set_matching": (_I, [_P, _U32, _U32]),
+    "db_set_step_shape": (_I, [_P, _U32, _U32]),
+    "db_get_step_shape": (_I, [_P, ctypes.POINTER(_U32), ctypes.POINTER(_U32)]),
     "db_validate": (_I, [_P]),
     "db_get_reaction": (_I, [_P, _U32, ctypes.POINTER(ReactionDesc), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "db_commit": (_I, [_P]),
@@ -192,6 +194,17 @@ def db_set_integrator(h, dt, kT, gamma, sweep_period, kt_source=DB_KT_SETPOINT):
 
 def db_set_cell_capacity(h, slots):
     _check(h, load().db_set_cell_capacity(h, slots))
+
+
+def db_set_step_shape(h, threads_per_particle, list_batch=0):
+    _check(h, load().db_set_step_shape(h, threads_per_particle, list_batch))
+
+
+def db_get_step_shape(h):
+    """(threads per particle, list batch) of the step kernel."""
+    t, q = _U32(), _U32()
+    _check(h, load().db_get_step_shape(h, ctypes.byref(t), ctypes.byref(q)))
+    return int(t.value), int(q.value)
 
 
 def db_set_neighbor_list(h, skin=-1.0, max_neighbors=0):

@@ -350,6 +350,34 @@ def test_batched_run_across_launch_chunks():
             x.close()
 
 
+@pytest.mark.parametrize("shape", [(1, 0), (2, 0), (4, 1), (4, 2), (8, 0)])
+def test_step_shape_does_not_change_results(shape):
+    """Any launch shape of the step and proposal kernels (threads per
+    particle, list entries loaded up front) gives the same trajectory bit for
+    bit, also when switched during a run (telechelic: static FENE bonds and
+    valence-4 crosslinkers, so bond slots and list entries beyond the first
+    batch are taken too)."""
+    w = inputs.telechelic(seed=3)
+    log(f"case step shape {shape}: telechelic n={w.n}")
+    ref = db.System.from_workload(w)
+    alt = db.System.from_workload(w)
+    try:
+        db.db_set_step_shape(alt.h, *shape)
+        tpp, qb = db.db_get_step_shape(alt.h)
+        assert tpp == shape[0] and (shape[1] == 0 or qb == shape[1])
+        ref.step(130)
+        alt.step(130)
+        _assert_same_state(ref, alt, f"shape {shape}, 130 steps")
+        db.db_set_step_shape(alt.h, 0, 0)
+        assert db.db_get_step_shape(alt.h) == db.db_get_step_shape(ref.h)
+        ref.step(70)
+        alt.step(70)
+        _assert_same_state(ref, alt, "back to the automatic shape, 200 steps")
+    finally:
+        ref.close()
+        alt.close()
+
+
 def test_batch_autotuner_keeps_results_and_stores_its_plan():
     """The autotuner's trials are ordinary steps: afterwards every system
     equals a plain run of as many steps; the plan it picks is stored for
