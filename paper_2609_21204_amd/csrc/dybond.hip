@@ -580,7 +580,7 @@ void launch_sweep(db_system* s, int xcur, int sp) {
     const Params& P = s->P;
     const unsigned g = grid_of(P.n);
     for (int slot = 0; slot < (int)P.nrx; ++slot) {
-        const unsigned gp = (unsigned)(((uint64_t)P.n * P.tpp + kBlock - 1) / kBlock);
+        const unsigned gp = grid_of(P.n);       // 256 sites per workgroup
         switch (P.tpp) {
             case 1: LAUNCH(s, k_propose<1>, gp, kBlock, P, s->D, slot, xcur, sp); break;
             case 2: LAUNCH(s, k_propose<2>, gp, kBlock, P, s->D, slot, xcur, sp); break;

@@ -1199,30 +1199,50 @@ __device__ __forceinline__ int propose_site(const Params& P, const Dev& D, int a
 
 // Proposal phase fused with the first matching round: proposals and their
 // priority keys (Philox of the MATCH stream), posted with 64-bit atomicMin at
-// both sites for round 1.
+// both sites for round 1.  A workgroup owns 256 consecutive sites: one
+// thread per site clears the site's sweep state and tests whether it can
+// propose (a type of the reaction, free valence); the sites that can are
+// listed in LDS, and then TPP threads per listed site scan its neighbour
+// list.  Full or unreactive sites, most of a bonded system, so cost one
+// thread each.
 template <int TPP>
 __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur, int sp) {
+    constexpr uint32_t kSites = 256, kPerPass = 256 / TPP;
+    __shared__ uint32_t list[kSites];
+    __shared__ uint32_t count;
     const unsigned long long s = D.stepv[sp];
     const int a = sweep_reaction(P, s, slot);
-    const uint32_t tg = xcd_block() * blockDim.x + threadIdx.x;
-    const uint32_t i = tg / TPP, lane = tg % TPP;
-    if (tg == 0) D.live_count[0] = 0u;
-    if (i >= P.n) return;
-    if (lane == 0) {
-        D.best[2][i] = kNoKey;
-        D.claimed[i] = 0;
-        D.estate[i] = kEdgeNone;
-        D.prop[i] = -1;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t i0 = xcd_block() * kSites + tid;
+    if (blockIdx.x == 0 && tid == 0) D.live_count[0] = 0u;
+    if (tid == 0) count = 0u;
+    __syncthreads();
+    if (i0 < P.n) {
+        D.best[2][i0] = kNoKey;
+        D.claimed[i0] = 0;
+        D.estate[i0] = kEdgeNone;
+        D.prop[i0] = -1;
+        const uint32_t ti = type_of(D.x[xcur][i0]);
+        const uint32_t occ = D.occ[i0];
+        if ((ti == P.ra[a] || ti == P.rb[a]) && occ < P.cap[ti]) list[atomicAdd(&count, 1u)] = i0;
     }
-    uint32_t tgi = 0;
-    const int best_j = propose_site<TPP>(P, D, a, D.x[xcur], i, lane, tgi);
-    if (lane != 0 || best_j < 0) return;
-    const unsigned long long key = match_key(P, a, s, tgi);
-    D.prop[i] = best_j;
-    D.key[i] = key;
-    D.estate[i] = kEdgeLive;
-    atomicMin(&D.best[1][i], key);
-    atomicMin(&D.best[1][best_j], key);
+    __syncthreads();
+    const uint32_t nlist = count;
+    const uint32_t lane = tid % TPP;
+    for (uint32_t c0 = 0; c0 < nlist; c0 += kPerPass) {
+        const uint32_t p = c0 + tid / TPP;
+        if (p >= nlist) break;                 // whole TPP groups leave together
+        const uint32_t i = list[p];
+        uint32_t tgi = 0;
+        const int best_j = propose_site<TPP>(P, D, a, D.x[xcur], i, lane, tgi);
+        if (lane != 0 || best_j < 0) continue;
+        const unsigned long long key = match_key(P, a, s, tgi);
+        D.prop[i] = best_j;
+        D.key[i] = key;
+        D.estate[i] = kEdgeLive;
+        atomicMin(&D.best[1][i], key);
+        atomicMin(&D.best[1][best_j], key);
+    }
 }
 
 // Acceptance of a claimed pair (Eq. pon): returns true when the bond forms,
