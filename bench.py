@@ -30,7 +30,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10000)
     p.add_argument("--warmup", type=int, default=200)
-    p.add_argument("--workload", default="gel", choices=["gel", "telechelic", "small"])
+    p.add_argument("--workload", default="gel", choices=["gel", "gel-lattice", "telechelic", "small"])
     p.add_argument("--n", type=int, default=0, help="particle count for the gel workload (default 200000)")
     p.add_argument("--seed", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -105,6 +105,23 @@ def cpu_baseline(w, steps):
                       f"{steps // w.period} bonding sweeps) from its initial state, {dt:.1f} s"}
 
 
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Achievable HBM bandwidth: a plain device-to-device copy of `mib` MiB
+    (far larger than the 256 MB last-level cache), read + write bytes over
+    the time of `reps` copies."""
+    src = torch.empty(mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del src, dst
+    return 2.0 * (mib << 20) * reps / dt / 1e9
+
+
 def batch_vs_plain(a, db, inputs, torch):
     """Replicas/hour of the parameter-sweep batch run by db_step_batch (one
     launch per 2000 steps, all replicas together) against the same replicas
@@ -165,6 +182,8 @@ def main():
         sys.exit(1)
     if a.workload == "gel":
         w = inputs.gel(seed=a.seed, n=a.n or 200000)
+    elif a.workload == "gel-lattice":
+        w = inputs.gel_lattice(seed=a.seed, n=a.n or 200000)
     else:
         w = inputs.WORKLOADS[a.workload](seed=a.seed)
     tag = f"{w.name}{w.n // 1000}k"
@@ -175,6 +194,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = copy_bandwidth(torch)
     s = db.System.from_workload(w, device=0, skin=a.skin)
     if a.step_threads or a.list_batch:
         db.db_set_step_shape(s.h, a.step_threads, a.list_batch)
@@ -223,7 +243,7 @@ def main():
                    "sweep_period": w.period, "dt": w.dt, "kT": w.kT, "gamma": w.gamma,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
+                     "frac": achieved / HBM_PEAK_GBS, "copy_gbs": copy_gbs,
                      "traffic": traffic,
                      "kernel": "k_step", "kernel_avg_us": step_us, "threads_per_particle": tpp, "list_batch": qb,
                      "alg_bytes_per_particle": bpp, "bond_slots_per_particle": slots},

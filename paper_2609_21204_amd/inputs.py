@@ -224,19 +224,26 @@ def telechelic(seed=1, n_chains=1000, chain_len=10, n_cross=500, density=0.3,
 
 
 def gel(seed=1, n=200000, density=0.3, eps_ab=8.0, eps_ac=4.0):
-    """Multi-partner gel: A (valence 6) with B (valence 2) and C (valence 1)."""
-    rng = np.random.default_rng(seed)
+    """Multi-partner gel: A (valence 6) with B (valence 2) and C (valence 1),
+    uniform positions with overlap rejection."""
+    return _gel(seed, n, density, eps_ab, eps_ac)
+
+
+def _gel(seed, n, density, eps_ab, eps_ac, pos=None, tid=None, rng=None):
+    if rng is None:
+        rng = np.random.default_rng(seed)
     L = box_length(n, density)
     n_a = n // 5
     n_b = n // 2
     n_c = n - n_a - n_b
     types = [(6, 1.0, 1.0, 1.0), (2, 0.5, 1.0, 1.0), (1, 0.5, 1.0, 1.0)]
     sigma = np.array([t[1] for t in types])
-    tid = np.array([0] * n_a + [1] * n_b + [2] * n_c, dtype=np.uint32)
-    grid = _Grid(L, 1.0)
-    order = rng.permutation(n)
-    pos = np.zeros((n, 3))
-    pos[order] = np.array(_place_uniform(grid, tid[order], sigma, rng, L))
+    if pos is None:
+        tid = np.array([0] * n_a + [1] * n_b + [2] * n_c, dtype=np.uint32)
+        grid = _Grid(L, 1.0)
+        order = rng.permutation(n)
+        pos = np.zeros((n, 3))
+        pos[order] = np.array(_place_uniform(grid, tid[order], sigma, rng, L))
     r0 = 0.5 * (1.0 + 0.5)
     masses = np.ones(n)
     return Workload(
@@ -252,6 +259,33 @@ def gel(seed=1, n=200000, density=0.3, eps_ab=8.0, eps_ac=4.0):
                  k_on=math.nan, k_off=math.nan, epsilon=eps_ac, p_on0=0.25, self_avoid=0),
         ],
         steps=10000, seed=seed)
+
+
+def gel_lattice(seed=1, n=200000, density=0.3, eps_ab=8.0, eps_ac=4.0):
+    """The gel chemistry of `gel` placed without rejection sampling, for
+    systems of millions of particles: n of the m^3 sites of a cubic lattice
+    of spacing a = L / m (m^3 >= n, a >= 1.2 at density <= 0.5) are taken at
+    random, types are dealt out at random, and each position is jittered by
+    up to (a - 1.05) / 2 per axis, so that no two particles come closer than
+    1.05 (above every WCA sigma_ij <= 1) and nothing overlaps."""
+    rng = np.random.default_rng(seed)
+    L = box_length(n, density)
+    m = int(math.floor(L / 1.2))
+    while m ** 3 < n:
+        m -= 1
+    a = L / m
+    if a < 1.15:
+        raise ValueError("density too high for the lattice placement")
+    site = rng.choice(m ** 3, n, replace=False)
+    ijk = np.stack([site % m, (site // m) % m, site // (m * m)], axis=1).astype(np.float64)
+    jit = 0.5 * (a - 1.05)
+    pos = (ijk + 0.5) * a - 0.5 * L + rng.uniform(-jit, jit, (n, 3))
+    n_a = n // 5
+    n_b = n // 2
+    tid = np.array([0] * n_a + [1] * n_b + [2] * (n - n_a - n_b), dtype=np.uint32)[rng.permutation(n)]
+    w = _gel(seed, n, density, eps_ab, eps_ac, pos=pos, tid=tid, rng=rng)
+    w.name = "gel-lattice"
+    return w
 
 
 def _snake_lattice(L, spacing_min):
@@ -351,4 +385,4 @@ def replica_set(seed=1, count=1024, n_min=256, n_max=8192):
             for k in range(count)]
 
 
-WORKLOADS = {"small": small, "telechelic": telechelic, "gel": gel}
+WORKLOADS = {"small": small, "telechelic": telechelic, "gel": gel, "gel-lattice": gel_lattice}

@@ -5,9 +5,9 @@ point -- bond free energy eps (in kT), number density rho, crosslinker
 valence cap_B (A sites have valence 1) and temperature kT -- to the two
 observables a sweep is run for: the bonded fraction of the A-B reaction and
 the largest-cluster fraction (largest connected component of static plus
-dynamic bonds over N).  Both are end-of-run averages of replicas simulated
-by the library itself (db_step_batch), so the network learns what the
-simulator produces.
+dynamic bonds over N).  Both are averages over the last quarter of runs of
+replicas simulated by the library itself (db_step_batch), so the network
+learns what the simulator produces.
 
 The network then picks where the next plain simulations are spent: a large
 uniform pool of candidate points is scored and the points predicted closest
@@ -85,15 +85,14 @@ def _workload(p, k):
 def simulate(points, steps=20000, samples=5, plain=False, chunk=1024, device=0, log=None):
     """Observables of every point: (len(points), 2) end-of-run averages of
     (bonded fraction, largest-cluster fraction) over `samples` equally spaced
-    reads in the second half of a `steps`-step run.
+    reads in the last quarter of a `steps`-step run.
 
     plain=False runs each chunk of replicas together (db_step_batch);
     plain=True runs every replica on its own with db_step.  Both give the
     same trajectory bit for bit, so they differ only in time."""
-    half = steps // 2
-    span = half // samples
+    span = (steps // 4) // samples
     if span < 1:
-        raise ValueError("steps must be at least 2 * samples")
+        raise ValueError("steps must be at least 4 * samples")
     first = steps - span * samples
     out = np.zeros((len(points), 2))
     for c0 in range(0, len(points), chunk):
