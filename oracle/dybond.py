@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY: the product path never imports this module.
 
 What it computes (paper sections in parentheses):
 
-* forces: WCA on every pair closer than 2**(1/6) sigma_ij, harmonic and FENE
-  bonds (the potentials of the paper's examples, Sec. 4);
+* forces: WCA on every pair closer than 2**(1/6) sigma_ij, harmonic, FENE
+  and tether bonds (the bond evaluators the paper's method accepts, Sec. 2.2);
 * BAOAB Langevin integration (the paper uses the integrator of its MD
   engine; BAOAB, Leimkuhler & Matthews 2013, is the reading here);
 * every ``sweep_period`` steps, one bonding sweep (Sec. 2.3): for each
@@ -13,7 +13,10 @@ What it computes (paper sections in parentheses):
   acceptance with P_on(r) = P0_on exp(-U_b(r)/kT) (Eq. pon) -> breaking of
   the bonds of that reaction present at the start of the sweep with
   P0_off (Eq. pon); rates from k n dt (Eq. probs) and K = e^eps
-  (Eq. epsilon);
+  (Eq. epsilon); optional rate modifiers per reaction (Sec. 2.4): melting,
+  rates interpolated between their initial and melted values by
+  g(T) = [tanh(lambda (T - T_melt)) + 1] / 2 (Eqs. gT, kT), or slip bonds,
+  P_off(r) = P0_off exp(a sqrt(U_b(r)/kT)) (Eq. slip);
 * observables: bond counts, bonded fraction, largest cluster, energies.
 
 Particle index == tag throughout.  All arithmetic is FP64 numpy; library
@@ -36,7 +39,13 @@ implements them; the central ones are:
 * distances: positions converted to FP64, d = x_j - x_i,
   d -= rint(d / L) * L (as d * (1/L)), r = sqrt((dx*dx + dy*dy) + dz*dz),
   window r_min <= r <= r_max inclusive;
-* kT = 0: the Boltzmann factor is 1 for U_b <= 0 and 0 otherwise.
+* kT = 0: the Boltzmann factor is 1 for U_b <= 0 and 0 otherwise; the slip
+  factor is 1 for U_b = 0 and infinite (P_off = 1) for U_b > 0 (a > 0);
+* the target length r0 of a proposal is the minimum of the reaction's bond
+  potential: r0 (harmonic), 0 (FENE), the middle of the flat region
+  (l_c1 + l_c0)/2 (tether);
+* the temperature of the modifiers is the sweep's kT (set point, or the
+  kinetic temperature in that mode), with k_B = 1.
 """
 
 import math
@@ -52,6 +61,7 @@ from .philox import (KIND_MATCH, KIND_OFF, KIND_ON, KIND_THERMO, box_muller3,
 
 BOND_HARMONIC = 0
 BOND_FENE = 1
+BOND_TETHER = 2
 
 WCA_RC = 2.0 ** (1.0 / 6.0)
 
@@ -126,6 +136,29 @@ def resolve_rates(k_on, k_off, epsilon, p_on0, dt, period):
     return k_on, k_off, epsilon, p_on, p_off
 
 
+def melt_switch(lam, T_melt, T):
+    """g(T) = [tanh(lambda (T - T_melt)) + 1] / 2 (Eq. gT)."""
+    return 0.5 * (math.tanh(lam * (T - T_melt)) + 1.0)
+
+
+def melted_probabilities(p_on_init, p_off_init, p_on_melt, p_off_melt, lam, T_melt, T):
+    """Per-sweep probabilities at temperature T with the melting modifier:
+    each rate is k_init (1 - g) + k_melt g (Eq. kT), and P0 = k n dt
+    (Eq. probs) is linear in k, so the same mix applies to the P0."""
+    g = melt_switch(lam, T_melt, T)
+    return p_on_init * (1.0 - g) + p_on_melt * g, p_off_init * (1.0 - g) + p_off_melt * g
+
+
+def slip_probability(p_off0, a, U, kT):
+    """P_off(r) = P0_off exp(a sqrt(U_b(r) / kT)) (Eq. slip), capped at 1;
+    for kT = 0 the factor is 1 when U_b = 0 and unbounded otherwise."""
+    if kT > 0.0:
+        return min(1.0, p_off0 * math.exp(a * math.sqrt(U / kT)))
+    if U > 0.0 and a > 0.0:
+        return 1.0
+    return p_off0
+
+
 class OracleSystem:
     """A periodic cubic box of N particles with static and dynamic bonds."""
 
@@ -139,8 +172,9 @@ class OracleSystem:
         self.sigma = np.ones(n_types)
         self.eps = np.ones(n_types)
         self.mass = np.ones(n_types)
-        self.bond_kinds = []      # (kind, k, r0 or R0)
+        self.bond_kinds = []      # (kind, k, r0 or R0[, l_min, l_c1, l_c0, l_max])
         self.reactions = []
+        self.modifiers = {}       # reaction -> ("melt", lam, T_melt, k_on_melt, k_off_melt) | ("slip", a)
         self.static = []          # (i, j, bond_type)
         self.x = None
         self.v = None
@@ -161,6 +195,24 @@ class OracleSystem:
     def add_bond_type(self, kind, k, r0):
         self.bond_kinds.append((int(kind), float(k), float(r0)))
         return len(self.bond_kinds) - 1
+
+    def add_tether_bond_type(self, k_b, l_min, l_c1, l_c0, l_max):
+        """Tether bond: U = U_rep + U_att with
+        U_att(r) = k_b exp(1/(l_c0 - r)) / (l_max - r) for r > l_c0,
+        U_rep(r) = k_b exp(1/(r - l_c1)) / (r - l_min) for r < l_c1,
+        zero between l_c1 and l_c0; defined on l_min < r < l_max."""
+        self.bond_kinds.append((BOND_TETHER, float(k_b), 0.5 * (l_c1 + l_c0),
+                                float(l_min), float(l_c1), float(l_c0), float(l_max)))
+        return len(self.bond_kinds) - 1
+
+    def set_melting(self, a, lam, T_melt, k_on_melt, k_off_melt):
+        self.modifiers[a] = ("melt", float(lam), float(T_melt), float(k_on_melt), float(k_off_melt))
+
+    def set_slip(self, a, coeff):
+        self.modifiers[a] = ("slip", float(coeff))
+
+    def set_temperature(self, kT):
+        self.kT = float(kT)
 
     def set_particles(self, pos, vel, types):
         self.x = np.array(pos, dtype=np.float64).reshape(self.n, 3)
@@ -194,9 +246,13 @@ class OracleSystem:
                 raise OracleError("EINVAL", "self_avoid must be stated")
             if not (0 <= rx.type_a < self.n_types and 0 <= rx.type_b < self.n_types):
                 raise OracleError("EINVAL", "reaction type out of range")
-            if not (0 <= rx.bond_type < len(self.bond_kinds)) or \
-                    self.bond_kinds[rx.bond_type][0] != BOND_HARMONIC:
-                raise OracleError("EINVAL", "dynamic bond type must be harmonic")
+            if not (0 <= rx.bond_type < len(self.bond_kinds)):
+                raise OracleError("EINVAL", "bond type out of range")
+            bk = self.bond_kinds[rx.bond_type]
+            if bk[0] == BOND_FENE and not rx.r_max < bk[2]:
+                raise OracleError("EINVAL", "FENE reaction window must end below R0")
+            if bk[0] == BOND_TETHER and not (bk[3] < rx.r_min and rx.r_max < bk[6]):
+                raise OracleError("EINVAL", "tether reaction window must lie inside (l_min, l_max)")
             if rx.bond_type in seen_bt:
                 raise OracleError("EINVAL", "each reaction owns its bond type")
             seen_bt.add(rx.bond_type)
@@ -204,6 +260,19 @@ class OracleSystem:
                 raise OracleError("EINVAL", "bad window")
             self.rates.append(resolve_rates(rx.k_on, rx.k_off, rx.epsilon, rx.p_on0,
                                             self.dt, self.period))
+        self.melt_p = {}
+        for a, mod in self.modifiers.items():
+            if not 0 <= a < len(self.reactions):
+                raise OracleError("EINVAL", "modifier of an unknown reaction")
+            if mod[0] == "melt":
+                _, lam, T_melt, k_on_m, k_off_m = mod
+                ndt = float(self.period) * self.dt
+                pm_on, pm_off = k_on_m * ndt, k_off_m * ndt
+                if not (lam >= 0.0 and math.isfinite(T_melt) and 0.0 <= pm_on <= 1.0 and 0.0 <= pm_off <= 1.0):
+                    raise OracleError("ERANGE", "melted rates out of range")
+                self.melt_p[a] = (pm_on, pm_off, lam, T_melt)
+            elif not mod[1] >= 0.0:
+                raise OracleError("EINVAL", "slip coefficient must be >= 0")
         # sigma_ij / eps_ij tables (arithmetic / geometric means)
         self.sig_ij = 0.5 * (self.sigma[:, None] + self.sigma[None, :])
         self.eps_ij = np.sqrt(self.eps[:, None] * self.eps[None, :])
@@ -256,21 +325,40 @@ class OracleSystem:
 
     # -------------------------------------------------------------- forces
     def bond_energy_force(self, bt, r):
-        """U(r) and dU/dr of bond type ``bt`` (harmonic or FENE)."""
-        kind, k, r0 = self.bond_kinds[bt]
+        """U(r) and dU/dr of bond type ``bt`` (harmonic, FENE or tether)."""
+        kind, k, r0 = self.bond_kinds[bt][:3]
         if kind == BOND_HARMONIC:
             d = r - r0
             return (0.5 * k) * (d * d), k * d
-        x2 = (r * r) / (r0 * r0)
-        return -0.5 * k * r0 * r0 * np.log1p(-x2), k * r / (1.0 - x2)
+        if kind == BOND_FENE:
+            x2 = (r * r) / (r0 * r0)
+            return -0.5 * k * r0 * r0 * np.log1p(-x2), k * r / (1.0 - x2)
+        l_min, l_c1, l_c0, l_max = self.bond_kinds[bt][3:]
+        U, dU = 0.0, 0.0
+        if r > l_c0:                       # attraction beyond l_c0
+            e = math.exp(1.0 / (l_c0 - r))
+            U += k * e / (l_max - r)
+            dU += k * e * (1.0 / ((l_c0 - r) ** 2 * (l_max - r)) + 1.0 / (l_max - r) ** 2)
+        if r < l_c1:                       # repulsion below l_c1
+            e = math.exp(1.0 / (r - l_c1))
+            U += k * e / (r - l_min)
+            dU -= k * e * (1.0 / ((r - l_c1) ** 2 * (r - l_min)) + 1.0 / (r - l_min) ** 2)
+        return U, dU
+
+    def bond_in_domain(self, bt, r):
+        """FENE needs r < R0, tether l_min < r < l_max."""
+        kind = self.bond_kinds[bt][0]
+        if kind == BOND_FENE:
+            return r < self.bond_kinds[bt][2]
+        if kind == BOND_TETHER:
+            return self.bond_kinds[bt][3] < r < self.bond_kinds[bt][6]
+        return True
 
     def _check_fene(self, x):
         for i, j, b in self.static:
-            kind, _, r0 = self.bond_kinds[b]
-            if kind == BOND_FENE:
-                r = self.norm(self.delta(x[i], x[j]))
-                if r >= r0:
-                    raise OracleError("EBOND", f"FENE bond {i}-{j} overstretched r={r}")
+            r = self.norm(self.delta(x[i], x[j]))
+            if not self.bond_in_domain(b, r):
+                raise OracleError("EBOND", f"bond {i}-{j} outside its range r={r}")
 
     def forces(self, x):
         """Total force on every particle and total potential energy (FP64)."""
@@ -291,9 +379,8 @@ class OracleSystem:
         for i, j, bt in self.all_bonds():
             d = self.delta(x[i], x[j])
             r = float(self.norm(d))
-            kind, _, r0 = self.bond_kinds[bt]
-            if kind == BOND_FENE and r >= r0:
-                raise OracleError("EBOND", f"FENE bond {i}-{j} overstretched")
+            if not self.bond_in_domain(bt, r):
+                raise OracleError("EBOND", f"bond {i}-{j} outside its range")
             U, dudr = self.bond_energy_force(bt, r)
             PE += float(U)
             fi = (dudr / r) * d
@@ -402,7 +489,8 @@ class OracleSystem:
         partner, never one of its own molecule when self_avoid is set.
         """
         rx = self.reactions[a]
-        r0 = self.bond_kinds[rx.bond_type][2]
+        kind = self.bond_kinds[rx.bond_type][0]
+        r0 = 0.0 if kind == BOND_FENE else self.bond_kinds[rx.bond_type][2]
         i, j, _, r = self.pairs_within(self.x, rx.r_max)
         src = np.concatenate([i, j])
         dst = np.concatenate([j, i])
@@ -467,6 +555,10 @@ class OracleSystem:
     def _react(self, a, s, start, kT):
         rx = self.reactions[a]
         _, _, _, p_on, p_off = self.rates[a]
+        if a in self.melt_p:
+            pm_on, pm_off, lam, T_melt = self.melt_p[a]
+            p_on, p_off = melted_probabilities(p_on, p_off, pm_on, pm_off, lam, T_melt, kT)
+        slip = self.modifiers[a][1] if self.modifiers.get(a, ("",))[0] == "slip" else None
         occ0 = self.occ.copy()
         props = self.propose(a, occ0)
         pairs = self.match(a, s, props)
@@ -485,7 +577,12 @@ class OracleSystem:
         for (i, j), b in sorted(start.items()):             # breaking
             if b != a:
                 continue
-            if self.pair_u53(KIND_OFF, a, s, i, j) < p_off:
+            q = p_off
+            if slip is not None:
+                r = float(self.norm(self.delta(self.x[i], self.x[j])))
+                U, _ = self.bond_energy_force(rx.bond_type, r)
+                q = slip_probability(p_off, slip, float(U), kT)
+            if self.pair_u53(KIND_OFF, a, s, i, j) < q:
                 del self.dyn[(i, j)]
                 self.occ[i] -= 1
                 self.occ[j] -= 1
