@@ -60,7 +60,8 @@ typedef enum {
 } db_status;
 
 enum { DB_BOND_HARMONIC = 0,   /* U = k/2 (r - r0)^2 */
-       DB_BOND_FENE = 1 };     /* U = -k R0^2/2 ln(1 - r^2/R0^2), r0 argument = R0 */
+       DB_BOND_FENE = 1,       /* U = -k R0^2/2 ln(1 - r^2/R0^2), r0 argument = R0 */
+       DB_BOND_TETHER = 2 };   /* registered with db_add_tether_bond_type */
 
 enum { DB_KT_SETPOINT = 0,     /* acceptance uses the thermostat set point kT */
        DB_KT_KINETIC = 1 };    /* acceptance uses the instantaneous kinetic temperature
@@ -126,6 +127,17 @@ DB_API db_status db_set_particles(db_system* sys, const float* pos3, const float
  * rest length r0 or FENE maximum extension R0); *id receives its index. */
 DB_API db_status db_add_bond_type(db_system* sys, int kind, double k, double r0, uint32_t* id);
 
+/* Register a tether bond type (Sec. 2.2 names it among the bond potentials
+ * a reaction may use): U(r) = U_att + U_rep with
+ *   U_att = k_b exp(1/(l_c0 - r)) / (l_max - r)   for r > l_c0,
+ *   U_rep = k_b exp(1/(r - l_c1)) / (r - l_min)   for r < l_c1,
+ * zero for l_c1 <= r <= l_c0; defined on l_min < r < l_max (a bond outside
+ * stops the run with DB_EBOND, as an overstretched FENE bond).  Requires
+ * k_b >= 0 and 0 <= l_min < l_c1 < l_c0 < l_max.  Usable for static bonds
+ * and as the bond of a reaction.  Errors: DB_EINVAL, DB_ESTATE. */
+DB_API db_status db_add_tether_bond_type(db_system* sys, double k_b, double l_min, double l_c1, double l_c0,
+                                         double l_max, uint32_t* id);
+
 /* Add m static (never-breaking) bonds: tag_pairs[2m] and bond_types[m].
  * Static bonds define the molecules used by self_avoid (Sec. 2.4). */
 DB_API db_status db_add_static_bonds(db_system* sys, const uint32_t* tag_pairs,
@@ -135,11 +147,38 @@ DB_API db_status db_add_static_bonds(db_system* sys, const uint32_t* tag_pairs,
  * redrawn at random every sweep, Sec. 2.3). */
 DB_API db_status db_add_reaction(db_system* sys, const db_reaction_desc* desc, uint32_t* id);
 
+/* Rate modifiers of a reaction (Sec. 2.4; at most one per reaction, the two
+ * are mutually exclusive; before db_commit).
+ *
+ * Melting (Eqs. gT, kT): with g(T) = [tanh(lambda (T - T_melt)) + 1] / 2,
+ * each rate becomes k(T) = k_init (1 - g) + k_melt g, where k_init are the
+ * reaction's own closed rates and k_on_melt, k_off_melt the melted ones;
+ * the per-sweep probabilities are k(T) n dt (Eq. probs).  T is the sweep's
+ * temperature: the set point (db_set_temperature changes it), or the
+ * kinetic temperature in DB_KT_KINETIC mode.  Errors: DB_EINVAL (lambda < 0,
+ * non-finite values, negative rates, unknown reaction, slip already set),
+ * DB_ERANGE at validation when k_melt n dt exceeds 1.
+ *
+ * Slip bond (Eq. slip): bonds of the reaction break with
+ * P_off(r) = min(1, P0_off exp(a sqrt(U_b(r) / kT))), r the bond's length at
+ * the sweep and U_b the energy of the reaction's bond type; at kT = 0 the
+ * factor is 1 for U_b = 0 and P_off = 1 otherwise (a > 0).  Errors:
+ * DB_EINVAL (a < 0 or non-finite, unknown reaction, melting already set). */
+DB_API db_status db_set_reaction_melting(db_system* sys, uint32_t reaction, double lambda, double T_melt,
+                                         double k_on_melt, double k_off_melt);
+DB_API db_status db_set_reaction_slip(db_system* sys, uint32_t reaction, double a);
+
 /* Integrator: time step dt > 0, thermostat kT >= 0, friction gamma >= 0,
  * sweep period n >= 1 (the n of Eq. probs), temperature source for the
  * acceptance factor (DB_KT_SETPOINT or DB_KT_KINETIC).  Defaults 0.005, 1, 1, 10. */
 DB_API db_status db_set_integrator(db_system* sys, double dt, double kT, double gamma,
                             uint32_t sweep_period, int kt_source);
+
+/* Change the set-point temperature kT (>= 0), before or after db_commit:
+ * the thermostat's noise, the acceptance factor and the melting modifier
+ * use the new value from the next step on (for temperature ramps such as
+ * melting curves).  Errors: DB_EINVAL, DB_EDEVICE. */
+DB_API db_status db_set_temperature(db_system* sys, double kT);
 
 /* Particle slots per cell of the neighbour cell list.  0 (default) = chosen
  * at commit from the density and the fullest cell of the initial state (at
@@ -293,6 +332,21 @@ DB_API db_status db_read_bonds(db_system* sys, uint32_t* tag_pairs, uint32_t* bo
 
 /* Observables of the current state (computed on the device). */
 DB_API db_status db_read_observables(db_system* sys, db_observables* out);
+
+/* Device-side read-outs, for callers that keep the data on the GPU (for
+ * example in PyTorch tensors): the same values as db_read_positions,
+ * db_read_velocities and db_read_forces, written as 3 n floats in tag order
+ * to dev_out3, device memory of the system's device that the caller owns.
+ * The work is enqueued on hip_stream (a hipStream_t; NULL = the system's own
+ * stream) after everything already enqueued for the system, and the
+ * system's later work waits for it; the call itself does not wait, so
+ * dev_out3 is ready once hip_stream reaches this point.  Errors found by
+ * this work (as the force evaluation's DB_EBOND) are reported by the next
+ * call that checks.  Errors: DB_EINVAL (dev_out3 NULL), DB_ESTATE,
+ * DB_EDEVICE. */
+DB_API db_status db_read_positions_device(db_system* sys, float* dev_pos3, void* hip_stream);
+DB_API db_status db_read_velocities_device(db_system* sys, float* dev_vel3, void* hip_stream);
+DB_API db_status db_read_forces_device(db_system* sys, float* dev_force3, void* hip_stream);
 
 /* Current step counter (host mirror). */
 DB_API uint64_t db_get_step(const db_system* sys);

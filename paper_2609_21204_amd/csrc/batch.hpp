@@ -177,7 +177,7 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
         if (ake) {
             for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
             if (__lane_id() == 0 && ke)
-                __hip_atomic_fetch_add(D.ke_fix, ke, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(&D.ke_fix[ke_slot(P, s)], ke, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         __syncthreads();
         xin ^= 1;
@@ -251,11 +251,11 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
             count_add(D, a, kCtrAttempt, att);
             count_add(D, a, kCtrForm, form);
             uint32_t broke = 0;
-            for (uint32_t i = tid; i < n; i += bs) broke += break_site(P, D, a, s, i);
+            for (uint32_t i = tid; i < n; i += bs) broke += break_site(P, D, a, s, i, Xs);
             count_add(D, a, kCtrBreak, broke);
             __syncthreads();
         }
-        if (tid == 0) *D.ke_fix = 0ull;
+        if (tid == 0) D.ke_fix[ke_slot(P, s) ^ 1u] = 0ull;   // the next sweep's slot, as db_step leaves it
     }
     // hand the state back in the form db_step leaves it: step slots, no list
     // rebuild pending, round-1 key buffer clear

@@ -29,7 +29,7 @@ enum : uint32_t { kThermo = 1, kOrder = 2, kMatch = 3, kOn = 4, kOff = 5 };
 enum : uint8_t { kEdgeNone = 0, kEdgeLive = 1, kEdgeMatched = 2, kEdgeDead = 3 };
 
 // Device error flags (sticky until the host clears them).
-enum : uint32_t { kErrOverflow = 1u, kErrFene = 2u, kErrForce = 4u, kErrNlist = 8u };
+enum : uint32_t { kErrOverflow = 1u, kErrFene = 2u, kErrForce = 4u, kErrNlist = 8u };   // kErrFene: a bond outside its range
 
 // ---------------------------------------------------------------- Philox
 struct Word4 { uint32_t w0, w1, w2, w3; };
@@ -137,11 +137,19 @@ struct Params {
     float sig2f[kMaxTypes * kMaxTypes];    // sigma_ij^2
     float eps24f[kMaxTypes * kMaxTypes];   // 24 eps_ij
 
-    uint32_t bkind[kMaxBondTypes];
+    uint32_t bkind[kMaxBondTypes];     // 0 harmonic, 1 FENE, 2 tether
     double bk[kMaxBondTypes], br0[kMaxBondTypes], bR02[kMaxBondTypes], binvR02[kMaxBondTypes];
+    double blmin[kMaxBondTypes], blc1[kMaxBondTypes], blc0[kMaxBondTypes], blmax[kMaxBondTypes];  // tether
     float rmax2_pre[kMaxRx], rmin2_pre[kMaxRx];  // FP32 prefilter of the reaction window
     uint32_t ra[kMaxRx], rb[kMaxRx], rbt[kMaxRx], rself[kMaxRx];
     double rmin[kMaxRx], rmax[kMaxRx], r0[kMaxRx], hk[kMaxRx], pon[kMaxRx], poff[kMaxRx];
+    // rate modifiers (0 none, 1 melting, 2 slip bond).  With the set-point
+    // temperature the melted probabilities are already in pon / poff; with the
+    // kinetic temperature the sweep mixes pon_i / pon_m (poff_i / poff_m) by
+    // the switch at that temperature.
+    uint32_t rmod[kMaxRx];
+    double mlam[kMaxRx], mtm[kMaxRx], pon_i[kMaxRx], pon_m[kMaxRx], poff_i[kMaxRx], poff_m[kMaxRx];
+    double slip[kMaxRx];
 };
 
 // WCA parameters of one type pair, evaluated in FP64.
@@ -164,6 +172,7 @@ struct alignas(16) StepTabs {
     float rl2[kMaxTypes * kMaxTypes];   // neighbour-list radius^2 of the type pair
     PairTab pair[kMaxTypes * kMaxTypes];
     double bk[kMaxBondTypes], br0[kMaxBondTypes], binvR02[kMaxBondTypes];
+    double blmin[kMaxBondTypes], blc1[kMaxBondTypes], blc0[kMaxBondTypes], blmax[kMaxBondTypes];
     uint32_t bkind[kMaxBondTypes];
     uint32_t rbt[kMaxRx];
     float hm[kMaxTypes], noise_sd[kMaxTypes], mass[kMaxTypes];   // hm = (dt / 2) / m
@@ -194,7 +203,7 @@ struct Dev {
     uint32_t* live_count;  // [0] = length of `live`
     unsigned long long* counters;   // nrx x 3 x kCtrSlots: attempts, forms, breaks
     unsigned long long* stepv;      // two step slots (parity of the step)
-    unsigned long long* ke_fix;     // sum m v^2 in 2^-32 fixed point (kinetic kT)
+    unsigned long long* ke_fix;     // [2] sum m v^2 in 2^-32 fixed point (kinetic kT), one slot per sweep parity
     uint32_t* err;         // [0] flags, [1], [2] tags of the offending pair
     float4* f4;            // forces + per-particle energy (evaluation kernels)
     unsigned long long* red;        // reduction scratch (observables)

@@ -29,8 +29,10 @@ constexpr uint32_t kCellCapMin = 16;   // minimum particle slots per cell
 thread_local std::string g_create_error;
 
 struct TypeCfg { uint32_t valence = 0; double sigma = 1.0, eps = 1.0, mass = 1.0; };
-struct BondCfg { int kind; double k, r0; };
+struct BondCfg { int kind; double k, r0; double lmin = 0, lc1 = 0, lc0 = 0, lmax = 0; };
 struct RxRes { double k_on, k_off, eps, p_on, p_off; };
+// rate modifier of one reaction: 0 none, 1 melting, 2 slip bond
+struct RxMod { int kind = 0; double lam = 0, tm = 0, k_on_m = 0, k_off_m = 0, a = 0; };
 
 struct Timing {
     bool on = false;
@@ -51,6 +53,7 @@ struct db_system {
     std::vector<TypeCfg> types;
     std::vector<BondCfg> bonds;
     std::vector<db_reaction_desc> rx;
+    std::vector<RxMod> mods;               // one per reaction
     std::vector<RxRes> res;
     std::vector<float> pos, vel;
     std::vector<uint32_t> type;
@@ -75,6 +78,7 @@ struct db_system {
     std::vector<PairTab> pair_h;           // WCA table uploaded to D.pair
     Timing timing;
     std::map<int, hipGraphExec_t> graphs;  // keyed by (cur_x, cur_list)
+    hipEvent_t ev_out = nullptr, ev_back = nullptr;   // ordering of device-side read-outs
     bool use_graphs = true;
     uint32_t cellcap_user = 0;             // 0 = automatic
     double skin = 0.4;                     // neighbour-list skin
@@ -232,8 +236,12 @@ db_status validate(db_system* s) {
             return fail(s, DB_EINVAL, "reaction %zu: self_avoid must be stated as 0 or 1", a);
         if (d.type_a >= s->ntypes || d.type_b >= s->ntypes)
             return fail(s, DB_EINVAL, "reaction %zu: type out of range", a);
-        if (d.bond_type >= s->bonds.size() || s->bonds[d.bond_type].kind != DB_BOND_HARMONIC)
-            return fail(s, DB_EINVAL, "reaction %zu: bond type must be a harmonic bond type", a);
+        if (d.bond_type >= s->bonds.size()) return fail(s, DB_EINVAL, "reaction %zu: bond type out of range", a);
+        const BondCfg& bc = s->bonds[d.bond_type];
+        if (bc.kind == DB_BOND_FENE && !(d.r_max < bc.r0))
+            return fail(s, DB_EINVAL, "reaction %zu: a FENE reaction window must end below R0", a);
+        if (bc.kind == DB_BOND_TETHER && !(bc.lmin < d.r_min && d.r_max < bc.lmax))
+            return fail(s, DB_EINVAL, "reaction %zu: a tether reaction window must lie inside (l_min, l_max)", a);
         if (bt_owner[d.bond_type] >= 0)
             return fail(s, DB_EINVAL, "reaction %zu: bond type already owned by reaction %d", a, bt_owner[d.bond_type]);
         bt_owner[d.bond_type] = (int)a;
@@ -242,9 +250,16 @@ db_status validate(db_system* s) {
         rmax_all = std::max(rmax_all, d.r_max);
         db_status st = close_rates(s, d, s->res[a]);
         if (st != DB_OK) return st;
+        const RxMod& m = s->mods[a];
+        if (m.kind == 1) {
+            const double ndt = (double)s->period * s->dt;
+            const double pm_on = m.k_on_m * ndt, pm_off = m.k_off_m * ndt;
+            if (!(pm_on >= 0.0 && pm_on <= 1.0 && pm_off >= 0.0 && pm_off <= 1.0))
+                return fail(s, DB_ERANGE, "reaction %zu: melted rate k n dt outside [0, 1]", a);
+        }
     }
     for (const auto& b : s->bonds)
-        if (!(b.k >= 0.0) || !(b.r0 > 0.0 || (b.kind == DB_BOND_HARMONIC && b.r0 >= 0.0)))
+        if (b.kind != DB_BOND_TETHER && (!(b.k >= 0.0) || !(b.r0 > 0.0 || (b.kind == DB_BOND_HARMONIC && b.r0 >= 0.0))))
             return fail(s, DB_EINVAL, "bond type parameters out of range");
     double rc = 0.0;
     for (uint32_t a = 0; a < s->ntypes; ++a)
@@ -353,6 +368,59 @@ void choose_tiles(const db_system* s, Params& P) {
     }
 }
 
+// Melting modifier at temperature T (Eqs. gT, kT): P = P_init (1 - g) + P_melt g,
+// g = [tanh(lambda (T - T_melt)) + 1] / 2; P0 = k n dt is linear in k.
+double melt_mix_host(double p_init, double p_melt, double lam, double tm, double T) {
+#pragma clang fp contract(off)
+    const double g = 0.5 * (std::tanh(lam * (T - tm)) + 1.0);
+    return p_init * (1.0 - g) + p_melt * g;
+}
+
+// Step tables: the same numbers k_step would read from the parameter block,
+// laid out for one 16-byte copy per thread into LDS.
+void fill_tabs(const db_system* s, StepTabs& th) {
+    const Params& P = s->P;
+    th = StepTabs{};
+    for (int k = 0; k < kMaxTypes * kMaxTypes; ++k) {
+        th.rc2_pre[k] = P.rc2_pre[k];
+        th.rc2_in[k] = P.rc2_in[k];
+        th.sig2f[k] = P.sig2f[k];
+        th.eps24f[k] = P.eps24f[k];
+        th.rl2[k] = P.rl2[k];
+        th.pair[k] = s->pair_h[k];
+    }
+    for (int k = 0; k < 8; ++k) {
+        th.bk[k] = P.bk[k];
+        th.br0[k] = P.br0[k];
+        th.binvR02[k] = P.binvR02[k];
+        th.blmin[k] = P.blmin[k];
+        th.blc1[k] = P.blc1[k];
+        th.blc0[k] = P.blc0[k];
+        th.blmax[k] = P.blmax[k];
+        th.bkind[k] = P.bkind[k];
+        th.rbt[k] = P.rbt[k];
+        th.hm[k] = P.h * P.inv_mass[k];
+        th.noise_sd[k] = P.noise_sd[k];
+        th.mass[k] = P.mass[k];
+        th.cap[k] = P.cap[k];
+    }
+}
+
+// The parts of the parameters that depend on the temperature: the noise
+// amplitudes and, at a set-point temperature, the melted probabilities.
+void apply_temperature(db_system* s) {
+    Params& P = s->P;
+    const double c1 = std::exp(-s->gamma * s->dt);
+    P.kT = s->kT;
+    for (uint32_t t = 0; t < s->ntypes; ++t)
+        P.noise_sd[t] = (float)(std::sqrt(std::max(0.0, 1.0 - c1 * c1)) * std::sqrt(s->kT / s->types[t].mass));
+    for (size_t a = 0; a < s->rx.size(); ++a)
+        if (s->mods[a].kind == 1 && s->kt_source != DB_KT_KINETIC) {
+            P.pon[a] = melt_mix_host(P.pon_i[a], P.pon_m[a], P.mlam[a], P.mtm[a], s->kT);
+            P.poff[a] = melt_mix_host(P.poff_i[a], P.poff_m[a], P.mlam[a], P.mtm[a], s->kT);
+        }
+}
+
 // threads per particle: 4, or more for small systems so that a launch has
 // at least 2^19 threads
 uint32_t auto_tpp(uint32_t n) {
@@ -411,6 +479,10 @@ void fill_params(db_system* s) {
         P.br0[b] = s->bonds[b].r0;
         P.bR02[b] = s->bonds[b].r0 * s->bonds[b].r0;
         P.binvR02[b] = P.bR02[b] > 0.0 ? 1.0 / P.bR02[b] : 0.0;
+        P.blmin[b] = s->bonds[b].lmin;
+        P.blc1[b] = s->bonds[b].lc1;
+        P.blc0[b] = s->bonds[b].lc0;
+        P.blmax[b] = s->bonds[b].lmax;
     }
     for (size_t a = 0; a < s->rx.size(); ++a) {
         const auto& d = s->rx[a];
@@ -421,10 +493,29 @@ void fill_params(db_system* s) {
         P.any_self_avoid |= (uint32_t)d.self_avoid;
         P.rmin[a] = d.r_min;
         P.rmax[a] = d.r_max;
-        P.r0[a] = s->bonds[d.bond_type].r0;
-        P.hk[a] = 0.5 * s->bonds[d.bond_type].k;
+        // target length of proposals: the minimum of the reaction's bond
+        // potential (harmonic r0, FENE 0, tether the middle of its flat region)
+        const BondCfg& bc = s->bonds[d.bond_type];
+        P.r0[a] = bc.kind == DB_BOND_FENE ? 0.0 : bc.r0;
+        P.hk[a] = 0.5 * bc.k;
         P.pon[a] = s->res[a].p_on;
         P.poff[a] = s->res[a].p_off;
+        const RxMod& m = s->mods[a];
+        P.rmod[a] = (uint32_t)m.kind;
+        P.slip[a] = m.a;
+        if (m.kind == 1) {
+            const double ndt = (double)s->period * s->dt;
+            P.mlam[a] = m.lam;
+            P.mtm[a] = m.tm;
+            P.pon_i[a] = s->res[a].p_on;
+            P.poff_i[a] = s->res[a].p_off;
+            P.pon_m[a] = m.k_on_m * ndt;
+            P.poff_m[a] = m.k_off_m * ndt;
+            if (s->kt_source != DB_KT_KINETIC) {      // fixed temperature: mix once here
+                P.pon[a] = melt_mix_host(P.pon_i[a], P.pon_m[a], m.lam, m.tm, s->kT);
+                P.poff[a] = melt_mix_host(P.poff_i[a], P.poff_m[a], m.lam, m.tm, s->kT);
+            }
+        }
         P.rmax2_pre[a] = (float)(d.r_max * d.r_max * (1.0 + 1e-3) + 1e-4);
         P.rmin2_pre[a] = (float)std::max(0.0, d.r_min * d.r_min * (1.0 - 1e-3) - 1e-4);
         rmax_all = std::max(rmax_all, d.r_max);
@@ -518,7 +609,7 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
     sv[(s->step & 1) ^ 1] = s->step;
     HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv, sizeof sv, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemsetAsync(s->D.err, 0, 4 * sizeof(uint32_t), s->stream));
-    HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, sizeof(unsigned long long), s->stream));
+    HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, 2 * sizeof(unsigned long long), s->stream));
     const uint32_t flags[3] = {s->step % 3 == 0, s->step % 3 == 1, s->step % 3 == 2};   // lists built below
     HIPCHK(s, hipMemcpyAsync(s->D.rflag, flags, sizeof flags, hipMemcpyHostToDevice, s->stream));
     s->cur_x = 0;
@@ -533,7 +624,7 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
     uint32_t err[4];
     HIPCHK(s, hipMemcpy(err, s->D.err, sizeof err, hipMemcpyDeviceToHost));
     if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", s->P.cellcap); }
-    if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "FENE bond %u-%u overstretched", err[1], err[2]); }
+    if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "bond %u-%u outside its range (FENE r >= R0, tether r outside (l_min, l_max))", err[1], err[2]); }
     if (err[0] & kErrForce) { s->invalid = true; return fail(s, DB_EBOND, "force out of range"); }
     if (err[0] & kErrNlist) { s->invalid = true; return fail(s, DB_EOVERFLOW, "more than %u neighbours of one particle", s->P.nlmax); }
     s->invalid = false;
@@ -569,7 +660,7 @@ db_status check_errors(db_system* s) {
     uint32_t err[4];
     HIPCHK(s, hipMemcpy(err, s->D.err, sizeof err, hipMemcpyDeviceToHost));
     if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", s->P.cellcap); }
-    if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "FENE bond %u-%u reached r >= R0", err[1], err[2]); }
+    if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "bond %u-%u outside its range (FENE r >= R0, tether r outside (l_min, l_max))", err[1], err[2]); }
     if (err[0] & kErrForce) { s->invalid = true; return fail(s, DB_EBOND, "force out of the representable range"); }
     if (err[0] & kErrNlist) { s->invalid = true; return fail(s, DB_EOVERFLOW, "more than %u neighbours of one particle", s->P.nlmax); }
     return DB_OK;
@@ -739,6 +830,8 @@ void db_destroy(db_system* s) {
         destroy_graphs(s);
         for (auto& p : s->timing.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
         for (auto e : s->timing.pool) (void)hipEventDestroy(e);
+        if (s->ev_out) (void)hipEventDestroy(s->ev_out);
+        if (s->ev_back) (void)hipEventDestroy(s->ev_back);
         for (void* p : s->allocs) (void)hipFree(p);
         if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     }
@@ -787,6 +880,60 @@ db_status db_add_bond_type(db_system* s, int kind, double k, double r0, uint32_t
     return DB_OK;
 }
 
+db_status db_add_tether_bond_type(db_system* s, double k_b, double l_min, double l_c1, double l_c0, double l_max,
+                                  uint32_t* id) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "parameters are fixed after commit");
+    if (s->bonds.size() >= (size_t)kMaxBondTypes) return fail(s, DB_EINVAL, "too many bond types");
+    for (double v : {k_b, l_min, l_c1, l_c0, l_max})
+        if (!std::isfinite(v)) return fail(s, DB_EINVAL, "tether parameters must be finite");
+    if (!(k_b >= 0.0) || !(l_min >= 0.0) || !(l_min < l_c1) || !(l_c1 < l_c0) || !(l_c0 < l_max))
+        return fail(s, DB_EINVAL, "tether needs k_b >= 0 and 0 <= l_min < l_c1 < l_c0 < l_max");
+    BondCfg b{DB_BOND_TETHER, k_b, 0.5 * (l_c1 + l_c0)};
+    b.lmin = l_min;
+    b.lc1 = l_c1;
+    b.lc0 = l_c0;
+    b.lmax = l_max;
+    s->bonds.push_back(b);
+    if (id) *id = (uint32_t)s->bonds.size() - 1;
+    s->validated = false;
+    return DB_OK;
+}
+
+db_status db_set_reaction_melting(db_system* s, uint32_t reaction, double lambda, double T_melt, double k_on_melt,
+                                  double k_off_melt) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "reactions are fixed after commit");
+    if (reaction >= s->rx.size()) return fail(s, DB_EINVAL, "no reaction %u", reaction);
+    if (s->mods[reaction].kind == 2) return fail(s, DB_EINVAL, "melting and slip modifiers are mutually exclusive");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda) || !std::isfinite(T_melt) || !(k_on_melt >= 0.0) ||
+        !(k_off_melt >= 0.0) || !std::isfinite(k_on_melt) || !std::isfinite(k_off_melt))
+        return fail(s, DB_EINVAL, "melting needs lambda >= 0, finite T_melt, melted rates >= 0");
+    RxMod& m = s->mods[reaction];
+    m = RxMod{};
+    m.kind = 1;
+    m.lam = lambda;
+    m.tm = T_melt;
+    m.k_on_m = k_on_melt;
+    m.k_off_m = k_off_melt;
+    s->validated = false;
+    return DB_OK;
+}
+
+db_status db_set_reaction_slip(db_system* s, uint32_t reaction, double a) {
+    if (!s) return DB_EINVAL;
+    if (s->committed) return fail(s, DB_ESTATE, "reactions are fixed after commit");
+    if (reaction >= s->rx.size()) return fail(s, DB_EINVAL, "no reaction %u", reaction);
+    if (s->mods[reaction].kind == 1) return fail(s, DB_EINVAL, "melting and slip modifiers are mutually exclusive");
+    if (!(a >= 0.0) || !std::isfinite(a)) return fail(s, DB_EINVAL, "slip coefficient must be finite and >= 0");
+    RxMod& m = s->mods[reaction];
+    m = RxMod{};
+    m.kind = 2;
+    m.a = a;
+    s->validated = false;
+    return DB_OK;
+}
+
 db_status db_add_static_bonds(db_system* s, const uint32_t* pairs, const uint32_t* bt, uint64_t m) {
     if (!s) return DB_EINVAL;
     if (s->committed) return fail(s, DB_ESTATE, "static bonds are fixed after commit");
@@ -802,6 +949,7 @@ db_status db_add_reaction(db_system* s, const db_reaction_desc* d, uint32_t* id)
     if (s->committed) return fail(s, DB_ESTATE, "reactions are fixed after commit");
     if (s->rx.size() >= (size_t)kMaxRx) return fail(s, DB_EINVAL, "at most %d reactions", kMaxRx);
     s->rx.push_back(*d);
+    s->mods.push_back(RxMod{});
     if (id) *id = (uint32_t)s->rx.size() - 1;
     s->validated = false;
     return DB_OK;
@@ -820,6 +968,26 @@ db_status db_set_integrator(db_system* s, double dt, double kT, double gamma, ui
     s->period = period;
     s->kt_source = kt_source;
     s->validated = false;
+    return DB_OK;
+}
+
+db_status db_set_temperature(db_system* s, double kT) {
+    if (!s) return DB_EINVAL;
+    if (!(kT >= 0.0) || !std::isfinite(kT)) return fail(s, DB_EINVAL, "kT must be finite and >= 0");
+    if (!s->committed) {
+        s->kT = kT;
+        s->validated = false;
+        return DB_OK;
+    }
+    if (s->dead) return fail(s, DB_EDEVICE, "device error earlier on this handle");
+    HIPCHK(s, hipSetDevice(s->device));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->kT = kT;
+    apply_temperature(s);
+    StepTabs th;
+    fill_tabs(s, th);
+    HIPCHK(s, hipMemcpy((void*)s->D.tabs, &th, sizeof th, hipMemcpyHostToDevice));
+    destroy_graphs(s);
     return DB_OK;
 }
 
@@ -934,25 +1102,7 @@ static db_status commit_impl(db_system* s) {
         // step tables: the same numbers k_step would read from the parameter
         // block, laid out for one 16-byte copy per thread into LDS
         StepTabs th{};
-        for (int k = 0; k < kMaxTypes * kMaxTypes; ++k) {
-            th.rc2_pre[k] = P.rc2_pre[k];
-            th.rc2_in[k] = P.rc2_in[k];
-            th.sig2f[k] = P.sig2f[k];
-            th.eps24f[k] = P.eps24f[k];
-            th.rl2[k] = P.rl2[k];
-            th.pair[k] = s->pair_h[k];
-        }
-        for (int k = 0; k < 8; ++k) {
-            th.bk[k] = P.bk[k];
-            th.br0[k] = P.br0[k];
-            th.binvR02[k] = P.binvR02[k];
-            th.bkind[k] = P.bkind[k];
-            th.rbt[k] = P.rbt[k];
-            th.hm[k] = P.h * P.inv_mass[k];
-            th.noise_sd[k] = P.noise_sd[k];
-            th.mass[k] = P.mass[k];
-            th.cap[k] = P.cap[k];
-        }
+        fill_tabs(s, th);
         StepTabs* tt = nullptr;
         DALLOC(s, tt, 1);
         HIPCHK(s, hipMemcpy(tt, &th, sizeof th, hipMemcpyHostToDevice));
@@ -981,7 +1131,7 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.live_count, 4);
     DALLOC(s, D.counters, (size_t)3 * kMaxRx * kCtrSlots);
     DALLOC(s, D.stepv, 2);
-    DALLOC(s, D.ke_fix, 1);
+    DALLOC(s, D.ke_fix, 2);
     DALLOC(s, D.err, 4);
     DALLOC(s, D.f4, 2 * (size_t)n);
     DALLOC(s, D.red, 4 + kMaxRx);
@@ -1337,10 +1487,12 @@ db_status db_sweep_frozen(db_system* s, uint64_t step_key) {
     const unsigned long long sv_back[2] = {s->step, s->step};
     HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv, sizeof sv, hipMemcpyHostToDevice, s->stream));
     if (s->P.kt_kinetic) {
-        HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, 8, s->stream));
-        LAUNCH(s, k_ke_accum, g, kBlock, s->P, s->D, xc);
+        HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, 16, s->stream));
+        LAUNCH(s, k_ke_accum, g, kBlock, s->P, s->D, xc, step_key);
     }
     launch_sweep(s, xc, (int)(step_key & 1));
+    // both kinetic-energy slots start the next regular sweep cleared
+    if (s->P.kt_kinetic) HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, 16, s->stream));
     LAUNCH(s, k_eval, g, kBlock, s->P, s->D, xc, lc, s->n);
     LAUNCH(s, k_fix_u, g, kBlock, s->P, s->D, xc);
     HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv_back, sizeof sv_back, hipMemcpyHostToDevice, s->stream));
@@ -1428,6 +1580,34 @@ static db_status read_vec(db_system* s, float* out3, int mode) {
     }
     return DB_OK;
 }
+
+// Device-side read-out on the caller's stream, ordered after the system's
+// pending work, with the system's later work ordered after it.
+static db_status read_vec_device(db_system* s, float* out3, void* stream, int mode) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!out3) return fail(s, DB_EINVAL, "output is NULL");
+    HIPCHK(s, hipSetDevice(s->device));
+    const hipStream_t q = stream ? (hipStream_t)stream : s->stream;
+    if (mode != 0) LAUNCH(s, k_eval, grid_of(s->n), kBlock, s->P, s->D, s->cur_x, s->cur_list, 0u);
+    if (q != s->stream) {
+        if (!s->ev_out) HIPCHK(s, hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
+        if (!s->ev_back) HIPCHK(s, hipEventCreateWithFlags(&s->ev_back, hipEventDisableTiming));
+        HIPCHK(s, hipEventRecord(s->ev_out, s->stream));
+        HIPCHK(s, hipStreamWaitEvent(q, s->ev_out, 0));
+    }
+    hipLaunchKernelGGL(k_gather3, dim3(grid_of(s->n)), dim3(kBlock), 0, q, s->P, s->D, out3, s->cur_x, mode);
+    HIPCHK(s, hipGetLastError());
+    if (q != s->stream) {
+        HIPCHK(s, hipEventRecord(s->ev_back, q));
+        HIPCHK(s, hipStreamWaitEvent(s->stream, s->ev_back, 0));
+    }
+    return DB_OK;
+}
+
+db_status db_read_positions_device(db_system* s, float* pos3, void* stream) { return read_vec_device(s, pos3, stream, 0); }
+db_status db_read_velocities_device(db_system* s, float* vel3, void* stream) { return read_vec_device(s, vel3, stream, 1); }
+db_status db_read_forces_device(db_system* s, float* force3, void* stream) { return read_vec_device(s, force3, stream, 2); }
 
 db_status db_read_velocities(db_system* s, float* vel3) { return read_vec(s, vel3, 1); }
 db_status db_read_forces(db_system* s, float* force3) { return read_vec(s, force3, 2); }

@@ -25,6 +25,85 @@ namespace dyb {
 // ------------------------------------------------------------ force kernel
 struct Force3 { float x, y, z; };
 
+// Slot of the kinetic-energy sum that the sweep with step key s reads: sweeps
+// alternate between two slots, so the last kernel of a sweep can clear the
+// slot of the next one while its own is still being read.
+__device__ __forceinline__ uint32_t ke_slot(const Params& P, unsigned long long s) {
+    return (uint32_t)((s / P.period) & 1ull);
+}
+
+// Temperature of the sweep with step key s: the set point, or the kinetic
+// temperature sum m v^2 / (3 N) accumulated by the step before it.
+__device__ __forceinline__ double sweep_kT(const Params& P, const Dev& D, unsigned long long s) {
+    return P.kt_kinetic ? (double)D.ke_fix[ke_slot(P, s)] * kFixInv / (3.0 * (double)P.n) : P.kT;
+}
+
+// Tether bond: U = U_att + U_rep with U_att = k e^{1/(l_c0 - r)} / (l_max - r)
+// for r > l_c0 and U_rep = k e^{1/(r - l_c1)} / (r - l_min) for r < l_c1,
+// zero in between; returns U, dU/dr in du.
+__device__ __forceinline__ double tether_u(double r, double k, double lmin, double lc1, double lc0, double lmax,
+                                           double* du) {
+#pragma clang fp contract(off)
+    double U = 0.0, d = 0.0;
+    if (r > lc0) {
+        const double e = exp(1.0 / (lc0 - r));
+        U += k * e / (lmax - r);
+        d += k * e * (1.0 / ((lc0 - r) * (lc0 - r) * (lmax - r)) + 1.0 / ((lmax - r) * (lmax - r)));
+    }
+    if (r < lc1) {
+        const double e = exp(1.0 / (r - lc1));
+        U += k * e / (r - lmin);
+        d -= k * e * (1.0 / ((r - lc1) * (r - lc1) * (r - lmin)) + 1.0 / ((r - lmin) * (r - lmin)));
+    }
+    *du = d;
+    return U;
+}
+
+// Energy U_b(r) of bond type bt (the acceptance and slip factors of the
+// sweep use it): harmonic k/2 (r - r0)^2, FENE -k R0^2/2 ln(1 - r^2/R0^2),
+// tether as above.  The reaction window keeps r inside the bond's range.
+__device__ __forceinline__ double bond_energy(const Params& P, uint32_t bt, double r) {
+#pragma clang fp contract(off)
+    const uint32_t kind = P.bkind[bt];
+    if (kind == 0u) {
+        const double d = r - P.br0[bt];
+        return (0.5 * P.bk[bt]) * (d * d);
+    }
+    if (kind == 1u) {
+        const double x2 = (r * r) / P.bR02[bt];
+        return -0.5 * P.bk[bt] * P.br0[bt] * P.br0[bt] * log1p(-x2);
+    }
+    double du;
+    return tether_u(r, P.bk[bt], P.blmin[bt], P.blc1[bt], P.blc0[bt], P.blmax[bt], &du);
+}
+
+// Melting modifier: P = P_init (1 - g) + P_melt g with
+// g = [tanh(lambda (T - T_melt)) + 1] / 2.
+__device__ __forceinline__ double melt_mix(double p_init, double p_melt, double lam, double tm, double T) {
+#pragma clang fp contract(off)
+    const double g = 0.5 * (tanh(lam * (T - tm)) + 1.0);
+    return p_init * (1.0 - g) + p_melt * g;
+}
+
+// Slip bond: P_off = P0_off exp(a sqrt(U_b / kT)), at most 1; at kT = 0 the
+// factor is 1 for U_b = 0 and unbounded otherwise.
+__device__ __forceinline__ double slip_prob(double p0, double a, double U, double kT) {
+#pragma clang fp contract(off)
+    if (kT > 0.0) {
+        const double q = p0 * exp(a * sqrt(U / kT));
+        return q < 1.0 ? q : 1.0;
+    }
+    return (U > 0.0 && a > 0.0) ? 1.0 : p0;
+}
+
+// Report a bond outside its range (FENE r >= R0, tether outside (l_min, l_max)).
+__device__ __forceinline__ void bond_range_error(const Dev& D, uint32_t i, uint32_t j) {
+    if (atomicOr(&D.err[0], kErrFene) == 0u) {
+        D.err[1] = D.tag[i];
+        D.err[2] = D.tag[j];
+    }
+}
+
 // Bond force on site i from partner position pj (bond type bt), in FP64 from
 // the exact minimum-image separation.
 __device__ __forceinline__ void bond_force(const Params& P, const Dev& D, float4 pi, float4 pj,
@@ -40,14 +119,21 @@ __device__ __forceinline__ void bond_force(const Params& P, const Dev& D, float4
     if (P.bkind[bt] == 1u) {                      // FENE: F_i = k / (1 - r^2/R0^2) d
         const double g = 1.0 - r2 * P.binvR02[bt];
         if (!(g > 0.0)) {
-            if (atomicOr(&D.err[0], kErrFene) == 0u) {
-                D.err[1] = D.tag[i];
-                D.err[2] = D.tag[j];
-            }
+            bond_range_error(D, i, j);
             return;
         }
         f = P.bk[bt] * rcp64(g);
         if (e) *e += 0.5 * (-0.5 * P.bk[bt] * P.bR02[bt] * log(g));
+    } else if (P.bkind[bt] == 2u) {               // tether: F_i = (dU/dr) / r d
+        const double r = sqrt(r2);
+        if (!(r > P.blmin[bt] && r < P.blmax[bt])) {
+            bond_range_error(D, i, j);
+            return;
+        }
+        double du;
+        const double U = tether_u(r, P.bk[bt], P.blmin[bt], P.blc1[bt], P.blc0[bt], P.blmax[bt], &du);
+        f = du / r;
+        if (e) *e += 0.5 * U;
     } else {                                      // harmonic: F_i = k (r - r0) / r d
         if (!(r2 > 0.0)) return;
         const double ir = rsqrt64(r2);
@@ -245,7 +331,7 @@ __global__ void k_fix_u(const Params P, const Dev D, int xin) {
 }
 
 // sum m v^2 of the full-step velocities (v = u + h F/m, F in f4) into ke_fix.
-__global__ __launch_bounds__(256) void k_ke_accum(const Params P, const Dev D, int xin) {
+__global__ __launch_bounds__(256) void k_ke_accum(const Params P, const Dev D, int xin, unsigned long long s) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long ke = 0ull;
     if (i < P.n) {
@@ -257,7 +343,7 @@ __global__ __launch_bounds__(256) void k_ke_accum(const Params P, const Dev D, i
         ke = (unsigned long long)rint((double)P.mass[ti] * v2 * 4294967296.0);
     }
     for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
-    if (__lane_id() == 0 && ke) atomicAdd(D.ke_fix, ke);
+    if (__lane_id() == 0 && ke) atomicAdd(&D.ke_fix[ke_slot(P, s)], ke);
 }
 
 // Block-wide exclusive scan (blockDim a multiple of 64, at most 1024).
@@ -746,13 +832,19 @@ __device__ __forceinline__ void bond_force_tab(const Params& P, const StepTabs& 
     if (T.bkind[bt] == 1u) {                      // FENE: F_i = k / (1 - r^2/R0^2) d
         const double g = 1.0 - r2 * T.binvR02[bt];
         if (!(g > 0.0)) {
-            if (atomicOr(&D.err[0], kErrFene) == 0u) {
-                D.err[1] = D.tag[i];
-                D.err[2] = D.tag[j];
-            }
+            bond_range_error(D, i, j);
             return;
         }
         f = T.bk[bt] * rcp64(g);
+    } else if (T.bkind[bt] == 2u) {               // tether: F_i = (dU/dr) / r d
+        const double r = sqrt(r2);
+        if (!(r > T.blmin[bt] && r < T.blmax[bt])) {
+            bond_range_error(D, i, j);
+            return;
+        }
+        double du;
+        (void)tether_u(r, T.bk[bt], T.blmin[bt], T.blc1[bt], T.blc0[bt], T.blmax[bt], &du);
+        f = du / r;
     } else {                                      // harmonic: F_i = k (r - r0) / r d
         if (!(r2 > 0.0)) return;
         const double ir = rsqrt64(r2);
@@ -894,7 +986,7 @@ __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int x
     }
     if (accum_ke) {
         for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
-        if (__lane_id() == 0 && ke) atomicAdd(D.ke_fix, ke);
+        if (__lane_id() == 0 && ke) atomicAdd(&D.ke_fix[ke_slot(P, s)], ke);
     }
 }
 
@@ -990,7 +1082,7 @@ __global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int 
     }
     if (accum_ke) {
         for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
-        if (__lane_id() == 0 && ke) atomicAdd(D.ke_fix, ke);
+        if (__lane_id() == 0 && ke) atomicAdd(&D.ke_fix[ke_slot(P, s)], ke);
     }
 }
 
@@ -1260,20 +1352,20 @@ __device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a
         wj[k] = (uint32_t)k < P.cap_max ? D.dyn[(size_t)k * n + j] : 0u;
     }
     const uint32_t occ_i = D.occ[i], occ_j = D.occ[j];
-    double kT = P.kT;
-    if (P.kt_kinetic) kT = (double)(*D.ke_fix) * kFixInv / (3.0 * (double)P.n);
+    const double kT = sweep_kT(P, D, s);
     const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
     const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
     const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
     const double r = norm3(dx, dy, dz);
-    const double d = r - P.r0[a];
-    const double U = P.hk[a] * (d * d);
+    const double U = bond_energy(P, P.rbt[a], r);
+    double pon = P.pon[a];
+    if (P.rmod[a] == 1u && P.kt_kinetic) pon = melt_mix(P.pon_i[a], P.pon_m[a], P.mlam[a], P.mtm[a], kT);
     double prob;
     if (kT > 0.0) {
-        prob = P.pon[a] * exp(-U / kT);
+        prob = pon * exp(-U / kT);
         prob = prob < 1.0 ? prob : 1.0;
     } else {
-        prob = U <= 0.0 ? P.pon[a] : 0.0;
+        prob = U <= 0.0 ? pon : 0.0;
     }
     const uint32_t lo = tgi < tgj ? tgi : tgj, hi = tgi < tgj ? tgj : tgi;
     const Word4 w = philox((uint32_t)s, (uint32_t)(s >> 32), lo, hi, P.seed, stream_k1(kOn, a, 0));
@@ -1490,7 +1582,7 @@ __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, in
 // draw the same number.  All slot words are loaded at once, then the
 // partners' tags.  Returns the number of bonds broken with i as the lower tag.
 __device__ __forceinline__ uint32_t break_site(const Params& P, const Dev& D, int a, unsigned long long s,
-                                               uint32_t i) {
+                                               uint32_t i, const float4* __restrict__ X) {
     const size_t n = P.n;
     uint32_t broke = 0;
     uint32_t w[kMaxValence];
@@ -1510,6 +1602,16 @@ __device__ __forceinline__ uint32_t break_site(const Params& P, const Dev& D, in
         tgj[k] = D.tag[mine[k] ? (w[k] & kIdxMask) : i];
     uint32_t occ = D.occ[i];
     const uint32_t occ0 = occ;
+    // rate modifiers: the melted P0_off at the kinetic temperature, or the
+    // slip factor from each bond's length (both ends compute the same r)
+    const uint32_t mod = P.rmod[a];
+    double poff = P.poff[a], kT = 0.0;
+    float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (mod != 0u) {
+        kT = sweep_kT(P, D, s);
+        if (mod == 1u && P.kt_kinetic) poff = melt_mix(P.poff_i[a], P.poff_m[a], P.mlam[a], P.mtm[a], kT);
+        if (mod == 2u) pi = X[i];
+    }
 #pragma unroll
     for (int k = 0; k < kMaxValence; ++k) {
         if (!mine[k]) continue;
@@ -1517,7 +1619,15 @@ __device__ __forceinline__ uint32_t break_site(const Params& P, const Dev& D, in
         if (w[k] & kNewBit) { *sl = w[k] & ~kNewBit; continue; }
         const uint32_t lo = tgi < tgj[k] ? tgi : tgj[k], hi = tgi < tgj[k] ? tgj[k] : tgi;
         const Word4 r = philox((uint32_t)s, (uint32_t)(s >> 32), lo, hi, P.seed, stream_k1(kOff, a, 0));
-        if (u53(r.w0, r.w1) < P.poff[a]) {
+        double q = poff;
+        if (mod == 2u) {
+            const float4 pj = X[w[k] & kIdxMask];
+            const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
+            const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
+            const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
+            q = slip_prob(poff, P.slip[a], bond_energy(P, P.rbt[a], norm3(dx, dy, dz)), kT);
+        }
+        if (u53(r.w0, r.w1) < q) {
             *sl = kEmpty;
             --occ;
             if (tgi < tgj[k]) ++broke;
@@ -1534,11 +1644,11 @@ __global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int 
     const unsigned long long s = D.stepv[sp];
     const int a = sweep_reaction(P, s, slot);
     const uint32_t i = xcd_block() * blockDim.x + threadIdx.x;
-    if (last && i == 0) *D.ke_fix = 0ull;
+    if (last && i == 0) D.ke_fix[ke_slot(P, s) ^ 1u] = 0ull;   // the next sweep's slot
     uint32_t broke = 0;
     if (i < P.n) {
         D.best[1][i] = kNoKey;
-        broke = break_site(P, D, a, s, i);
+        broke = break_site(P, D, a, s, i, D.x[xcur]);
     }
     count_add(D, a, kCtrBreak, broke);
 }
@@ -1568,6 +1678,26 @@ __global__ void k_gather(const Params P, const Dev D, float4* __restrict__ out, 
     } else {
         out[t] = D.f4[i];
     }
+}
+// The same read-outs as k_gather, as x, y, z triplets in tag order into
+// caller memory (out3 holds 3 n floats).
+__global__ void k_gather3(const Params P, const Dev D, float* __restrict__ out3, int xin, int mode) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P.n) return;
+    const uint32_t i = D.rtag[t];
+    float4 v;
+    if (mode == 0) {
+        v = D.x[xin][i];
+    } else if (mode == 1) {
+        const float hm = P.h * P.inv_mass[type_of(D.x[xin][i])];
+        const float4 u = D.u[i], f = D.f4[i];
+        v = make_float4(u.x + hm * f.x, u.y + hm * f.y, u.z + hm * f.z, 0.0f);
+    } else {
+        v = D.f4[i];
+    }
+    out3[3 * (size_t)t] = v.x;
+    out3[3 * (size_t)t + 1] = v.y;
+    out3[3 * (size_t)t + 2] = v.z;
 }
 __global__ void k_gather_img(const Params P, const Dev D, int32_t* __restrict__ out) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libdybond.so")
 DB_OK, DB_EINVAL, DB_ENOMEM, DB_EDEVICE, DB_ESTATE, DB_ERANGE, DB_EBOND, DB_ETRUNC, DB_EOVERFLOW = range(9)
 STATUS_NAMES = ["DB_OK", "DB_EINVAL", "DB_ENOMEM", "DB_EDEVICE", "DB_ESTATE", "DB_ERANGE",
                 "DB_EBOND", "DB_ETRUNC", "DB_EOVERFLOW"]
-DB_BOND_HARMONIC, DB_BOND_FENE = 0, 1
+DB_BOND_HARMONIC, DB_BOND_FENE, DB_BOND_TETHER = 0, 1, 2
 DB_KT_SETPOINT, DB_KT_KINETIC = 0, 1
 MAX_RX = 8
 
@@ -70,6 +70,10 @@ _SIGS = {
     "db_set_type": (_I, [_P, _U32, _U32, _D, _D, _D]),
     "db_set_particles": (_I, [_P, _P, _P, _P]),
     "db_add_bond_type": (_I, [_P, _I, _D, _D, ctypes.POINTER(_U32)]),
+    "db_add_tether_bond_type": (_I, [_P, _D, _D, _D, _D, _D, ctypes.POINTER(_U32)]),
+    "db_set_reaction_melting": (_I, [_P, _U32, _D, _D, _D, _D]),
+    "db_set_reaction_slip": (_I, [_P, _U32, _D]),
+    "db_set_temperature": (_I, [_P, _D]),
     "db_add_static_bonds": (_I, [_P, _P, _P, _U64]),
     "db_add_reaction": (_I, [_P, ctypes.POINTER(ReactionDesc), ctypes.POINTER(_U32)]),
     "db_set_integrator": (_I, [_P, _D, _D, _D, _U32, _I]),
@@ -94,6 +98,9 @@ _SIGS = {
     "db_read_forces": (_I, [_P, _P]),
     "db_read_bonds": (_I, [_P, _P, _P, _U64, ctypes.POINTER(_U64)]),
     "db_read_observables": (_I, [_P, ctypes.POINTER(Observables)]),
+    "db_read_positions_device": (_I, [_P, _P, _P]),
+    "db_read_velocities_device": (_I, [_P, _P, _P]),
+    "db_read_forces_device": (_I, [_P, _P, _P]),
     "db_get_step": (_U64, [_P]),
     "db_last_error": (ctypes.c_char_p, [_P]),
     "db_set_stream": (_I, [_P, _P]),
@@ -168,6 +175,24 @@ def db_add_bond_type(h, kind, k, r0):
     i = _U32()
     _check(h, load().db_add_bond_type(h, kind, k, r0, ctypes.byref(i)))
     return i.value
+
+
+def db_add_tether_bond_type(h, k_b, l_min, l_c1, l_c0, l_max):
+    i = _U32()
+    _check(h, load().db_add_tether_bond_type(h, k_b, l_min, l_c1, l_c0, l_max, ctypes.byref(i)))
+    return i.value
+
+
+def db_set_reaction_melting(h, reaction, lam, T_melt, k_on_melt, k_off_melt):
+    _check(h, load().db_set_reaction_melting(h, reaction, lam, T_melt, k_on_melt, k_off_melt))
+
+
+def db_set_reaction_slip(h, reaction, a):
+    _check(h, load().db_set_reaction_slip(h, reaction, a))
+
+
+def db_set_temperature(h, kT):
+    _check(h, load().db_set_temperature(h, kT))
 
 
 def db_add_static_bonds(h, pairs, bond_types):
@@ -370,6 +395,21 @@ def db_read_observables(h):
             "PE": o.pe, "KE": o.ke, "T_kin": o.t_kin}
 
 
+def db_read_positions_device(h, dev_ptr, stream=None):
+    """Positions (3 n floats, tag order) into device memory at dev_ptr (an
+    integer address, e.g. tensor.data_ptr()), enqueued on `stream` (an
+    integer hipStream_t, e.g. torch.cuda.current_stream().cuda_stream)."""
+    _check(h, load().db_read_positions_device(h, dev_ptr, stream))
+
+
+def db_read_velocities_device(h, dev_ptr, stream=None):
+    _check(h, load().db_read_velocities_device(h, dev_ptr, stream))
+
+
+def db_read_forces_device(h, dev_ptr, stream=None):
+    _check(h, load().db_read_forces_device(h, dev_ptr, stream))
+
+
 def db_get_step(h):
     return int(load().db_get_step(h))
 
@@ -475,12 +515,21 @@ class System:
         for t, (val, sig, eps, m) in enumerate(w.types):
             db_set_type(s.h, t, val, sig, eps, m)
         db_set_particles(s.h, w.pos, w.vel, w.type_id)
-        for kind, k, r0 in w.bond_types:
-            db_add_bond_type(s.h, kind, k, r0)
+        for bt in w.bond_types:
+            if bt[0] == DB_BOND_TETHER:                # (kind, k_b, l_min, l_c1, l_c0, l_max)
+                db_add_tether_bond_type(s.h, *bt[1:])
+            else:
+                db_add_bond_type(s.h, *bt)
         if len(w.static_pairs):
             db_add_static_bonds(s.h, w.static_pairs, w.static_types)
-        for r in w.reactions:
+        for a, r in enumerate(w.reactions):
+            r = dict(r)
+            melt, slip = r.pop("melt", None), r.pop("slip", None)
             db_add_reaction(s.h, make_reaction(**r))
+            if melt is not None:
+                db_set_reaction_melting(s.h, a, *melt)
+            if slip is not None:
+                db_set_reaction_slip(s.h, a, slip)
         db_set_integrator(s.h, w.dt, w.kT, w.gamma, w.period, kt_source)
         if commit:
             db_commit(s.h)

@@ -46,10 +46,11 @@ class Workload:
     pos: np.ndarray        # (n, 3) float32 in [-L/2, L/2)
     vel: np.ndarray        # (n, 3) float32
     type_id: np.ndarray    # (n,) uint32
-    bond_types: list       # (kind, k, r0 or R0)
+    bond_types: list       # (kind, k, r0 or R0), or (tether kind, k_b, l_min, l_c1, l_c0, l_max)
     static_pairs: np.ndarray   # (m, 2) uint32 tags
     static_types: np.ndarray   # (m,) uint32
-    reactions: list        # dicts: type_a, type_b, bond_type, r_min, r_max, k_on, k_off, epsilon, p_on0, self_avoid
+    reactions: list        # dicts: type_a, type_b, bond_type, r_min, r_max, k_on, k_off, epsilon, p_on0, self_avoid,
+                           # optionally melt = (lambda, T_melt, k_on_melt, k_off_melt) or slip = a
     dt: float = 0.005
     kT: float = 1.0
     gamma: float = 1.0

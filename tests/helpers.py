@@ -11,13 +11,22 @@ def oracle_from_workload(w, kinetic_T=False):
     o = OracleSystem(w.n, len(w.types), w.L, w.seed)
     for t, (val, sig, eps, m) in enumerate(w.types):
         o.set_type(t, val, sig, eps, m)
-    for kind, k, r0 in w.bond_types:
-        o.add_bond_type(kind, k, r0)
+    for bt in w.bond_types:
+        if bt[0] == 2:                                  # tether: (kind, k_b, l_min, l_c1, l_c0, l_max)
+            o.add_tether_bond_type(*bt[1:])
+        else:
+            o.add_bond_type(*bt)
     o.set_particles(w.pos, w.vel, w.type_id)
     if len(w.static_pairs):
         o.add_static_bonds(w.static_pairs, w.static_types)
-    for r in w.reactions:
+    for a, r in enumerate(w.reactions):
+        r = dict(r)
+        melt, slip = r.pop("melt", None), r.pop("slip", None)
         o.add_reaction(Reaction(**r))
+        if melt is not None:
+            o.set_melting(a, *melt)
+        if slip is not None:
+            o.set_slip(a, slip)
     o.set_integrator(w.dt, w.kT, w.gamma, w.period, kinetic_T)
     o.commit()
     return o

@@ -115,6 +115,54 @@ def test_batch_plans_are_validated_before_any_device_call():
         a.close()
 
 
+def test_tether_bonds_and_rate_modifiers_are_validated_on_host():
+    ok = dict(epsilon=2.0, p_on0=0.5)
+    R = db.make_reaction
+    with db.System(2, 2, 6.0, 1) as s:
+        for bad in ((-1.0, 0.5, 0.8, 1.2, 1.6), (1.0, 0.9, 0.8, 1.2, 1.6), (1.0, 0.5, 0.8, 1.6, 1.6),
+                    (1.0, -0.1, 0.8, 1.2, 1.6), (1.0, 0.5, 0.8, 1.2, math.inf)):
+            assert _status_of(lambda: db.db_add_tether_bond_type(s.h, *bad)) == "DB_EINVAL", bad
+        assert db.db_add_tether_bond_type(s.h, 1.0, 0.5, 0.8, 1.2, 1.6) == 0
+
+    def status(rx, tether=False, setup=None):
+        s = _two_particle(None)
+        try:
+            bt = db.db_add_tether_bond_type(s.h, 1.0, 0.5, 0.8, 1.2, 1.6) if tether else 0
+            rx.bond_type = bt
+            db.db_add_reaction(s.h, rx)
+            if setup:
+                setup(s.h)
+            db.db_validate(s.h)
+            return "DB_OK"
+        except db.DybondError as e:
+            return e.name
+        finally:
+            s.close()
+    # a tether reaction's window must lie inside (l_min, l_max)
+    assert status(R(0, 1, 0, 0.6, 1.5, self_avoid=0, **ok), tether=True) == "DB_OK"
+    assert status(R(0, 1, 0, 0.4, 1.5, self_avoid=0, **ok), tether=True) == "DB_EINVAL"
+    assert status(R(0, 1, 0, 0.6, 1.7, self_avoid=0, **ok), tether=True) == "DB_EINVAL"
+    # modifiers: ranges, melted k n dt <= 1, mutual exclusion, unknown reaction
+    assert status(R(0, 1, 0, 0.0, 1.3, self_avoid=0, **ok),
+                  setup=lambda h: db.db_set_reaction_melting(h, 0, 5.0, 1.1, 0.0, 2.0)) == "DB_OK"
+    assert status(R(0, 1, 0, 0.0, 1.3, self_avoid=0, **ok),
+                  setup=lambda h: db.db_set_reaction_melting(h, 0, 5.0, 1.1, 0.0, 30.0)) == "DB_ERANGE"
+    assert status(R(0, 1, 0, 0.0, 1.3, self_avoid=0, **ok),
+                  setup=lambda h: db.db_set_reaction_melting(h, 0, -1.0, 1.1, 0.0, 1.0)) == "DB_EINVAL"
+    assert status(R(0, 1, 0, 0.0, 1.3, self_avoid=0, **ok),
+                  setup=lambda h: db.db_set_reaction_slip(h, 0, 1.5)) == "DB_OK"
+    assert status(R(0, 1, 0, 0.0, 1.3, self_avoid=0, **ok),
+                  setup=lambda h: db.db_set_reaction_slip(h, 0, -0.5)) == "DB_EINVAL"
+    assert status(R(0, 1, 0, 0.0, 1.3, self_avoid=0, **ok),
+                  setup=lambda h: (db.db_set_reaction_slip(h, 0, 1.0),
+                                   db.db_set_reaction_melting(h, 0, 5.0, 1.1, 0.0, 1.0))) == "DB_EINVAL"
+    assert status(R(0, 1, 0, 0.0, 1.3, self_avoid=0, **ok),
+                  setup=lambda h: db.db_set_reaction_slip(h, 3, 1.0)) == "DB_EINVAL"
+    with db.System(2, 2, 6.0, 1) as s:
+        assert _status_of(lambda: db.db_set_temperature(s.h, -1.0)) == "DB_EINVAL"
+        db.db_set_temperature(s.h, 0.0)
+
+
 def test_rate_closure_matches_oracle_bit_for_bit():
     w = inputs.small(seed=1)
     cases = [dict(epsilon=5.0, p_on0=1.0), dict(k_on=3.0, k_off=0.5), dict(k_on=1.5, epsilon=2.0),
@@ -176,8 +224,10 @@ def test_validation_errors_on_host():
     assert _validate_status(R(0, 1, 0, 0.0, 1.3, k_on=3.0, self_avoid=0)) == "DB_EINVAL"
     # inconsistent over-specification
     assert _validate_status(R(0, 1, 0, 0.0, 1.3, k_on=3.0, k_off=1.0, epsilon=2.0, self_avoid=0)) == "DB_EINVAL"
-    # dynamic bonds must be harmonic; window must be ordered
-    assert _validate_status(R(0, 1, 1, 0.0, 1.3, self_avoid=0, **ok)) == "DB_EINVAL"
+    # a FENE bond (R0 = 1.5) may be a reaction's bond when the window ends below R0;
+    # the window must be ordered
+    assert _validate_status(R(0, 1, 1, 0.0, 1.5, self_avoid=0, **ok)) == "DB_EINVAL"
+    assert _validate_status(R(0, 1, 1, 0.0, 1.3, self_avoid=0, **ok)) == "DB_OK"
     assert _validate_status(R(0, 1, 0, 1.3, 1.3, self_avoid=0, **ok)) == "DB_EINVAL"
     # box must hold 3 cells of the search radius
     assert _validate_status(R(0, 1, 0, 0.0, 1.3, self_avoid=0, **ok), L=3.8) == "DB_EINVAL"
