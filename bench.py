@@ -13,6 +13,7 @@ oracle timed on a bounded sample of the same workload.
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -39,6 +40,8 @@ def parse():
     p.add_argument("--skin", type=float, default=None, help="neighbour-list skin (default: the library's)")
     p.add_argument("--step-threads", type=int, default=0,
                    help="threads per particle in the step kernel (0: the library's choice)")
+    p.add_argument("--modifier", default="none", choices=["none", "slip", "melt"],
+                   help="rate modifier on every reaction: slip bonds (a = 1) or melting with T_melt = kT")
     p.add_argument("--list-batch", type=int, default=0,
                    help="list entries per thread loaded up front in the step kernel (0: the library's choice)")
     p.add_argument("--replicas", type=int, default=1024,
@@ -186,6 +189,14 @@ def main():
         w = inputs.gel_lattice(seed=a.seed, n=a.n or 200000)
     else:
         w = inputs.WORKLOADS[a.workload](seed=a.seed)
+    if a.modifier != "none":
+        ndt = w.period * w.dt
+        for r in w.reactions:
+            if a.modifier == "slip":
+                r["slip"] = 1.0
+            else:                       # half bound at T_melt = kT: k_on_melt 0, k_off_melt = k_on - k_off
+                k_on = r["p_on0"] / ndt
+                r["melt"] = (5.0, w.kT, 0.0, k_on - k_on * math.exp(-r["epsilon"]))
     tag = f"{w.name}{w.n // 1000}k"
     if a.calibrate_copy:
         src = torch.empty(a.calibrate_copy << 18, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -241,7 +252,7 @@ def main():
         "config": {"workload": tag, "n_particles": w.n, "box_L": round(w.L, 4),
                    "types": len(w.types), "reactions": len(w.reactions),
                    "sweep_period": w.period, "dt": w.dt, "kT": w.kT, "gamma": w.gamma,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", **({"modifier": a.modifier} if a.modifier != "none" else {})},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "copy_gbs": copy_gbs,
                      "traffic": traffic,

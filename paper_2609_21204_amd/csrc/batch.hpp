@@ -51,6 +51,7 @@ __device__ __forceinline__ void bin_particle_wg(const Params& P, const Dev& D, i
 
 // Total force on particle i at X (list + bonds), one thread, in 2^-32 fixed
 // point.  List entries are taken 8 at a time with all their loads in flight.
+template <bool EXT>
 __device__ __forceinline__ Force3 force_site(const Params& P, const StepTabs& T, const Dev& D,
                                              const float4* __restrict__ X, uint32_t i, float4 pi) {
     const size_t n = P.n;
@@ -70,13 +71,13 @@ __device__ __forceinline__ Force3 force_site(const Params& P, const StepTabs& T,
     }
     for (uint32_t b = 0; b < P.stat_max; ++b) {
         const uint32_t w = D.stat[(size_t)b * n + i];
-        if (w != kEmpty) bond_force_tab(P, T, D, pi, X[w & kIdxMask], w >> 24, i, w & kIdxMask, fx, fy, fz);
+        if (w != kEmpty) bond_force_tab<EXT>(P, T, D, pi, X[w & kIdxMask], w >> 24, i, w & kIdxMask, fx, fy, fz);
     }
     const uint32_t cap = T.cap[ti];
     for (uint32_t b = 0; b < cap; ++b) {
         const uint32_t w = D.dyn[(size_t)b * n + i];
         if (w != kEmpty)
-            bond_force_tab(P, T, D, pi, X[w & kIdxMask], T.rbt[(w >> 24) & 0x7Fu], i, w & kIdxMask, fx, fy, fz);
+            bond_force_tab<EXT>(P, T, D, pi, X[w & kIdxMask], T.rbt[(w >> 24) & 0x7Fu], i, w & kIdxMask, fx, fy, fz);
     }
     return fix_to_force(D, fx, fy, fz);
 }
@@ -137,6 +138,7 @@ __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T
 // Any workgroup size that is a multiple of 64 up to kBatchMaxThreads gives
 // the same result: particles are dealt out round robin over the threads and
 // every sum is exact.
+template <bool EXT>
 __global__ __launch_bounds__(kBatchMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state, uint32_t nsteps) {
     const BatchItem& B = items[blockIdx.x];
@@ -167,7 +169,7 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
             const float4 ui = D.u[i];
             const uint32_t tg = D.tag[i];
             const float4 r = D.xref[i];
-            const Force3 F = force_site(P, T, D, X, i, pi);
+            const Force3 F = force_site<EXT>(P, T, D, X, i, pi);
             float4 po;
             ke += advance_particle(P, T, D, xin, i, pi, type_of(pi), F, ui, tg, s, ake, po);
             bin_particle_wg(P, D, lnext, i, po);
@@ -228,7 +230,7 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
                         D.claimed[i] = 1;
                         D.claimed[j] = 1;
                         ++att;
-                        form += accept_pair(P, D, a, s, Xs, i, j) ? 1u : 0u;
+                        form += accept_pair<EXT>(P, D, a, s, Xs, i, j) ? 1u : 0u;
                     }
                 }
                 __syncthreads();
@@ -251,7 +253,7 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
             count_add(D, a, kCtrAttempt, att);
             count_add(D, a, kCtrForm, form);
             uint32_t broke = 0;
-            for (uint32_t i = tid; i < n; i += bs) broke += break_site(P, D, a, s, i, Xs);
+            for (uint32_t i = tid; i < n; i += bs) broke += break_site<EXT>(P, D, a, s, i, Xs);
             count_add(D, a, kCtrBreak, broke);
             __syncthreads();
         }

@@ -124,6 +124,7 @@ struct Params {
     uint32_t tpp;                      // threads per particle in k_propose (host side: launch shape)
     uint32_t tpp_step;                 // threads per particle in k_step
     uint32_t qb_step;                  // list entries per thread issued up front in k_step (0: by TPP)
+    uint32_t ext;                      // tether bonds or rate modifiers present: kernels in their full variant
     float disp2;                       // (skin / 2 - 1e-4)^2: displacement that triggers a rebuild
     uint32_t nlmax;                    // neighbour-list slots per particle
     double kT;

@@ -146,6 +146,13 @@ struct TimerScope {
 // runtime stamps when the kernel itself begins and ends (not when the stream
 // reaches the launch), so the per-kernel times are kernel execution times.
 #define LAUNCH(sys, kern, grid, block, ...) LAUNCH_AS(sys, #kern, kern, grid, block, __VA_ARGS__)
+// kernels built in two variants: the full one for systems with tether bonds
+// or rate modifiers, the lean one otherwise
+#define LAUNCH_EXT(sys, tname, kern, grid, block, ...)                                       \
+    do {                                                                                     \
+        if ((sys)->P.ext) LAUNCH_AS(sys, tname, (kern<true>), grid, block, __VA_ARGS__);     \
+        else LAUNCH_AS(sys, tname, (kern<false>), grid, block, __VA_ARGS__);                 \
+    } while (0)
 // the same, with the name the kernel is timed under given explicitly
 #define LAUNCH_AS(sys, tname, kern, grid, block, ...)                                            \
     do {                                                                                         \
@@ -483,6 +490,7 @@ void fill_params(db_system* s) {
         P.blc1[b] = s->bonds[b].lc1;
         P.blc0[b] = s->bonds[b].lc0;
         P.blmax[b] = s->bonds[b].lmax;
+        if (s->bonds[b].kind == DB_BOND_TETHER) P.ext = 1u;
     }
     for (size_t a = 0; a < s->rx.size(); ++a) {
         const auto& d = s->rx[a];
@@ -501,6 +509,7 @@ void fill_params(db_system* s) {
         P.pon[a] = s->res[a].p_on;
         P.poff[a] = s->res[a].p_off;
         const RxMod& m = s->mods[a];
+        if (m.kind != 0 || bc.kind != DB_BOND_HARMONIC) P.ext = 1u;
         P.rmod[a] = (uint32_t)m.kind;
         P.slip[a] = m.a;
         if (m.kind == 1) {
@@ -680,15 +689,15 @@ void launch_sweep(db_system* s, int xcur, int sp) {
             case 16: LAUNCH(s, k_propose<16>, gp, kBlock, P, s->D, slot, xcur, sp); break;
             default: LAUNCH(s, k_propose<32>, gp, kBlock, P, s->D, slot, xcur, sp); break;
         }
-        LAUNCH(s, k_claim, g, kBlock, P, s->D, slot, 1, xcur, sp);
+        LAUNCH_EXT(s, "k_claim", k_claim, g, kBlock, P, s->D, slot, 1, xcur, sp);
         const int R = (int)s->match_rounds;
         for (int q = 2; q <= R; ++q) {
             LAUNCH(s, k_kill, g, kBlock, P, s->D, q, 0);
-            LAUNCH(s, k_claim, g, kBlock, P, s->D, slot, q, xcur, sp);
+            LAUNCH_EXT(s, "k_claim", k_claim, g, kBlock, P, s->D, slot, q, xcur, sp);
         }
         LAUNCH(s, k_kill, g, kBlock, P, s->D, R + 1, 1);
-        LAUNCH(s, k_finish, 1, 1024, P, s->D, slot, (R + 1) % 3, xcur, sp, s->finish_lds);
-        LAUNCH(s, k_break, g, kBlock, P, s->D, slot, xcur, sp, slot == (int)P.nrx - 1 ? 1 : 0);
+        LAUNCH_EXT(s, "k_finish", k_finish, 1, 1024, P, s->D, slot, (R + 1) % 3, xcur, sp, s->finish_lds);
+        LAUNCH_EXT(s, "k_break", k_break, g, kBlock, P, s->D, slot, xcur, sp, slot == (int)P.nrx - 1 ? 1 : 0);
     }
 }
 
@@ -719,20 +728,36 @@ void launch_step(db_system* s) {
     const bool sweep = P.nrx > 0 && ((t + 1) % P.period == 0);
     const int ake = (sweep && P.kt_kinetic) ? 1 : 0;
     const unsigned gs = (unsigned)(((uint64_t)P.n * P.tpp_step + kBlock - 1) / kBlock);
-    switch (P.tpp_step) {
-        case 1: LAUNCH_AS(s, "k_step", k_step1, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
-        case 2: LAUNCH(s, k_step<2>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
-        case 4:
-            if (P.qb_step == 1)
-                LAUNCH_AS(s, "k_step", (k_step<4, 1>), gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake);
-            else if (P.qb_step == 2)
-                LAUNCH_AS(s, "k_step", (k_step<4, 2>), gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake);
-            else LAUNCH(s, k_step<4>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake);
-            break;
-        case 8: LAUNCH(s, k_step<8>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
-        case 16: LAUNCH(s, k_step<16>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
-        default: LAUNCH(s, k_step<32>, gs, kBlock, P, s->D, xin, lnext, lclr, sp, (int)(t % 3), ake); break;
+    const int f3 = (int)(t % 3);
+#define STEP_AS(...) LAUNCH_AS(s, "k_step", (__VA_ARGS__), gs, kBlock, P, s->D, xin, lnext, lclr, sp, f3, ake)
+    if (P.ext) {
+        switch (P.tpp_step) {
+            case 1: STEP_AS(k_step1<true>); break;
+            case 2: STEP_AS(k_step<2, 0, true>); break;
+            case 4:
+                if (P.qb_step == 1) STEP_AS(k_step<4, 1, true>);
+                else if (P.qb_step == 2) STEP_AS(k_step<4, 2, true>);
+                else STEP_AS(k_step<4, 0, true>);
+                break;
+            case 8: STEP_AS(k_step<8, 0, true>); break;
+            case 16: STEP_AS(k_step<16, 0, true>); break;
+            default: STEP_AS(k_step<32, 0, true>); break;
+        }
+    } else {
+        switch (P.tpp_step) {
+            case 1: STEP_AS(k_step1<false>); break;
+            case 2: STEP_AS(k_step<2, 0, false>); break;
+            case 4:
+                if (P.qb_step == 1) STEP_AS(k_step<4, 1, false>);
+                else if (P.qb_step == 2) STEP_AS(k_step<4, 2, false>);
+                else STEP_AS(k_step<4, 0, false>);
+                break;
+            case 8: STEP_AS(k_step<8, 0, false>); break;
+            case 16: STEP_AS(k_step<16, 0, false>); break;
+            default: STEP_AS(k_step<32, 0, false>); break;
+        }
     }
+#undef STEP_AS
     LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, lnext, (int)((t + 1) % 3));
     s->cur_x ^= 1;
     s->cur_list = lnext;
@@ -1283,17 +1308,21 @@ db_status run_batch(db_system* const* systems, uint32_t count, uint64_t nsteps, 
     if (nsteps == 0) return DB_OK;
     // classes in plan order; largest systems first inside a class, so that
     // their workgroups start in the first wave
-    std::vector<std::vector<uint32_t>> groups(plan.n_classes);
-    for (uint32_t k = 0; k < count; ++k) groups[class_of(plan, systems[k]->n)].push_back(k);
+    // groups: (class, kernel variant); systems with tether bonds or rate
+    // modifiers run the full variant of the kernel
+    std::vector<std::vector<uint32_t>> groups(2 * plan.n_classes);
+    for (uint32_t k = 0; k < count; ++k)
+        groups[2 * class_of(plan, systems[k]->n) + (systems[k]->P.ext ? 1 : 0)].push_back(k);
     std::vector<uint32_t> order;
-    std::vector<std::pair<uint32_t, uint32_t>> spans;    // (offset, size) of each occupied class
-    std::vector<uint32_t> threads;
-    for (uint32_t g = 0; g < plan.n_classes; ++g) {
+    std::vector<std::pair<uint32_t, uint32_t>> spans;    // (offset, size) of each occupied group
+    std::vector<uint32_t> threads, full;
+    for (uint32_t g = 0; g < 2 * plan.n_classes; ++g) {
         auto& v = groups[g];
         if (v.empty()) continue;
         std::stable_sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) { return systems[a]->n > systems[b]->n; });
         spans.emplace_back((uint32_t)order.size(), (uint32_t)v.size());
-        threads.push_back(plan.threads[g]);
+        threads.push_back(plan.threads[g / 2]);
+        full.push_back(g & 1u);
         order.insert(order.end(), v.begin(), v.end());
     }
     std::vector<BatchItem> items(count);
@@ -1332,7 +1361,7 @@ db_status run_batch(db_system* const* systems, uint32_t count, uint64_t nsteps, 
         for (size_t g = 1; g < spans.size(); ++g) join.push_back(R.event());
         if (!fork || !t_a || !t_b || std::find(join.begin(), join.end(), nullptr) != join.end())
             return dev_fail("event creation failed");
-        // capture: one branch per occupied class, a chain of launches each
+        // capture: one branch per occupied group, a chain of launches each
         bool ok = hipStreamBeginCapture(s0->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             ok = hipEventRecord(fork, s0->stream) == hipSuccess;
@@ -1341,8 +1370,12 @@ db_status run_batch(db_system* const* systems, uint32_t count, uint64_t nsteps, 
                 hipStream_t q = g ? R.streams[g - 1] : s0->stream;
                 for (uint64_t done = 0; ok && done < nsteps;) {
                     const uint32_t chunk = (uint32_t)std::min<uint64_t>(kBatchChunk, nsteps - done);
-                    hipLaunchKernelGGL(k_batch, dim3(spans[g].second), dim3(threads[g]), 0, q,
-                                       (const BatchItem*)(R.items + spans[g].first), R.state + spans[g].first, chunk);
+                    if (full[g])
+                        hipLaunchKernelGGL(k_batch<true>, dim3(spans[g].second), dim3(threads[g]), 0, q,
+                                           (const BatchItem*)(R.items + spans[g].first), R.state + spans[g].first, chunk);
+                    else
+                        hipLaunchKernelGGL(k_batch<false>, dim3(spans[g].second), dim3(threads[g]), 0, q,
+                                           (const BatchItem*)(R.items + spans[g].first), R.state + spans[g].first, chunk);
                     ok = hipGetLastError() == hipSuccess;
                     done += chunk;
                 }

@@ -820,6 +820,9 @@ __device__ __forceinline__ void pair_force_tab(const Params& P, const StepTabs& 
 
 // Bond force on site i from partner j (bond type bt), FP64 from the exact
 // minimum-image separation, constants from LDS.
+// EXT: the system has tether bonds or rate modifiers (kernels are built in
+// two variants, so that systems without them keep the lean register budget).
+template <bool EXT>
 __device__ __forceinline__ void bond_force_tab(const Params& P, const StepTabs& T, const Dev& D, float4 pi,
                                                float4 pj, uint32_t bt, uint32_t i, uint32_t j,
                                                long long& fx, long long& fy, long long& fz) {
@@ -836,7 +839,7 @@ __device__ __forceinline__ void bond_force_tab(const Params& P, const StepTabs& 
             return;
         }
         f = T.bk[bt] * rcp64(g);
-    } else if (T.bkind[bt] == 2u) {               // tether: F_i = (dU/dr) / r d
+    } else if (EXT && T.bkind[bt] == 2u) {        // tether: F_i = (dU/dr) / r d
         const double r = sqrt(r2);
         if (!(r > T.blmin[bt] && r < T.blmax[bt])) {
             bond_range_error(D, i, j);
@@ -876,7 +879,7 @@ __device__ __forceinline__ void bond_force_tab(const Params& P, const StepTabs& 
 //   xin = buffer of x_t, lnext = cell list receiving x_{t+1}, lclr = list
 //   cleared for the step after, sp = t mod 2, f3 = t mod 3.
 //   QB (if not 0) = list entries per thread issued up front.
-template <int TPP, int QB = 0>
+template <int TPP, int QB = 0, bool EXT = false>
 __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
                                               int f3, int accum_ke) {
     static_assert(TPP >= 1 && TPP <= 64, "256 threads per workgroup");
@@ -945,9 +948,9 @@ __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int x
             pair_force_tab(P, T, D.err, pi, X[D.nl[k * n + i]], ti, fx, fy, fz);
         auto bond = [&](uint32_t b, uint32_t w, float4 pw) {
             const uint32_t j = w & kIdxMask;
-            if (b < P.stat_max) bond_force_tab(P, T, D, pi, pw, w >> 24, i, j, fx, fy, fz);
+            if (b < P.stat_max) bond_force_tab<EXT>(P, T, D, pi, pw, w >> 24, i, j, fx, fy, fz);
             else if (b - P.stat_max < T.cap[ti])
-                bond_force_tab(P, T, D, pi, pw, T.rbt[(w >> 24) & 0x7Fu], i, j, fx, fy, fz);
+                bond_force_tab<EXT>(P, T, D, pi, pw, T.rbt[(w >> 24) & 0x7Fu], i, j, fx, fy, fz);
         };
 #pragma unroll
         for (int q = 0; q < BQ; ++q)
@@ -997,6 +1000,7 @@ __global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int x
 // together, takes further list entries 4 at a time the same way, and goes
 // on to the integration with its force in registers (no LDS reduction, one
 // barrier).  Same arguments and the same result bit for bit as k_step<TPP>.
+template <bool EXT = false>
 __global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
                                                int f3, int accum_ke) {
     constexpr int Q = 4, BQ = 4;
@@ -1062,9 +1066,9 @@ __global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int 
         }
         auto bond = [&](uint32_t b, uint32_t w, float4 pw) {
             const uint32_t j = w & kIdxMask;
-            if (b < P.stat_max) bond_force_tab(P, T, D, pi, pw, w >> 24, i, j, fx, fy, fz);
+            if (b < P.stat_max) bond_force_tab<EXT>(P, T, D, pi, pw, w >> 24, i, j, fx, fy, fz);
             else if (b - P.stat_max < T.cap[ti])
-                bond_force_tab(P, T, D, pi, pw, T.rbt[(w >> 24) & 0x7Fu], i, j, fx, fy, fz);
+                bond_force_tab<EXT>(P, T, D, pi, pw, T.rbt[(w >> 24) & 0x7Fu], i, j, fx, fy, fz);
         };
 #pragma unroll
         for (int q = 0; q < BQ; ++q)
@@ -1340,6 +1344,7 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
 // Acceptance of a claimed pair (Eq. pon): returns true when the bond forms,
 // in which case both sites get the bond in their first free slot.  The
 // positions, tags and all slot words of both sites are loaded together.
+template <bool EXT>
 __device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a, unsigned long long s,
                                             const float4* __restrict__ X, uint32_t i, uint32_t j) {
     const size_t n = P.n;
@@ -1357,9 +1362,14 @@ __device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a
     const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
     const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
     const double r = norm3(dx, dy, dz);
-    const double U = bond_energy(P, P.rbt[a], r);
-    double pon = P.pon[a];
-    if (P.rmod[a] == 1u && P.kt_kinetic) pon = melt_mix(P.pon_i[a], P.pon_m[a], P.mlam[a], P.mtm[a], kT);
+    double U, pon = P.pon[a];
+    if (EXT) {
+        U = bond_energy(P, P.rbt[a], r);
+        if (P.rmod[a] == 1u && P.kt_kinetic) pon = melt_mix(P.pon_i[a], P.pon_m[a], P.mlam[a], P.mtm[a], kT);
+    } else {                                      // harmonic, the same arithmetic as bond_energy
+        const double d = r - P.r0[a];
+        U = P.hk[a] * (d * d);
+    }
     double prob;
     if (kT > 0.0) {
         prob = pon * exp(-U / kT);
@@ -1387,6 +1397,7 @@ __device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a
 
 // Claim round q: a live proposal whose key is the minimum at both of its
 // sites is part of the greedy matching; it is claimed and tried at once.
+template <bool EXT>
 __global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int slot, int q,
                                                int xcur, int sp) {
     const unsigned long long s = D.stepv[sp];
@@ -1404,7 +1415,7 @@ __global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int 
             D.estate[i] = kEdgeMatched;
             D.claimed[i] = 1;
             D.claimed[j] = 1;
-            formed = accept_pair(P, D, a, s, D.x[xcur], i, j) ? 1u : 0u;
+            formed = accept_pair<EXT>(P, D, a, s, D.x[xcur], i, j) ? 1u : 0u;
         }
     }
     count_add(D, a, kCtrAttempt, matched);
@@ -1455,6 +1466,7 @@ constexpr uint32_t kFinishLds = 256;    // live proposals matched inside LDS by 
 // smaller key; then live edges touching a claimed site die.  Claimed edges
 // are vertex-disjoint and acceptance depends only on the pair, so they are
 // all tried after the last round.
+template <bool EXT>
 __device__ __forceinline__ void finish_in_lds(const Params& P, const Dev& D, int a, unsigned long long s,
                                               int xcur, unsigned long long* B, uint32_t count) {
     __shared__ uint32_t ei[kFinishLds], ej[kFinishLds];
@@ -1504,7 +1516,7 @@ __device__ __forceinline__ void finish_in_lds(const Params& P, const Dev& D, int
             D.claimed[i] = 1;
             D.claimed[j] = 1;
             att = 1;
-            form = accept_pair(P, D, a, s, D.x[xcur], i, j) ? 1u : 0u;
+            form = accept_pair<EXT>(P, D, a, s, D.x[xcur], i, j) ? 1u : 0u;
         } else {
             D.estate[i] = kEdgeDead;
         }
@@ -1515,6 +1527,7 @@ __device__ __forceinline__ void finish_in_lds(const Params& P, const Dev& D, int
     }
 }
 
+template <bool EXT>
 __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, int slot, int buf,
                                                  int xcur, int sp, uint32_t lds_limit) {
     const unsigned long long s = D.stepv[sp];
@@ -1522,7 +1535,7 @@ __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, in
     unsigned long long* B = D.best[buf];
     const uint32_t count = D.live_count[0];
     if (count <= lds_limit && count <= kFinishLds) {
-        finish_in_lds(P, D, a, s, xcur, B, count);
+        finish_in_lds<EXT>(P, D, a, s, xcur, B, count);
         return;
     }
     __shared__ int any;
@@ -1557,7 +1570,7 @@ __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, in
                 D.claimed[i] = 1;
                 D.claimed[j] = 1;
                 atomicAdd(&n_att, 1u);
-                if (accept_pair(P, D, a, s, D.x[xcur], i, j)) atomicAdd(&n_form, 1u);
+                if (accept_pair<EXT>(P, D, a, s, D.x[xcur], i, j)) atomicAdd(&n_form, 1u);
             }
         }
         __threadfence();
@@ -1581,6 +1594,7 @@ __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, in
 // sweep only lose their "new" mark.  Each site edits its own slots; both ends
 // draw the same number.  All slot words are loaded at once, then the
 // partners' tags.  Returns the number of bonds broken with i as the lower tag.
+template <bool EXT>
 __device__ __forceinline__ uint32_t break_site(const Params& P, const Dev& D, int a, unsigned long long s,
                                                uint32_t i, const float4* __restrict__ X) {
     const size_t n = P.n;
@@ -1604,7 +1618,7 @@ __device__ __forceinline__ uint32_t break_site(const Params& P, const Dev& D, in
     const uint32_t occ0 = occ;
     // rate modifiers: the melted P0_off at the kinetic temperature, or the
     // slip factor from each bond's length (both ends compute the same r)
-    const uint32_t mod = P.rmod[a];
+    const uint32_t mod = EXT ? P.rmod[a] : 0u;
     double poff = P.poff[a], kT = 0.0;
     float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
     if (mod != 0u) {
@@ -1639,6 +1653,7 @@ __device__ __forceinline__ uint32_t break_site(const Params& P, const Dev& D, in
 
 // Breaking phase (Sec. 2.3, Fig. sweep d), one thread per site (break_site).
 // Also resets best[1] for the next reaction's proposal round.
+template <bool EXT>
 __global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int slot, int xcur, int sp,
                                                int last) {
     const unsigned long long s = D.stepv[sp];
@@ -1648,7 +1663,7 @@ __global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int 
     uint32_t broke = 0;
     if (i < P.n) {
         D.best[1][i] = kNoKey;
-        broke = break_site(P, D, a, s, i, D.x[xcur]);
+        broke = break_site<EXT>(P, D, a, s, i, D.x[xcur]);
     }
     count_add(D, a, kCtrBreak, broke);
 }

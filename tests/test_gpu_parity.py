@@ -403,3 +403,35 @@ def test_batch_autotuner_keeps_results_and_stores_its_plan():
         for x in plain + batch:
             x.close()
     assert db.db_get_batch_plan(0) == [(_TOP, 1024)]
+
+
+def test_device_readouts_match_host_readouts():
+    """Positions, velocities and forces written into device memory (torch
+    tensors) on a caller's stream equal the host read-outs, and a read-out
+    followed by more steps sees the state it was enqueued after."""
+    import torch
+    w = inputs.small(seed=4)
+    log("case device read-outs")
+    with db.System.from_workload(w) as s:
+        s.step(35)
+        side = torch.cuda.Stream()                       # default priority
+        for fn, host in ((db.db_read_positions_device, s.positions), (db.db_read_velocities_device, s.velocities),
+                         (db.db_read_forces_device, s.forces)):
+            out = torch.full((w.n, 3), float("nan"), device="cuda")
+            fn(s.h, out.data_ptr(), side.cuda_stream)
+            side.synchronize()
+            assert np.array_equal(out.cpu().numpy(), host()), fn.__name__
+        before = s.positions()
+        out = torch.full((w.n, 3), float("nan"), device="cuda")
+        db.db_read_positions_device(s.h, out.data_ptr(), side.cuda_stream)
+        s.step(7)                                         # ordered after the read-out
+        side.synchronize()
+        assert np.array_equal(out.cpu().numpy(), before)
+        assert not np.array_equal(s.positions(), before)
+        # the system's own stream
+        out2 = torch.full((w.n, 3), float("nan"), device="cuda")
+        db.db_read_positions_device(s.h, out2.data_ptr(), None)
+        torch.cuda.synchronize()
+        assert np.array_equal(out2.cpu().numpy(), s.positions())
+        with pytest.raises(db.DybondError):
+            db.db_read_positions_device(s.h, 0, None)
