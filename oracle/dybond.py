@@ -17,7 +17,11 @@ What it computes (paper sections in parentheses):
   rates interpolated between their initial and melted values by
   g(T) = [tanh(lambda (T - T_melt)) + 1] / 2 (Eqs. gT, kT), or slip bonds,
   P_off(r) = P0_off exp(a sqrt(U_b(r)/kT)) (Eq. slip);
-* observables: bond counts, bonded fraction, largest cluster, energies.
+* observables: bond counts, bonded fraction, largest cluster, energies;
+* network analyses of the kind the paper's examples measure on assembled
+  gels (Sec. 4): the bond correlation function (the fraction of the bonds of
+  a reference time still present), the number of molecule pairs joined by
+  m dynamic bonds (bond multiplicity), and the cluster-size distribution.
 
 Particle index == tag throughout.  All arithmetic is FP64 numpy; library
 primitives used as steps: scipy's periodic k-d tree to enumerate candidate
@@ -618,6 +622,50 @@ class OracleSystem:
         rows = [(i, j, self.reactions[a].bond_type) for (i, j), a in self.dyn.items()]
         rows.sort()
         return np.array(rows, dtype=np.int64).reshape(-1, 3)
+
+    # ------------------------------------------------------------ analyses
+    def bond_reference(self):
+        """Remember the current dynamic bonds (pair -> reaction)."""
+        self.ref_bonds = dict(self.dyn)
+
+    def bond_correlation(self):
+        """(reference bonds, those present now between the same two sites
+        with the same reaction); a bond that broke and formed again counts
+        as present."""
+        ref = self.ref_bonds
+        return len(ref), sum(1 for pair, a in ref.items() if self.dyn.get(pair) == a)
+
+    def bond_multiplicity(self, length):
+        """Histogram of the number of dynamic bonds joining each pair of
+        distinct molecules: hist[m - 1] for m < length, hist[length - 1] for
+        m >= length; also the number of bonded molecule pairs and of bonds
+        within one molecule."""
+        per_pair = {}
+        intra = 0
+        for (i, j) in self.dyn:
+            a, b = int(self.mol[i]), int(self.mol[j])
+            if a == b:
+                intra += 1
+                continue
+            key = (min(a, b), max(a, b))
+            per_pair[key] = per_pair.get(key, 0) + 1
+        hist = np.zeros(length, dtype=np.int64)
+        for m in per_pair.values():
+            hist[min(m, length) - 1] += 1
+        return hist, len(per_pair), intra
+
+    def cluster_sizes(self, length):
+        """Histogram of cluster sizes (components of static + dynamic bonds):
+        hist[k - 1] clusters of k particles for k < length, hist[length - 1]
+        clusters of length or more; also the number of clusters."""
+        pairs = [(i, j) for i, j, _ in self.static] + list(self.dyn.keys())
+        lab = self._components(np.array(pairs, dtype=np.int64).reshape(-1, 2))
+        sizes = np.bincount(lab)
+        sizes = sizes[sizes > 0]
+        hist = np.zeros(length, dtype=np.int64)
+        for k in sizes:
+            hist[min(int(k), length) - 1] += 1
+        return hist, len(sizes)
 
     def observables(self):
         m = self.mass[self.types]
