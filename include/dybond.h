@@ -333,6 +333,33 @@ DB_API db_status db_read_bonds(db_system* sys, uint32_t* tag_pairs, uint32_t* bo
 /* Observables of the current state (computed on the device). */
 DB_API db_status db_read_observables(db_system* sys, db_observables* out);
 
+/* Network analyses of the bond network, computed on the device from the
+ * current state (the quantities the paper's examples measure on assembled
+ * gels, Sec. 4); synchronous; results are integer counts, the same whatever
+ * the internal numbering.  Call them between db_step calls to follow a run.
+ *
+ * db_bond_reference remembers the current dynamic bonds (by tag);
+ * db_bond_correlation then gives the number of those reference bonds and
+ * how many are present now between the same two sites with the same bond
+ * type (a bond that broke and formed again counts as present); the bond
+ * correlation function is n_intact / n_reference.  Errors: DB_ESTATE (no
+ * reference yet, or the system's state), DB_EINVAL (NULL outputs).
+ *
+ * db_bond_multiplicity: pairs of distinct molecules (components of the
+ * static bonds) joined by m dynamic bonds, hist[m - 1] for m < len and
+ * hist[len - 1] for m >= len (1 <= len <= 256); *n_pairs = bonded molecule
+ * pairs, *n_intra = dynamic bonds inside one molecule (loops).
+ *
+ * db_cluster_sizes: clusters (components of static + dynamic bonds) of k
+ * particles in hist[k - 1] for k < len, of len or more in hist[len - 1]
+ * (1 <= len <= 256); *n_clusters = all clusters, single particles included.
+ * Errors: DB_EINVAL (len out of range, NULL outputs), as db_read_observables. */
+DB_API db_status db_bond_reference(db_system* sys);
+DB_API db_status db_bond_correlation(db_system* sys, uint64_t* n_reference, uint64_t* n_intact);
+DB_API db_status db_bond_multiplicity(db_system* sys, uint64_t* hist, uint32_t len, uint64_t* n_pairs,
+                                      uint64_t* n_intra);
+DB_API db_status db_cluster_sizes(db_system* sys, uint64_t* hist, uint32_t len, uint64_t* n_clusters);
+
 /* Device-side read-outs, for callers that keep the data on the GPU (for
  * example in PyTorch tensors): the same values as db_read_positions,
  * db_read_velocities and db_read_forces, written as 3 n floats in tag order

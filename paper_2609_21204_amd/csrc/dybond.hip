@@ -30,6 +30,8 @@ thread_local std::string g_create_error;
 
 struct TypeCfg { uint32_t valence = 0; double sigma = 1.0, eps = 1.0, mass = 1.0; };
 struct BondCfg { int kind; double k, r0; double lmin = 0, lc1 = 0, lc0 = 0, lmax = 0; };
+constexpr uint32_t kAnaHist = 256;              // largest histogram of the network analyses
+constexpr uint32_t kAnaWords = kAnaHist + 8;
 struct RxRes { double k_on, k_off, eps, p_on, p_off; };
 // rate modifier of one reaction: 0 none, 1 melting, 2 slip bond
 struct RxMod { int kind = 0; double lam = 0, tm = 0, k_on_m = 0, k_off_m = 0, a = 0; };
@@ -79,6 +81,9 @@ struct db_system {
     Timing timing;
     std::map<int, hipGraphExec_t> graphs;  // keyed by (cur_x, cur_list)
     hipEvent_t ev_out = nullptr, ev_back = nullptr;   // ordering of device-side read-outs
+    uint32_t* bref = nullptr;              // reference bond table of the bond correlation (by tag)
+    bool have_ref = false;
+    unsigned long long* ana = nullptr;     // analysis results (device, kAnaWords words)
     bool use_graphs = true;
     uint32_t cellcap_user = 0;             // 0 = automatic
     double skin = 0.4;                     // neighbour-list skin
@@ -1160,6 +1165,7 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.err, 4);
     DALLOC(s, D.f4, 2 * (size_t)n);
     DALLOC(s, D.red, 4 + kMaxRx);
+    DALLOC(s, s->ana, kAnaWords);
     DALLOC(s, D.scan, (size_t)n + 1);
     DALLOC(s, D.parent, n);
     DALLOC(s, s->bsum, grid_of(n) + 1);
@@ -1671,17 +1677,12 @@ db_status db_read_bonds(db_system* s, uint32_t* pairs, uint32_t* bts, uint64_t c
     return check_errors(s);
 }
 
-db_status db_read_observables(db_system* s, db_observables* out) {
-    db_status st = ready(s);
-    if (st != DB_OK) return st;
-    if (!out) return fail(s, DB_EINVAL, "out is NULL");
-    HIPCHK(s, hipSetDevice(s->device));
+// Clusters of static + dynamic bonds: union by minimum index until no hook
+// changes a root; then D.parent holds each particle's root and D.scan each
+// root's cluster size.
+static db_status label_clusters(db_system* s) {
     const unsigned g = grid_of(s->n);
     const Params& P = s->P;
-    LAUNCH(s, k_eval, g, kBlock, P, s->D, s->cur_x, s->cur_list, 0u);
-    HIPCHK(s, hipMemsetAsync(s->D.red, 0, (4 + kMaxRx) * 8, s->stream));
-    LAUNCH(s, k_observe, g, kBlock, P, s->D, s->cur_x);
-    // largest cluster: union by minimum index until no hook changes a root
     LAUNCH(s, k_cc_init, g, kBlock, P, s->D);
     for (int it = 0; it < 64; ++it) {
         uint32_t changed = 0;
@@ -1695,6 +1696,98 @@ db_status db_read_observables(db_system* s, db_observables* out) {
     }
     HIPCHK(s, hipMemsetAsync(s->D.scan, 0, (size_t)s->n * 4, s->stream));
     LAUNCH(s, k_cc_size, g, kBlock, P, s->D);
+    return DB_OK;
+}
+
+db_status db_cluster_sizes(db_system* s, uint64_t* hist, uint32_t len, uint64_t* n_clusters) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!hist || !n_clusters || len < 1 || len > kAnaHist)
+        return fail(s, DB_EINVAL, "histogram of 1..%u bins and output pointers required", kAnaHist);
+    HIPCHK(s, hipSetDevice(s->device));
+    st = label_clusters(s);
+    if (st != DB_OK) return st;
+    HIPCHK(s, hipMemsetAsync(s->ana, 0, kAnaWords * 8, s->stream));
+    LAUNCH(s, k_cc_hist, grid_of(s->n), kBlock, s->P, s->D, s->ana + 1, len, s->ana);
+    unsigned long long h[kAnaWords];
+    HIPCHK(s, hipMemcpyAsync(h, s->ana, (len + 1) * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *n_clusters = h[0];
+    for (uint32_t k = 0; k < len; ++k) hist[k] = h[1 + k];
+    return check_errors(s);
+}
+
+db_status db_bond_reference(db_system* s) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    HIPCHK(s, hipSetDevice(s->device));
+    if (!s->bref) DALLOC(s, s->bref, (size_t)std::max(s->P.cap_max, 1u) * s->n);
+    LAUNCH(s, k_bond_ref, grid_of(s->n), kBlock, s->P, s->D, s->bref, s->cur_x);
+    HIPCHK(s, hipGetLastError());
+    s->have_ref = true;
+    return DB_OK;
+}
+
+db_status db_bond_correlation(db_system* s, uint64_t* n_reference, uint64_t* n_intact) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!n_reference || !n_intact) return fail(s, DB_EINVAL, "NULL outputs");
+    if (!s->have_ref) return fail(s, DB_ESTATE, "no reference bonds (call db_bond_reference first)");
+    HIPCHK(s, hipSetDevice(s->device));
+    HIPCHK(s, hipMemsetAsync(s->ana, 0, 16, s->stream));
+    LAUNCH(s, k_bond_corr, grid_of(s->n), kBlock, s->P, s->D, s->bref, s->ana);
+    unsigned long long h[2];
+    HIPCHK(s, hipMemcpyAsync(h, s->ana, 16, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *n_reference = h[0];
+    *n_intact = h[1];
+    return check_errors(s);
+}
+
+db_status db_bond_multiplicity(db_system* s, uint64_t* hist, uint32_t len, uint64_t* n_pairs, uint64_t* n_intra) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!hist || !n_pairs || !n_intra || len < 1 || len > kAnaHist)
+        return fail(s, DB_EINVAL, "histogram of 1..%u bins and output pointers required", kAnaHist);
+    HIPCHK(s, hipSetDevice(s->device));
+    // table: a power of two at least twice the largest possible number of bonds
+    uint64_t max_bonds = 0;
+    for (uint32_t i = 0; i < s->n; ++i) max_bonds += s->types[s->type[i]].valence;
+    uint32_t size = 1024;
+    while (size < 2 * (max_bonds / 2 + 1)) size *= 2;
+    unsigned long long* keys = nullptr;
+    uint32_t* counts = nullptr;
+    HIPCHK(s, hipMallocAsync((void**)&keys, (size_t)size * 8, s->stream));
+    HIPCHK(s, hipMallocAsync((void**)&counts, (size_t)size * 4, s->stream));
+    HIPCHK(s, hipMemsetAsync(keys, 0xFF, (size_t)size * 8, s->stream));
+    HIPCHK(s, hipMemsetAsync(counts, 0, (size_t)size * 4, s->stream));
+    HIPCHK(s, hipMemsetAsync(s->ana, 0, kAnaWords * 8, s->stream));
+    LAUNCH(s, k_mol_pairs, grid_of(s->n), kBlock, s->P, s->D, s->cur_x, keys, counts, size - 1u, s->ana);
+    LAUNCH(s, k_mol_hist, grid_of(size), kBlock, keys, counts, size, s->ana + 2, len, s->ana + 1);
+    unsigned long long h[kAnaWords];
+    HIPCHK(s, hipMemcpyAsync(h, s->ana, (len + 2) * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipFreeAsync(keys, s->stream));
+    HIPCHK(s, hipFreeAsync(counts, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *n_intra = h[0];
+    *n_pairs = h[1];
+    for (uint32_t k = 0; k < len; ++k) hist[k] = h[2 + k];
+    return check_errors(s);
+}
+
+db_status db_read_observables(db_system* s, db_observables* out) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!out) return fail(s, DB_EINVAL, "out is NULL");
+    HIPCHK(s, hipSetDevice(s->device));
+    const unsigned g = grid_of(s->n);
+    const Params& P = s->P;
+    LAUNCH(s, k_eval, g, kBlock, P, s->D, s->cur_x, s->cur_list, 0u);
+    HIPCHK(s, hipMemsetAsync(s->D.red, 0, (4 + kMaxRx) * 8, s->stream));
+    LAUNCH(s, k_observe, g, kBlock, P, s->D, s->cur_x);
+    // largest cluster
+    st = label_clusters(s);
+    if (st != DB_OK) return st;
     LAUNCH(s, k_cc_max, g, kBlock, P, s->D);
     unsigned long long red[4 + kMaxRx];
     std::vector<unsigned long long> slots((size_t)3 * kMaxRx * kCtrSlots);

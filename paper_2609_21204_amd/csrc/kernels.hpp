@@ -1802,6 +1802,118 @@ __global__ void k_cc_max(const Params P, const Dev D) {
     if (i < P.n && D.scan[i]) atomicMax((unsigned long long*)&D.red[2 + kMaxRx], (unsigned long long)D.scan[i]);
 }
 
+// ------------------------------------------------------------ network analyses
+// Clusters of size k (k < len) in hist[k - 1], larger ones in hist[len - 1];
+// D.scan holds each root's cluster size (k_cc_size).
+__global__ void k_cc_hist(const Params P, const Dev D, unsigned long long* hist, uint32_t len,
+                          unsigned long long* n_clusters) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const uint32_t k = D.scan[i];
+    if (k == 0u) return;
+    atomicAdd(&hist[(k < len ? k : len) - 1u], 1ull);
+    atomicAdd(n_clusters, 1ull);
+}
+
+// Reference bond table for the bond correlation, by tag: slot c of tag t
+// holds the c-th bond of t to a higher tag as partner tag | reaction << 24
+// (tags and indices are below 2^24).
+__global__ void k_bond_ref(const Params P, const Dev D, uint32_t* __restrict__ ref, int xin) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const size_t n = P.n;
+    const uint32_t t = D.tag[i];
+    const uint32_t cap = P.cap[type_of(D.x[xin][i])];
+    uint32_t c = 0;
+    for (uint32_t k = 0; k < cap; ++k) {
+        const uint32_t w = D.dyn[(size_t)k * n + i];
+        if (w == kEmpty) continue;
+        const uint32_t tj = D.tag[w & kIdxMask];
+        if (tj > t) ref[(size_t)c++ * n + t] = tj | (((w >> 24) & 0x7Fu) << 24);
+    }
+    for (; c < P.cap_max; ++c) ref[(size_t)c * n + t] = kEmpty;
+}
+
+// Reference bonds (out[0]) and those present now between the same two
+// sites with the same reaction (out[1]); one thread per tag.
+__global__ __launch_bounds__(256) void k_bond_corr(const Params P, const Dev D, const uint32_t* __restrict__ ref,
+                                                   unsigned long long* out) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long nref = 0, kept = 0;
+    if (t < P.n) {
+        const size_t n = P.n;
+        const uint32_t i = D.rtag[t];
+        for (uint32_t c = 0; c < P.cap_max; ++c) {
+            const uint32_t w = ref[(size_t)c * n + t];
+            if (w == kEmpty) continue;
+            ++nref;
+            const uint32_t j = D.rtag[w & kIdxMask], a = (w >> 24) & 0x7Fu;
+            for (uint32_t k = 0; k < P.cap_max; ++k) {
+                const uint32_t d = D.dyn[(size_t)k * n + i];
+                if (d != kEmpty && (d & kIdxMask) == j && ((d >> 24) & 0x7Fu) == a) {
+                    ++kept;
+                    break;
+                }
+            }
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        nref += __shfl_xor(nref, off, 64);
+        kept += __shfl_xor(kept, off, 64);
+    }
+    if (__lane_id() == 0 && nref) {
+        atomicAdd(&out[0], nref);
+        atomicAdd(&out[1], kept);
+    }
+}
+
+// Dynamic bonds per pair of molecules, counted in an open-addressing table
+// (keys: lower molecule id << 32 | higher one; ~0 = empty; size mask + 1, a
+// power of two above the number of bonds, so every probe sequence ends);
+// bonds inside one molecule go to intra[0].
+__global__ __launch_bounds__(256) void k_mol_pairs(const Params P, const Dev D, int xin,
+                                                   unsigned long long* __restrict__ keys,
+                                                   uint32_t* __restrict__ counts, uint32_t mask,
+                                                   unsigned long long* intra) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const size_t n = P.n;
+    const uint32_t tgi = D.tag[i], mi = D.mol[i];
+    const uint32_t cap = P.cap[type_of(D.x[xin][i])];
+    for (uint32_t k = 0; k < cap; ++k) {
+        const uint32_t w = D.dyn[(size_t)k * n + i];
+        if (w == kEmpty) continue;
+        const uint32_t j = w & kIdxMask;
+        if (D.tag[j] <= tgi) continue;                       // each bond once
+        const uint32_t mj = D.mol[j];
+        if (mj == mi) {
+            atomicAdd(intra, 1ull);
+            continue;
+        }
+        const unsigned long long key = ((unsigned long long)(mi < mj ? mi : mj) << 32) | (mi < mj ? mj : mi);
+        uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 32) & mask;
+        for (;;) {
+            const unsigned long long prev = atomicCAS(&keys[h], ~0ull, key);
+            if (prev == ~0ull || prev == key) {
+                atomicAdd(&counts[h], 1u);
+                break;
+            }
+            h = (h + 1u) & mask;
+        }
+    }
+}
+
+// Histogram of the table's counts: pairs joined by m bonds in hist[m - 1]
+// (m < len), by len or more in hist[len - 1]; pairs in n_pairs.
+__global__ void k_mol_hist(const unsigned long long* __restrict__ keys, const uint32_t* __restrict__ counts,
+                           uint32_t size, unsigned long long* hist, uint32_t len, unsigned long long* n_pairs) {
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= size || keys[h] == ~0ull) return;
+    const uint32_t m = counts[h];
+    atomicAdd(&hist[(m < len ? m : len) - 1u], 1ull);
+    atomicAdd(n_pairs, 1ull);
+}
+
 // Bond read-out, in tag order.  Pass 1: per tag, the number of its dynamic
 // bonds to a higher tag, exclusive-scanned inside each block (wave shuffles),
 // block totals to `bsum`.  Pass 2 scans `bsum`; pass 3 writes the rows.

@@ -98,6 +98,10 @@ _SIGS = {
     "db_read_forces": (_I, [_P, _P]),
     "db_read_bonds": (_I, [_P, _P, _P, _U64, ctypes.POINTER(_U64)]),
     "db_read_observables": (_I, [_P, ctypes.POINTER(Observables)]),
+    "db_bond_reference": (_I, [_P]),
+    "db_bond_correlation": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "db_bond_multiplicity": (_I, [_P, _P, _U32, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "db_cluster_sizes": (_I, [_P, _P, _U32, ctypes.POINTER(_U64)]),
     "db_read_positions_device": (_I, [_P, _P, _P]),
     "db_read_velocities_device": (_I, [_P, _P, _P]),
     "db_read_forces_device": (_I, [_P, _P, _P]),
@@ -393,6 +397,34 @@ def db_read_observables(h):
             "bonded_fraction": np.array(o.bonded_fraction[:R]),
             "largest_cluster_fraction": o.largest_cluster_fraction,
             "PE": o.pe, "KE": o.ke, "T_kin": o.t_kin}
+
+
+def db_bond_reference(h):
+    _check(h, load().db_bond_reference(h))
+
+
+def db_bond_correlation(h):
+    """(reference bonds, reference bonds present now)."""
+    a, b = _U64(), _U64()
+    _check(h, load().db_bond_correlation(h, ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+def db_bond_multiplicity(h, length=8):
+    """(hist of molecule pairs by number of joining bonds, bonded pairs,
+    bonds inside one molecule)."""
+    hist = np.zeros(length, dtype=np.uint64)
+    pairs, intra = _U64(), _U64()
+    _check(h, load().db_bond_multiplicity(h, hist.ctypes.data, length, ctypes.byref(pairs), ctypes.byref(intra)))
+    return hist.astype(np.int64), int(pairs.value), int(intra.value)
+
+
+def db_cluster_sizes(h, length=64):
+    """(hist of clusters by size, number of clusters)."""
+    hist = np.zeros(length, dtype=np.uint64)
+    n = _U64()
+    _check(h, load().db_cluster_sizes(h, hist.ctypes.data, length, ctypes.byref(n)))
+    return hist.astype(np.int64), int(n.value)
 
 
 def db_read_positions_device(h, dev_ptr, stream=None):
