@@ -108,6 +108,33 @@ def cpu_baseline(w, steps):
                       f"{steps // w.period} bonding sweeps) from its initial state, {dt:.1f} s"}
 
 
+def cpu_replica_baseline(a, inputs, steps=100, count=4):
+    """The oracle on the sweep replicas: `count` replicas spread over the
+    size range of the replica set, `steps` steps each on one core, scaled to
+    the whole set (replicas/hour on one core, and on every host core if each
+    ran its own replicas)."""
+    from threadpoolctl import threadpool_limits
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from helpers import oracle_from_workload
+    reps = inputs.replica_set(seed=a.seed, count=a.replicas)
+    by_size = sorted(reps, key=lambda w: w.n)
+    sample = [by_size[int((k + 0.5) * len(by_size) / count)] for k in range(count)]
+    with threadpool_limits(limits=1):
+        t = 0.0
+        for w in sample:
+            o = oracle_from_workload(w)
+            t0 = time.perf_counter()
+            o.step(steps)
+            t += time.perf_counter() - t0
+    per_replica_s = t / count * (a.replica_steps / steps)
+    cores = os.cpu_count() or 1
+    return {"replicas_per_hour_1core": 3600.0 / per_replica_s, "replicas_per_hour_all_cores": 3600.0 / per_replica_s * cores,
+            "host_cores": cores,
+            "replica_sample": f"{count} replicas of N {', '.join(str(w.n) for w in sample)}, {steps} oracle steps each "
+                              f"({t:.1f} s), scaled to {a.replica_steps} steps; all-core figure assumes one replica "
+                              f"per core in parallel"}
+
+
 def copy_bandwidth(torch, mib=1024, reps=10):
     """Achievable HBM bandwidth: a plain device-to-device copy of `mib` MiB
     (far larger than the 256 MB last-level cache), read + write bytes over
@@ -266,6 +293,8 @@ def main():
         line["batch"] = batch_vs_plain(a, db, inputs, torch)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
+        if a.replicas > 0:
+            line["cpu_baseline"].update(cpu_replica_baseline(a, inputs))
     print(json.dumps(line), flush=True)
 
 

@@ -83,9 +83,10 @@ __device__ __forceinline__ Force3 force_site(const Params& P, const StepTabs& T,
 }
 
 // Neighbour list of particle i at X from cell list `lst` of the same
-// positions (one thread): counts of the 27 stencil cells, then the first
-// particle of every cell in groups of 9 with their loads in flight, then
-// the rest of the fuller cells.
+// positions (one thread), a z layer of the 27-cell stencil at a time: the
+// counts of its 9 cells together, then its entries taken 8 at a time from
+// one index space over the 9 cells, with their loads in flight together
+// (a cell's entries are not fetched one dependent load after another).
 __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T, const Dev& D, int lst,
                                               uint32_t i, float4 pi) {
     const uint32_t* __restrict__ cnt = D.ccount[lst];
@@ -93,6 +94,7 @@ __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T
     const int nc = (int)P.nc;
     const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
     const float* rrow = T.rl2 + type_of(pi) * kMaxTypes;
+    const uint32_t cap = P.cellcap;
     uint32_t m = 0;
     auto consider = [&](float4 q) {
         const uint32_t j = slot_index(q);
@@ -105,22 +107,37 @@ __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T
     };
 #pragma unroll
     for (int g = 0; g < 3; ++g) {                 // z layer oz = g - 1
-        uint32_t cell[9], cn[9];
-        float4 f[9];
+        uint32_t cell[9], off[10];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             const int ox = q % 3 - 1, oy = q / 3 - 1;
             cell[q] = (uint32_t)((wrapc(cz + g - 1, nc) * nc + wrapc(cy + oy, nc)) * nc + wrapc(cx + ox, nc));
         }
+        uint32_t cn[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) cn[q] = min(cnt[cell[q]], P.cellcap);
+        for (int q = 0; q < 9; ++q) cn[q] = min(cnt[cell[q]], cap);
+        off[0] = 0u;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) f[q] = cp[(size_t)cell[q] * P.cellcap];
+        for (int q = 0; q < 9; ++q) off[q + 1] = off[q] + cn[q];
+        const uint32_t total = off[9];
+        for (uint32_t k0 = 0; k0 < total; k0 += 8) {
+            float4 f[8];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            if (cn[q] == 0u) continue;
-            consider(f[q]);
-            for (uint32_t e = 1; e < cn[q]; ++e) consider(cp[(size_t)cell[q] * P.cellcap + e]);
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t idx = min(k0 + (uint32_t)e, total - 1u);
+                // the cell holding entry idx: the last one whose range starts at or below it
+                uint32_t c = cell[0], o = 0u;
+#pragma unroll
+                for (int q = 1; q < 9; ++q)
+                    if (idx >= off[q]) {
+                        c = cell[q];
+                        o = off[q];
+                    }
+                f[e] = cp[(size_t)c * cap + (idx - o)];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (k0 + (uint32_t)e < total) consider(f[e]);
         }
     }
     if (m > P.nlmax) atomicOr(&D.err[0], kErrNlist);

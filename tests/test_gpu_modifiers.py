@@ -137,3 +137,23 @@ def test_batched_runs_with_modifiers_match_plain_runs():
     finally:
         for x in plain + batch:
             x.close()
+
+
+def test_batch_mixing_lean_and_full_systems():
+    """One batch with systems that need the full kernel variant and systems
+    that do not: both groups run as branches of one graph, all equal to
+    db_step."""
+    ws = [inputs.small(seed=11), _small(12, slip=1.0), inputs.replica_set(seed=13, count=2)[1],
+          _small(14, melt=_melt_half_bound())]
+    log("case batch, lean and full variants: sizes " + " ".join(str(w.n) for w in ws))
+    plain = [db.System.from_workload(w) for w in ws]
+    batch = [db.System.from_workload(w) for w in ws]
+    try:
+        for p in plain:
+            p.step(90)
+        db.db_step_batch_plan([b.h for b in batch], 90, [(600, 256), (2 ** 32 - 1, 1024)])
+        for k, (p, b) in enumerate(zip(plain, batch)):
+            _assert_same_state(p, b, f"system {k}")
+    finally:
+        for x in plain + batch:
+            x.close()
