@@ -880,7 +880,7 @@ __device__ __forceinline__ void bond_force_tab(const Params& P, const StepTabs& 
 //   cleared for the step after, sp = t mod 2, f3 = t mod 3.
 //   QB (if not 0) = list entries per thread issued up front.
 template <int TPP, int QB = 0, bool EXT = false>
-__global__ __launch_bounds__(256) void k_step(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_step(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
                                               int f3, int accum_ke) {
     static_assert(TPP >= 1 && TPP <= 64, "256 threads per workgroup");
     constexpr int PPB = 256 / TPP;                       // particles per workgroup
