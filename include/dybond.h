@@ -330,6 +330,25 @@ DB_API db_status db_read_forces(db_system* sys, float* force3);
 DB_API db_status db_read_bonds(db_system* sys, uint32_t* tag_pairs, uint32_t* bond_types,
                         uint64_t cap, uint64_t* count);
 
+/* Bonds formed and broken by the most recent bonding sweep (Sec. 2.3: the
+ * formation pass of each reaction, then the breaking of the bonds of that
+ * reaction present when the sweep began), recorded on the device while the
+ * sweep runs, by db_step, db_step_batch* and db_sweep_frozen alike.
+ * which: DB_EVENT_FORMED or DB_EVENT_BROKEN.  tag_pairs[2*cap] (tag_lo <
+ * tag_hi) and bond_types[cap] receive the events sorted by (tag_lo, tag_hi,
+ * bond_type), the bond type being that of the reaction; *count receives
+ * their number (also on DB_ETRUNC); *sweep_step (may be NULL) the step key of
+ * that sweep, or UINT64_MAX when no sweep has run since db_commit or
+ * db_set_state (then *count is 0).  A bond formed by one reaction and broken
+ * by a later reaction of the same sweep cannot occur (a reaction breaks only
+ * its own bonds).  Over one sweep, the dynamic bonds after it are those
+ * before it minus the broken ones plus the formed ones.  Synchronous; buffers
+ * are the caller's.  Errors: DB_EINVAL (count NULL, bad `which`, NULL arrays
+ * when *count > 0), DB_ESTATE, DB_ETRUNC. */
+enum { DB_EVENT_FORMED = 0, DB_EVENT_BROKEN = 1 };
+DB_API db_status db_read_sweep_events(db_system* sys, int which, uint32_t* tag_pairs, uint32_t* bond_types,
+                                      uint64_t cap, uint64_t* count, uint64_t* sweep_step);
+
 /* Observables of the current state (computed on the device). */
 DB_API db_status db_read_observables(db_system* sys, db_observables* out);
 

@@ -188,6 +188,7 @@ class OracleSystem:
         self.step_count = 0
         self.committed = False
         self.events = None        # set to a list to record (s, a, kind, i, j)
+        self.last_sweep = None    # step key and the bonds formed / broken by the last sweep
 
     # ---------------------------------------------------------------- setup
     def set_type(self, t, valence, sigma, eps, mass):
@@ -480,6 +481,7 @@ class OracleSystem:
         """One bonding sweep with step key s (Sec. 2.3)."""
         kT = self.current_kT()
         start = dict(self.dyn)          # table at the start of the sweep
+        self.last_sweep = {"step": s, "formed": [], "broken": []}
         for a in reaction_order(self.seed, s, len(self.reactions)):
             self._react(a, s, start, kT)
 
@@ -576,6 +578,7 @@ class OracleSystem:
                 self.occ[i] += 1
                 self.occ[j] += 1
                 self.counters[a, 1] += 1
+                self.last_sweep["formed"].append((min(i, j), max(i, j), rx.bond_type))
                 if self.events is not None:
                     self.events.append((s, a, "form", min(i, j), max(i, j), r))
         for (i, j), b in sorted(start.items()):             # breaking
@@ -591,6 +594,7 @@ class OracleSystem:
                 self.occ[i] -= 1
                 self.occ[j] -= 1
                 self.counters[a, 2] += 1
+                self.last_sweep["broken"].append((i, j, rx.bond_type))
                 if self.events is not None:
                     self.events.append((s, a, "break", i, j, None))
 
@@ -615,6 +619,7 @@ class OracleSystem:
             self.occ[j] += 1
         if np.any(self.occ > self.valence[self.types]):
             raise OracleError("EINVAL", "state exceeds a valence")
+        self.last_sweep = None
         self.F, self.PE = self.forces(self.x)
 
     def bonds(self):
@@ -622,6 +627,17 @@ class OracleSystem:
         rows = [(i, j, self.reactions[a].bond_type) for (i, j), a in self.dyn.items()]
         rows.sort()
         return np.array(rows, dtype=np.int64).reshape(-1, 3)
+
+    def sweep_events(self, which):
+        """Bonds formed (which = "formed") or broken ("broken") by the last
+        sweep as a sorted (m, 3) array (tag_lo, tag_hi, bond_type), and that
+        sweep's step key (None when no sweep has run since the state was set).
+        A reaction forms bonds, then breaks its own bonds present at the start
+        of the sweep (Sec. 2.3)."""
+        if self.last_sweep is None:
+            return np.zeros((0, 3), dtype=np.int64), None
+        rows = sorted(self.last_sweep[which])
+        return np.array(rows, dtype=np.int64).reshape(-1, 3), self.last_sweep["step"]
 
     # ------------------------------------------------------------ analyses
     def bond_reference(self):

@@ -220,6 +220,12 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
                 D.prop[i] = -1;
             }
             if (tid < 3) more[tid] = 0u;
+            if (slot == 0 && tid == 0) {      // a new sweep: its event lists start empty
+                D.evc[0] = 0u;
+                D.evc[1] = 0u;
+                D.evc[2] = (uint32_t)s;
+                D.evc[3] = (uint32_t)(s >> 32);
+            }
             __syncthreads();
             for (uint32_t i = tid; i < n; i += bs) {
                 uint32_t tgi = 0;

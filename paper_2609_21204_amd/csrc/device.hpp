@@ -127,6 +127,7 @@ struct Params {
     uint32_t ext;                      // tether bonds or rate modifiers present: kernels in their full variant
     float disp2;                       // (skin / 2 - 1e-4)^2: displacement that triggers a rebuild
     uint32_t nlmax;                    // neighbour-list slots per particle
+    uint32_t evcap[2];                 // capacity of the formed / broken event lists of a sweep
     double kT;
     float inv_mass[kMaxTypes];
     float noise_sd[kMaxTypes];         // sqrt(1 - c1^2) sqrt(kT / m)
@@ -202,6 +203,8 @@ struct Dev {
     uint8_t* claimed;      // site claimed in the running reaction
     uint32_t* live;        // compacted live proposals handed to the finishing pass
     uint32_t* live_count;  // [0] = length of `live`
+    uint2* ev[2];          // bonds formed [0] and broken [1] in the last sweep: {tag_lo, tag_hi | rx << 24}
+    uint32_t* evc;         // [0], [1] lengths of ev[0], ev[1]; [2], [3] step key of that sweep (lo, hi)
     unsigned long long* counters;   // nrx x 3 x kCtrSlots: attempts, forms, breaks
     unsigned long long* stepv;      // two step slots (parity of the step)
     unsigned long long* ke_fix;     // [2] sum m v^2 in 2^-32 fixed point (kinetic kT), one slot per sweep parity
@@ -288,6 +291,23 @@ enum : int { kCtrAttempt = 0, kCtrForm = 1, kCtrBreak = 2 };
 
 __device__ __forceinline__ unsigned long long* ctr_slot(const Dev& D, int a, int kind, uint32_t w) {
     return &D.counters[((size_t)a * 3 + (size_t)kind) * kCtrSlots + (w & (kCtrSlots - 1))];
+}
+
+// Append one entry per lane that has `want` set to event list k (0 formed,
+// 1 broken): one atomic per wave reserves the wave's run of entries, each
+// lane writes at its rank among the wanting lanes.  Valid in divergent code
+// (the ballot covers the lanes that reach it).  The order of the entries
+// depends on scheduling; the read-out sorts them.
+__device__ __forceinline__ void ev_push(const Params& P, const Dev& D, int k, bool want, uint32_t lo, uint32_t hi,
+                                        int a) {
+    const unsigned long long mask = __ballot(want);
+    if (!want) return;
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (rank == 0) base = atomicAdd(&D.evc[k], (uint32_t)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (base + rank < P.evcap[k]) D.ev[k][base + rank] = make_uint2(lo, hi | ((uint32_t)a << 24));
 }
 
 __device__ __forceinline__ void count_add(const Dev& D, int a, int kind, uint32_t v) {

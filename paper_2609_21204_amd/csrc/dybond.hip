@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -624,6 +625,9 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
     HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv, sizeof sv, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemsetAsync(s->D.err, 0, 4 * sizeof(uint32_t), s->stream));
     HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, 2 * sizeof(unsigned long long), s->stream));
+    // no sweep has run on this state yet: empty event lists, step key all ones
+    const uint32_t evc0[4] = {0u, 0u, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    HIPCHK(s, hipMemcpyAsync(s->D.evc, evc0, sizeof evc0, hipMemcpyHostToDevice, s->stream));
     const uint32_t flags[3] = {s->step % 3 == 0, s->step % 3 == 1, s->step % 3 == 2};   // lists built below
     HIPCHK(s, hipMemcpyAsync(s->D.rflag, flags, sizeof flags, hipMemcpyHostToDevice, s->stream));
     s->cur_x = 0;
@@ -1118,6 +1122,11 @@ static db_status commit_impl(db_system* s) {
     HIPCHK(s, hipSetDevice(s->device));
     fill_params(s);
     const uint32_t n = s->n;
+    // a sweep forms at most one bond per site and reaction (n / 2 per
+    // reaction) and breaks only bonds present at its start (at most
+    // cap_max n / 2)
+    s->P.evcap[0] = std::max(s->P.nrx * (n / 2), 1u);
+    s->P.evcap[1] = std::max((uint32_t)(((uint64_t)s->P.cap_max * n) / 2), 1u);
     const Params& P = s->P;
     Dev& D = s->D;
     HIPCHK(s, hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
@@ -1159,6 +1168,9 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.claimed, n);
     DALLOC(s, D.live, n);
     DALLOC(s, D.live_count, 4);
+    DALLOC(s, D.ev[0], P.evcap[0]);
+    DALLOC(s, D.ev[1], P.evcap[1]);
+    DALLOC(s, D.evc, 4);
     DALLOC(s, D.counters, (size_t)3 * kMaxRx * kCtrSlots);
     DALLOC(s, D.stepv, 2);
     DALLOC(s, D.ke_fix, 2);
@@ -1674,6 +1686,42 @@ db_status db_read_bonds(db_system* s, uint32_t* pairs, uint32_t* bts, uint64_t c
     HIPCHK(s, hipMemcpyAsync(bts, db, (size_t)total * 4, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipFreeAsync(dp, s->stream));
     HIPCHK(s, hipFreeAsync(db, s->stream));
+    return check_errors(s);
+}
+
+db_status db_read_sweep_events(db_system* s, int which, uint32_t* pairs, uint32_t* bts, uint64_t cap,
+                               uint64_t* count, uint64_t* sweep_step) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!count) return fail(s, DB_EINVAL, "count is NULL");
+    if (which != DB_EVENT_FORMED && which != DB_EVENT_BROKEN)
+        return fail(s, DB_EINVAL, "which must be DB_EVENT_FORMED or DB_EVENT_BROKEN");
+    HIPCHK(s, hipSetDevice(s->device));
+    uint32_t c[4];
+    HIPCHK(s, hipMemcpyAsync(c, s->D.evc, sizeof c, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    const uint32_t m = c[which];
+    if (m > s->P.evcap[which]) return fail(s, DB_EDEVICE, "event list longer than its bound (%u > %u)", m, s->P.evcap[which]);
+    *count = m;
+    if (sweep_step) *sweep_step = ((uint64_t)c[3] << 32) | c[2];
+    if (m > cap) return fail(s, DB_ETRUNC, "%u events, capacity %llu", m, (unsigned long long)cap);
+    if (m == 0) return DB_OK;
+    if (!pairs || !bts) return fail(s, DB_EINVAL, "NULL output arrays");
+    std::vector<uint2> e(m);
+    HIPCHK(s, hipMemcpyAsync(e.data(), s->D.ev[which], (size_t)m * sizeof(uint2), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    std::vector<std::array<uint32_t, 3>> rows(m);
+    for (uint32_t k = 0; k < m; ++k) {
+        const uint32_t a = e[k].y >> 24;
+        if (a >= s->P.nrx) return fail(s, DB_EDEVICE, "event with reaction %u", a);
+        rows[k] = {e[k].x, e[k].y & kIdxMask, s->P.rbt[a]};
+    }
+    std::sort(rows.begin(), rows.end());
+    for (uint32_t k = 0; k < m; ++k) {
+        pairs[2 * k] = rows[k][0];
+        pairs[2 * k + 1] = rows[k][1];
+        bts[k] = rows[k][2];
+    }
     return check_errors(s);
 }
 

@@ -1310,7 +1310,15 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
     const int a = sweep_reaction(P, s, slot);
     const uint32_t tid = threadIdx.x;
     const uint32_t i0 = xcd_block() * kSites + tid;
-    if (blockIdx.x == 0 && tid == 0) D.live_count[0] = 0u;
+    if (blockIdx.x == 0 && tid == 0) {
+        D.live_count[0] = 0u;
+        if (slot == 0) {                      // a new sweep: its event lists start empty
+            D.evc[0] = 0u;
+            D.evc[1] = 0u;
+            D.evc[2] = (uint32_t)s;
+            D.evc[3] = (uint32_t)(s >> 32);
+        }
+    }
     if (tid == 0) count = 0u;
     __syncthreads();
     if (i0 < P.n) {
@@ -1392,6 +1400,7 @@ __device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a
     if (fj >= 0) D.dyn[(size_t)fj * n + j] = i | tagbits;
     D.occ[i] = (uint8_t)(occ_i + 1);
     D.occ[j] = (uint8_t)(occ_j + 1);
+    ev_push(P, D, 0, true, lo, hi, a);
     return true;
 }
 
@@ -1641,11 +1650,13 @@ __device__ __forceinline__ uint32_t break_site(const Params& P, const Dev& D, in
             const double dz = mi_delta(pi.z, pj.z, P.L, P.invL);
             q = slip_prob(poff, P.slip[a], bond_energy(P, P.rbt[a], norm3(dx, dy, dz)), kT);
         }
-        if (u53(r.w0, r.w1) < q) {
+        const bool gone = u53(r.w0, r.w1) < q;
+        if (gone) {
             *sl = kEmpty;
             --occ;
             if (tgi < tgj[k]) ++broke;
         }
+        ev_push(P, D, 1, gone && tgi < tgj[k], lo, hi, a);   // listed once, by the lower tag
     }
     if (occ != occ0) D.occ[i] = (uint8_t)occ;
     return broke;

@@ -21,6 +21,8 @@ STATUS_NAMES = ["DB_OK", "DB_EINVAL", "DB_ENOMEM", "DB_EDEVICE", "DB_ESTATE", "D
                 "DB_EBOND", "DB_ETRUNC", "DB_EOVERFLOW"]
 DB_BOND_HARMONIC, DB_BOND_FENE, DB_BOND_TETHER = 0, 1, 2
 DB_KT_SETPOINT, DB_KT_KINETIC = 0, 1
+DB_EVENT_FORMED, DB_EVENT_BROKEN = 0, 1
+NO_SWEEP = 2 ** 64 - 1
 MAX_RX = 8
 
 
@@ -97,6 +99,7 @@ _SIGS = {
     "db_read_velocities": (_I, [_P, _P]),
     "db_read_forces": (_I, [_P, _P]),
     "db_read_bonds": (_I, [_P, _P, _P, _U64, ctypes.POINTER(_U64)]),
+    "db_read_sweep_events": (_I, [_P, ctypes.c_int, _P, _P, _U64, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "db_read_observables": (_I, [_P, ctypes.POINTER(Observables)]),
     "db_bond_reference": (_I, [_P]),
     "db_bond_correlation": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
@@ -388,6 +391,23 @@ def db_read_bonds(h):
     return np.concatenate([pairs, bts[:, None]], axis=1).reshape(-1, 3)
 
 
+def db_read_sweep_events(h, which):
+    """Bonds formed (which = DB_EVENT_FORMED) or broken (DB_EVENT_BROKEN) by
+    the last sweep: ((m, 3) uint32 array (tag_lo, tag_hi, bond_type) sorted,
+    step key of that sweep, NO_SWEEP if none has run)."""
+    cnt, step = _U64(), _U64()
+    st = load().db_read_sweep_events(h, which, None, None, 0, ctypes.byref(cnt), ctypes.byref(step))
+    if st not in (DB_OK, DB_ETRUNC):
+        _check(h, st)
+    m = cnt.value
+    pairs = np.empty((m, 2), np.uint32)
+    bts = np.empty(m, np.uint32)
+    if m:
+        _check(h, load().db_read_sweep_events(h, which, pairs.ctypes.data_as(_P), bts.ctypes.data_as(_P), m,
+                                              ctypes.byref(cnt), ctypes.byref(step)))
+    return np.concatenate([pairs, bts[:, None]], axis=1).reshape(-1, 3), step.value
+
+
 def db_read_observables(h):
     o = Observables()
     _check(h, load().db_read_observables(h, ctypes.byref(o)))
@@ -602,6 +622,9 @@ class System:
 
     def bonds(self):
         return db_read_bonds(self.h)
+
+    def sweep_events(self, which):
+        return db_read_sweep_events(self.h, which)
 
     def observables(self):
         return db_read_observables(self.h)

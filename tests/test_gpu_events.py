@@ -1,0 +1,103 @@
+"""Per-sweep event lists (bonds formed and broken by the last sweep) on the
+GPU, through the C ABI: equal to the oracle's after frozen sweeps from
+identical states, consistent with the GPU's own bond tables and counters
+after MD steps (graph-replayed and launched one by one), and the read-out's
+error paths."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from helpers import oracle_from_workload
+from paper_2609_21204_amd import dybond as db
+from paper_2609_21204_amd import inputs
+from test_gpu_parity import assert_same_bonds, counters, log, sync_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _rows(a):
+    return {tuple(r) for r in np.asarray(a, dtype=np.int64).tolist()}
+
+
+def _check_identity(before, after, s, c0, label):
+    """after = before - broken + formed; formed new, broken old; list
+    lengths equal to the counter increments of the one sweep."""
+    f, _ = s.sweep_events(db.DB_EVENT_FORMED)
+    b, _ = s.sweep_events(db.DB_EVENT_BROKEN)
+    f, b = _rows(f), _rows(b)
+    assert not (f & before) and b <= before, label
+    assert after == (before - b) | f, label
+    dc = counters(s) - c0
+    assert len(f) == dc[:, 1].sum() and len(b) == dc[:, 2].sum(), f"{label}: {len(f)}, {len(b)} vs {dc.tolist()}"
+    return len(f), len(b)
+
+
+@pytest.mark.parametrize("name,warm", [("small", 60), ("telechelic", 100)])
+def test_events_of_frozen_sweeps_match_oracle(name, warm):
+    w = inputs.WORKLOADS[name](seed=8)
+    w.reactions = [dict(w.reactions[0], epsilon=2.0)]         # P0_off = P0_on e^-2: bonds also break
+    log(f"case events/{name}")
+    with db.System.from_workload(w) as s:
+        assert s.sweep_events(db.DB_EVENT_FORMED)[1] == db.NO_SWEEP
+        s.step(warm)
+        o = oracle_from_workload(w)
+        sync_oracle(s, o)
+        assert s.sweep_events(db.DB_EVENT_BROKEN)[1] == warm       # the last sweep of the steps
+        nf = nb = 0
+        for key in (3000, 3010, 3020, 2 ** 33 + 11):
+            before, c0 = _rows(s.bonds()), counters(s)
+            s.sweep_frozen(key)
+            o.sweep_frozen(key)
+            assert_same_bonds(s, o, f"{name} key {key}")      # bonds and both event lists
+            f, b = _check_identity(before, _rows(s.bonds()), s, c0, f"{name} key {key}")
+            nf, nb = nf + f, nb + b
+        log(f"{name}: {nf} formed, {nb} broken over 4 frozen sweeps")
+        assert nf > 0 and nb > 0
+
+
+def test_events_after_md_steps_graph_replayed_and_single():
+    """The sweep at the end of a graph-replayed span records the same events
+    as the same sweep launched step by step; each is the sweep's change of
+    the bond table."""
+    w = inputs.small(seed=9, eps_bond=2.0)
+    log("case events after MD steps")
+    with db.System.from_workload(w) as g, db.System.from_workload(w) as p:
+        g.step(240)                                   # two captured 120-step spans
+        for _ in range(23):
+            p.step(10)                                # launched one by one (shorter than a span)
+        before, c0 = _rows(p.bonds()), counters(p)
+        p.step(10)                                    # its last sweep at step 240
+        _check_identity(before, _rows(p.bonds()), p, c0, "sweep at 240")
+        for kind in (db.DB_EVENT_FORMED, db.DB_EVENT_BROKEN):
+            eg, sg = g.sweep_events(kind)
+            ep, sp = p.sweep_events(kind)
+            assert sg == sp == 240 and np.array_equal(eg, ep), f"event list {kind}"
+        assert np.array_equal(g.bonds(), p.bonds())
+        p.step(5)                                     # no sweep: the lists stay those of step 240
+        assert p.sweep_events(db.DB_EVENT_FORMED)[1] == 240
+
+
+def test_event_readout_errors_and_reset():
+    w = inputs.small(seed=10, eps_bond=2.0)
+    log("case event read-out errors")
+    with db.System.from_workload(w) as s:
+        s.step(50)
+        lib = db.load()
+        cnt, step = ctypes.c_uint64(), ctypes.c_uint64()
+        m = len(s.sweep_events(db.DB_EVENT_FORMED)[0])
+        assert m > 1
+        buf = np.zeros(2 * m, np.uint32)
+        bt = np.zeros(m, np.uint32)
+        st = lib.db_read_sweep_events(s.h, db.DB_EVENT_FORMED, buf.ctypes.data, bt.ctypes.data, m - 1,
+                                      ctypes.byref(cnt), ctypes.byref(step))
+        assert st == db.DB_ETRUNC and cnt.value == m and step.value == 50
+        assert lib.db_read_sweep_events(s.h, 2, None, None, 0, ctypes.byref(cnt), None) == db.DB_EINVAL
+        assert lib.db_read_sweep_events(s.h, db.DB_EVENT_FORMED, None, None, 0, None, None) == db.DB_EINVAL
+        # a replaced state has had no sweep
+        pos, vel, b = s.positions(), s.velocities(), s.bonds()
+        s.set_state(50, pos, vel, b[:, :2], b[:, 2])
+        for kind in (db.DB_EVENT_FORMED, db.DB_EVENT_BROKEN):
+            e, sk = s.sweep_events(kind)
+            assert len(e) == 0 and sk == db.NO_SWEEP

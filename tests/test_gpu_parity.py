@@ -51,6 +51,13 @@ def assert_same_bonds(s, o, label):
     g = s.bonds().astype(np.int64)
     r = o.bonds()
     assert g.shape == r.shape and np.array_equal(g, r), f"{label}: bond sets differ ({len(g)} vs {len(r)})"
+    if o.last_sweep is not None:              # both sides ran the same sweep last: same event lists
+        for which, kind in (("formed", db.DB_EVENT_FORMED), ("broken", db.DB_EVENT_BROKEN)):
+            ge, gstep = s.sweep_events(kind)
+            re_, rstep = o.sweep_events(which)
+            assert gstep == rstep, f"{label}: sweep step of the events {gstep} vs {rstep}"
+            assert ge.shape == re_.shape and np.array_equal(ge.astype(np.int64), re_), \
+                f"{label}: {which} events differ ({len(ge)} vs {len(re_)})"
 
 
 def counters(s):
@@ -285,12 +292,15 @@ def test_edge_cases():
 
 
 def _snapshot(s):
-    return s.positions(), s.velocities(), s.bonds(), counters(s)
+    fe, fs = s.sweep_events(db.DB_EVENT_FORMED)
+    be, _ = s.sweep_events(db.DB_EVENT_BROKEN)
+    return s.positions(), s.velocities(), s.bonds(), counters(s), fe, be, np.array([fs], np.uint64)
 
 
 def _assert_same_state(p, b, label):
     assert p.step_count == b.step_count, label
-    for name, x, y in zip(("positions", "velocities", "bonds", "counters"), _snapshot(p), _snapshot(b)):
+    names = ("positions", "velocities", "bonds", "counters", "formed events", "broken events", "event sweep")
+    for name, x, y in zip(names, _snapshot(p), _snapshot(b)):
         assert x.shape == y.shape and np.array_equal(x, y), f"{label}: {name} differ"
 
 
