@@ -1295,12 +1295,15 @@ __device__ __forceinline__ int propose_site(const Params& P, const Dev& D, int a
 
 // Proposal phase fused with the first matching round: proposals and their
 // priority keys (Philox of the MATCH stream), posted with 64-bit atomicMin at
-// both sites for round 1.  A workgroup owns 256 consecutive sites: one
-// thread per site clears the site's sweep state and tests whether it can
-// propose (a type of the reaction, free valence); the sites that can are
-// listed in LDS, and then TPP threads per listed site scan its neighbour
-// list.  Full or unreactive sites, most of a bonded system, so cost one
-// thread each.
+// both sites for round 1.  A workgroup owns 256 sites, four runs of 64
+// consecutive ones (one per wave) taken from the four quarters of the index
+// range: particles are stored type-major, so contiguous blocks would leave
+// some workgroups with no site of the reaction and others with only such
+// sites, several passes of the scan below in series.  One thread per site
+// clears the site's sweep state and tests whether it can propose (a type of
+// the reaction, free valence); the sites that can are listed in LDS, and
+// then TPP threads per listed site scan its neighbour list.  Full or
+// unreactive sites, most of a bonded system, so cost one thread each.
 template <int TPP>
 __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur, int sp) {
     constexpr uint32_t kSites = 256, kPerPass = 256 / TPP;
@@ -1309,7 +1312,9 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
     const unsigned long long s = D.stepv[sp];
     const int a = sweep_reaction(P, s, slot);
     const uint32_t tid = threadIdx.x;
-    const uint32_t i0 = xcd_block() * kSites + tid;
+    // run (wave * grid + workgroup) of 64 sites: a bijection of the 4 * grid
+    // runs, which cover [0, n) since grid = ceil(n / 256)
+    const uint32_t i0 = (((tid >> 6) * gridDim.x + xcd_block()) << 6) + (tid & 63u);
     if (blockIdx.x == 0 && tid == 0) {
         D.live_count[0] = 0u;
         if (slot == 0) {                      // a new sweep: its event lists start empty
