@@ -1354,22 +1354,43 @@ __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, in
     }
 }
 
-// Acceptance of a claimed pair (Eq. pon): returns true when the bond forms,
-// in which case both sites get the bond in their first free slot.  The
-// positions, tags and all slot words of both sites are loaded together.
-template <bool EXT>
-__device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a, unsigned long long s,
-                                            const float4* __restrict__ X, uint32_t i, uint32_t j) {
-    const size_t n = P.n;
-    const float4 pi = X[i], pj = X[j];
-    const uint32_t tgi = D.tag[i], tgj = D.tag[j];
+// What the acceptance of pair (i, j) reads: positions, tags, every slot word
+// and the occupancy of both sites, loaded together.
+struct PairData {
+    float4 pi, pj;
+    uint32_t tgi, tgj, occ_i, occ_j;
     uint32_t wi[kMaxValence], wj[kMaxValence];
+};
+
+__device__ __forceinline__ PairData load_pair(const Params& P, const Dev& D, const float4* __restrict__ X,
+                                              uint32_t i, uint32_t j) {
+    const size_t n = P.n;
+    PairData d;
+    d.pi = X[i];
+    d.pj = X[j];
+    d.tgi = D.tag[i];
+    d.tgj = D.tag[j];
 #pragma unroll
     for (int k = 0; k < kMaxValence; ++k) {
-        wi[k] = (uint32_t)k < P.cap_max ? D.dyn[(size_t)k * n + i] : 0u;
-        wj[k] = (uint32_t)k < P.cap_max ? D.dyn[(size_t)k * n + j] : 0u;
+        d.wi[k] = (uint32_t)k < P.cap_max ? D.dyn[(size_t)k * n + i] : 0u;
+        d.wj[k] = (uint32_t)k < P.cap_max ? D.dyn[(size_t)k * n + j] : 0u;
     }
-    const uint32_t occ_i = D.occ[i], occ_j = D.occ[j];
+    d.occ_i = D.occ[i];
+    d.occ_j = D.occ[j];
+    return d;
+}
+
+// Acceptance of a claimed pair (Eq. pon) from its loaded data: returns true
+// when the bond forms, in which case both sites get the bond in their first
+// free slot.
+template <bool EXT>
+__device__ __forceinline__ bool accept_loaded(const Params& P, const Dev& D, int a, unsigned long long s,
+                                              const PairData& d, uint32_t i, uint32_t j) {
+    const size_t n = P.n;
+    const float4 pi = d.pi, pj = d.pj;
+    const uint32_t tgi = d.tgi, tgj = d.tgj, occ_i = d.occ_i, occ_j = d.occ_j;
+    const uint32_t* wi = d.wi;
+    const uint32_t* wj = d.wj;
     const double kT = sweep_kT(P, D, s);
     const double dx = mi_delta(pi.x, pj.x, P.L, P.invL);
     const double dy = mi_delta(pi.y, pj.y, P.L, P.invL);
@@ -1409,8 +1430,19 @@ __device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a
     return true;
 }
 
+template <bool EXT>
+__device__ __forceinline__ bool accept_pair(const Params& P, const Dev& D, int a, unsigned long long s,
+                                            const float4* __restrict__ X, uint32_t i, uint32_t j) {
+    return accept_loaded<EXT>(P, D, a, s, load_pair(P, D, X, i, j), i, j);
+}
+
 // Claim round q: a live proposal whose key is the minimum at both of its
 // sites is part of the greedy matching; it is claimed and tried at once.
+// The state, proposal, key and minimum at i are loaded together; where the
+// key is the minimum at i, the minimum at the partner is loaded together
+// with everything the acceptance reads (safe to read early: when the pair is
+// claimed, no other claim touches either site, since claimed pairs share no
+// site), so that a claim waits for two memory round trips.
 template <bool EXT>
 __global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int slot, int q,
                                                int xcur, int sp) {
@@ -1419,17 +1451,22 @@ __global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int 
     const uint32_t i = xcd_block() * blockDim.x + threadIdx.x;
     const unsigned long long* __restrict__ B = D.best[q % 3];
     uint32_t matched = 0, formed = 0;
-    if (i < P.n && D.estate[i] == kEdgeLive) {
+    if (i < P.n) {
+        const uint8_t es = D.estate[i];
         const int32_t pj = D.prop[i];
         const unsigned long long key = D.key[i];
         const unsigned long long bi = B[i];
-        if (bi == key && B[(uint32_t)pj] == key) {
+        if (es == kEdgeLive && bi == key) {
             const uint32_t j = (uint32_t)pj;
-            matched = 1;
-            D.estate[i] = kEdgeMatched;
-            D.claimed[i] = 1;
-            D.claimed[j] = 1;
-            formed = accept_pair<EXT>(P, D, a, s, D.x[xcur], i, j) ? 1u : 0u;
+            const unsigned long long bj = B[j];
+            const PairData d = load_pair(P, D, D.x[xcur], i, j);
+            if (bj == key) {
+                matched = 1;
+                D.estate[i] = kEdgeMatched;
+                D.claimed[i] = 1;
+                D.claimed[j] = 1;
+                formed = accept_loaded<EXT>(P, D, a, s, d, i, j) ? 1u : 0u;
+            }
         }
     }
     count_add(D, a, kCtrAttempt, matched);
