@@ -201,7 +201,7 @@ struct Dev {
     unsigned long long* best[3];    // per-site minimum key of live incident proposals (3 rotating)
     uint8_t* estate;       // proposal state
     uint8_t* claimed;      // site claimed in the running reaction
-    uint32_t* live;        // compacted live proposals handed to the finishing pass
+    uint4* live;           // compacted live proposals handed to the finishing pass: {i, j, key lo, key hi}
     uint32_t* live_count;  // [0] = length of `live`
     uint2* ev[2];          // bonds formed [0] and broken [1] in the last sweep: {tag_lo, tag_hi | rx << 24}
     uint32_t* evc;         // [0], [1] lengths of ev[0], ev[1]; [2], [3] step key of that sweep (lo, hi)

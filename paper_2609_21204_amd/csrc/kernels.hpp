@@ -1473,22 +1473,27 @@ __global__ __launch_bounds__(256) void k_claim(const Params P, const Dev D, int 
     count_add(D, a, kCtrForm, formed);
 }
 
-// Kill round q: drop proposals that touch a claimed site, post the keys of
-// the rest for round q; `compact` appends the survivors to the live list
-// (wave ballot + mbcnt prefix, one atomic per wave).
+// Kill round q: drop proposals that touch a claimed site; post the keys of
+// the rest for claim round q, or, with `compact` (the last kill, before the
+// finishing pass), append them with their partner and key to the live list
+// instead (wave ballot + mbcnt prefix, one atomic per wave).
 __global__ __launch_bounds__(256) void k_kill(const Params P, const Dev D, int q, int compact) {
     const uint32_t i = xcd_block() * blockDim.x + threadIdx.x;
-    if (i < P.n) D.best[(q + 1) % 3][i] = kNoKey;
     bool live = false;
+    uint32_t j = 0;
+    unsigned long long key = 0;
+    if (i < P.n) D.best[(q + 1) % 3][i] = kNoKey;
     if (i < P.n && D.estate[i] == kEdgeLive) {
-        const uint32_t j = (uint32_t)D.prop[i];
+        j = (uint32_t)D.prop[i];
+        key = D.key[i];
         if (D.claimed[i] || D.claimed[j]) {
             D.estate[i] = kEdgeDead;
         } else {
             live = true;
-            const unsigned long long key = D.key[i];
-            atomicMin(&D.best[q % 3][i], key);
-            atomicMin(&D.best[q % 3][j], key);
+            if (!compact) {
+                atomicMin(&D.best[q % 3][i], key);
+                atomicMin(&D.best[q % 3][j], key);
+            }
         }
     }
     if (compact) {
@@ -1500,7 +1505,7 @@ __global__ __launch_bounds__(256) void k_kill(const Params P, const Dev D, int q
             uint32_t base = 0;
             if (__lane_id() == leader) base = atomicAdd(D.live_count, (uint32_t)__popcll(mask));
             base = __shfl(base, leader, 64);
-            if (live) D.live[base + rank] = i;
+            if (live) D.live[base + rank] = make_uint4(i, j, (uint32_t)key, (uint32_t)(key >> 32));
         }
     }
 }
@@ -1516,22 +1521,27 @@ constexpr uint32_t kFinishLds = 256;    // live proposals matched inside LDS by 
 // LDS.  An edge is claimed when no live edge sharing one of its sites has a
 // smaller key; then live edges touching a claimed site die.  Claimed edges
 // are vertex-disjoint and acceptance depends only on the pair, so they are
-// all tried after the last round.
+// all tried after the last round.  The list holds exactly the proposals that
+// the last kill found live with both sites unclaimed, and nothing claims a
+// site between that kill and this pass.
+// The pair data each entry's acceptance reads is loaded before the rounds,
+// overlapping them (no other entry writes the sites of a claimed pair).
 template <bool EXT>
 __device__ __forceinline__ void finish_in_lds(const Params& P, const Dev& D, int a, unsigned long long s,
-                                              int xcur, unsigned long long* B, uint32_t count) {
+                                              int xcur, uint32_t count) {
     __shared__ uint32_t ei[kFinishLds], ej[kFinishLds];
     __shared__ unsigned long long ek[kFinishLds];
     __shared__ uint8_t est[kFinishLds];
     __shared__ int live_left;
     const uint32_t t = threadIdx.x;
+    PairData d;
     if (t < count) {
-        const uint32_t i = D.live[t];
-        const uint32_t j = (uint32_t)D.prop[i];
-        ei[t] = i;
-        ej[t] = j;
-        ek[t] = D.key[i];
-        est[t] = (D.estate[i] == kEdgeLive && !D.claimed[i] && !D.claimed[j]) ? kEdgeLive : kEdgeDead;
+        const uint4 e = D.live[t];
+        ei[t] = e.x;
+        ej[t] = e.y;
+        ek[t] = ((unsigned long long)e.w << 32) | e.z;
+        est[t] = kEdgeLive;
+        d = load_pair(P, D, D.x[xcur], e.x, e.y);
     }
     auto touches = [&](uint32_t e, uint32_t f) {
         return ei[f] == ei[e] || ei[f] == ej[e] || ej[f] == ei[e] || ej[f] == ej[e];
@@ -1560,14 +1570,12 @@ __device__ __forceinline__ void finish_in_lds(const Params& P, const Dev& D, int
     uint32_t att = 0, form = 0;
     if (t < count) {
         const uint32_t i = ei[t], j = ej[t];
-        B[i] = kNoKey;
-        B[j] = kNoKey;
         if (est[t] == kEdgeMatched) {
             D.estate[i] = kEdgeMatched;
             D.claimed[i] = 1;
             D.claimed[j] = 1;
             att = 1;
-            form = accept_pair<EXT>(P, D, a, s, D.x[xcur], i, j) ? 1u : 0u;
+            form = accept_loaded<EXT>(P, D, a, s, d, i, j) ? 1u : 0u;
         } else {
             D.estate[i] = kEdgeDead;
         }
@@ -1586,7 +1594,7 @@ __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, in
     unsigned long long* B = D.best[buf];
     const uint32_t count = D.live_count[0];
     if (count <= lds_limit && count <= kFinishLds) {
-        finish_in_lds<EXT>(P, D, a, s, xcur, B, count);
+        finish_in_lds<EXT>(P, D, a, s, xcur, count);
         return;
     }
     __shared__ int any;
@@ -1597,7 +1605,7 @@ __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, in
         if (threadIdx.x == 0) any = 0;
         __syncthreads();
         for (uint32_t e = threadIdx.x; e < count; e += blockDim.x) {
-            const uint32_t i = D.live[e];
+            const uint32_t i = D.live[e].x;
             if (D.estate[i] != kEdgeLive) continue;
             const uint32_t j = (uint32_t)D.prop[i];
             if (D.claimed[i] || D.claimed[j]) {
@@ -1612,7 +1620,7 @@ __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, in
         __syncthreads();
         if (!any) break;
         for (uint32_t e = threadIdx.x; e < count; e += blockDim.x) {
-            const uint32_t i = D.live[e];
+            const uint32_t i = D.live[e].x;
             if (D.estate[i] != kEdgeLive) continue;
             const uint32_t j = (uint32_t)D.prop[i];
             const unsigned long long key = D.key[i];
@@ -1627,7 +1635,7 @@ __global__ __launch_bounds__(1024) void k_finish(const Params P, const Dev D, in
         __threadfence();
         __syncthreads();
         for (uint32_t e = threadIdx.x; e < count; e += blockDim.x) {
-            const uint32_t i = D.live[e];
+            const uint32_t i = D.live[e].x;
             B[i] = kNoKey;
             B[(uint32_t)D.prop[i]] = kNoKey;
         }
