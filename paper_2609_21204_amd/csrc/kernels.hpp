@@ -1482,7 +1482,9 @@ __global__ __launch_bounds__(256) void k_kill(const Params P, const Dev D, int q
     bool live = false;
     uint32_t j = 0;
     unsigned long long key = 0;
-    if (i < P.n) D.best[(q + 1) % 3][i] = kNoKey;
+    // clear the buffer of the next kill's keys; the last kill has none (the
+    // buffer it would clear is cleared again before any later use)
+    if (i < P.n && !compact) D.best[(q + 1) % 3][i] = kNoKey;
     if (i < P.n && D.estate[i] == kEdgeLive) {
         j = (uint32_t)D.prop[i];
         key = D.key[i];
