@@ -1191,10 +1191,14 @@ __device__ __forceinline__ unsigned long long match_key(const Params& P, int a, 
 // position and occupancy.  For a proposer, the loads that need only i (the
 // first Q list entries per thread, the bond words) are issued together, then
 // everything the candidates need (position, occupancy, molecule, tag), so
-// that it waits for about four memory round trips.  Returns the chosen
+// that it waits for about four memory round trips.  The group issues 4 list
+// entries up front (TPP when TPP > 4): lists hold a few entries (1.7 on
+// average in the gel), and every entry issued is a separate row of the
+// slot-major list, a cache line or more for the group's sites, which at
+// millions of sites is most of the kernel's traffic.  Returns the chosen
 // partner (the same on every thread of the group) or -1; `tgi` receives the
 // site's tag.
-template <int TPP, int Q = (TPP < 4 ? 4 : (16 / TPP > 1 ? 16 / TPP : 1))>
+template <int TPP, int Q = (TPP < 4 ? 4 / TPP : 1)>
 __device__ __forceinline__ int propose_site(const Params& P, const Dev& D, int a, const float4* __restrict__ X,
                                             uint32_t i, uint32_t lane, uint32_t& tgi_out) {
     const size_t n = P.n;

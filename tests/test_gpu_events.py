@@ -101,3 +101,30 @@ def test_event_readout_errors_and_reset():
         for kind in (db.DB_EVENT_FORMED, db.DB_EVENT_BROKEN):
             e, sk = s.sweep_events(kind)
             assert len(e) == 0 and sk == db.NO_SWEEP
+
+
+def test_tiny_system_certain_forming_and_breaking():
+    """Four particles, two A-B pairs at r0 far apart, P0_on = P0_off = 1
+    (epsilon 0): each sweep breaks every bond present at its start and forms
+    every free pair, and never tests a bond it formed itself; counted by hand
+    from the sweep's rules, the same as the oracle's pin."""
+    pos = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [-4.0, -4.0, -4.0], [-3.0, -4.0, -4.0]], np.float32)
+    log("case events, four particles")
+    with db.System(4, 2, 10.0, 3) as s:
+        db.db_set_type(s.h, 0, 1, 1.0, 1.0, 1.0)
+        db.db_set_type(s.h, 1, 1, 1.0, 1.0, 1.0)
+        db.db_add_bond_type(s.h, db.DB_BOND_HARMONIC, 100.0, 1.0)
+        db.db_set_particles(s.h, pos, np.zeros((4, 3)), [0, 1, 0, 1])
+        db.db_add_reaction(s.h, db.make_reaction(0, 1, 0, 0.0, 1.3, epsilon=0.0, p_on0=1.0, self_avoid=0))
+        db.db_commit(s.h)
+        s.set_state(0, pos, np.zeros((4, 3)), [[0, 1]], [0])
+        expect = [([[2, 3, 0]], [[0, 1, 0]]), ([[0, 1, 0]], [[2, 3, 0]])]
+        for k, key in enumerate((10, 20, 30, 40)):
+            s.sweep_frozen(key)
+            f, sf = s.sweep_events(db.DB_EVENT_FORMED)
+            b, _ = s.sweep_events(db.DB_EVENT_BROKEN)
+            ef, eb = expect[k % 2]
+            assert sf == key and f.tolist() == ef and b.tolist() == eb, (key, f.tolist(), b.tolist())
+            assert s.bonds().tolist() == ef
+        ob = s.observables()
+        assert ob["forms"].tolist() == [4] and ob["breaks"].tolist() == [4] and ob["attempts"].tolist() == [4]
