@@ -1232,13 +1232,18 @@ __device__ __forceinline__ int propose_site(const Params& P, const Dev& D, int a
     const uint32_t cap_want = P.cap[want];
     const double rmin = P.rmin[a], rmax = P.rmax[a], r0 = P.r0[a];
     const float rmax2 = P.rmax2_pre[a], rmin2 = P.rmin2_pre[a];
+    // the best candidate so far; its tag is read only when an exact tie of
+    // |r - r0| needs it (kTagUnread until then), so that a candidate costs a
+    // position and an occupancy gather (and its molecule only when the
+    // reaction avoids its own molecule)
+    constexpr uint32_t kTagUnread = 0xFFFFFFFFu;   // tags are below 2^24
     double best_score = 0.0;
-    uint32_t best_tag = 0xFFFFFFFFu;
+    uint32_t best_tag = kTagUnread;
     int best_j = -1;
     // candidate j: partner type, free, not yet bonded to i, other molecule if
     // required, inside [r_min, r_max] (FP32 screen, then the exact FP64 r);
     // keep the smallest (|r - r0|, tag)
-    auto consider = [&](uint32_t j, float4 pj, uint32_t occ_j, uint32_t mol_j, uint32_t tgj) {
+    auto consider = [&](uint32_t j, float4 pj, uint32_t occ_j, uint32_t mol_j) {
         if (type_of(pj) != want) return;
         if (occ_j >= cap_want) return;
         bool bonded = false;
@@ -1257,37 +1262,50 @@ __device__ __forceinline__ int propose_site(const Params& P, const Dev& D, int a
         const double r = norm3(dx, dy, dz);
         if (!(r >= rmin && r <= rmax)) return;
         const double score = fabs(r - r0);
-        if (best_j < 0 || score < best_score || (score == best_score && tgj < best_tag)) {
+        if (best_j < 0 || score < best_score) {
             best_score = score;
-            best_tag = tgj;
+            best_tag = kTagUnread;
             best_j = (int)j;
+        } else if (score == best_score) {           // exact tie: the smaller tag wins
+            if (best_tag == kTagUnread) best_tag = D.tag[best_j];
+            const uint32_t tgj = D.tag[j];
+            if (tgj < best_tag) {
+                best_tag = tgj;
+                best_j = (int)j;
+            }
         }
     };
     // the neighbour list (rebuilt right after every step that needed it) holds
     // every pair within r_search >= r_max
     float4 pj[Q];
-    uint32_t oj[Q], mj[Q], gj[Q];
+    uint32_t oj[Q], mj[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const uint32_t j = lane + (uint32_t)q * TPP < m ? nb[q] : i;
         pj[q] = X[j];
         oj[q] = D.occ[j];
-        mj[q] = D.mol[j];
-        gj[q] = D.tag[j];
+        mj[q] = avoid ? D.mol[j] : 0u;
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q)
-        if (lane + (uint32_t)q * TPP < m) consider(nb[q], pj[q], oj[q], mj[q], gj[q]);
+        if (lane + (uint32_t)q * TPP < m) consider(nb[q], pj[q], oj[q], mj[q]);
     for (uint32_t k = lane + (uint32_t)Q * TPP; k < m; k += TPP) {
         const uint32_t j = D.nl[k * n + i];
-        consider(j, X[j], D.occ[j], avoid ? D.mol[j] : 0u, D.tag[j]);
+        consider(j, X[j], D.occ[j], avoid ? D.mol[j] : 0u);
     }
 #pragma unroll
     for (int o = TPP / 2; o >= 1; o >>= 1) {
         const double os = __shfl_xor(best_score, o, 64);
-        const uint32_t ot = __shfl_xor(best_tag, o, 64);
+        uint32_t ot = __shfl_xor(best_tag, o, 64);
         const int oj2 = __shfl_xor(best_j, o, 64);
-        if (oj2 >= 0 && (best_j < 0 || os < best_score || (os == best_score && ot < best_tag))) {
+        if (oj2 < 0) continue;
+        bool take = best_j < 0 || os < best_score;
+        if (!take && os == best_score) {            // tie across the group: compare tags
+            if (ot == kTagUnread) ot = D.tag[oj2];
+            if (best_tag == kTagUnread) best_tag = D.tag[best_j];
+            take = ot < best_tag;
+        }
+        if (take) {
             best_score = os;
             best_tag = ot;
             best_j = oj2;

@@ -14,6 +14,7 @@ import pytest
 
 from helpers import oracle_from_workload
 from oracle import OracleSystem, Reaction
+from oracle.dybond import BOND_HARMONIC
 from paper_2609_21204_amd import dybond as db
 from paper_2609_21204_amd import inputs
 
@@ -244,6 +245,43 @@ def test_matching_under_heavy_contention(matching):
                 assert_same_bonds(s, o, f"contention seed {seed} key {key}")
             assert np.array_equal(counters(s), o.counters)
             log(f"seed {seed}: {len(o.dyn)} bonds, counters {o.counters.tolist()}")
+
+
+def test_exact_ties_on_a_lattice_match_oracle():
+    """Simple cubic lattice with spacing r0 = 1 (L = 10), A/B checkerboard,
+    window to 1.2: every candidate of every site lies at exactly r0, so every
+    proposal is decided by the tag rule (reading R3); tags are a random
+    permutation of the lattice order."""
+    log("case exact ties on a lattice")
+    g = np.arange(10, dtype=np.float32) - 5.0
+    gx, gy, gz = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1)
+    typ = ((gx + gy + gz).ravel().astype(np.int64) % 2).astype(np.uint32)
+    perm = np.random.default_rng(3).permutation(len(pos))
+    pos, typ = pos[perm], typ[perm]
+    n, valence = len(pos), (2, 3)
+    o = OracleSystem(n, 2, 10.0, 5)
+    with db.System(n, 2, 10.0, 5) as s:
+        for t in range(2):
+            db.db_set_type(s.h, t, valence[t], 1.0, 1.0, 1.0)
+            o.set_type(t, valence[t], 1.0, 1.0, 1.0)
+        db.db_add_bond_type(s.h, db.DB_BOND_HARMONIC, 100.0, 1.0)
+        o.add_bond_type(BOND_HARMONIC, 100.0, 1.0)
+        db.db_set_particles(s.h, pos, np.zeros((n, 3)), typ)
+        o.set_particles(pos, np.zeros((n, 3)), typ)
+        db.db_add_reaction(s.h, db.make_reaction(0, 1, 0, 0.0, 1.2, epsilon=1.5, p_on0=1.0, self_avoid=0))
+        o.add_reaction(Reaction(0, 1, 0, 0.0, 1.2, epsilon=1.5, p_on0=1.0, self_avoid=0))
+        db.db_commit(s.h)
+        o.set_integrator(0.005, 1.0, 1.0, 10)
+        o.commit()
+        c0 = counters(s)
+        for key in (10, 20, 30, 40, 50, 60):
+            s.sweep_frozen(key)
+            o.sweep_frozen(key)
+            assert_same_bonds(s, o, f"lattice key {key}")
+        assert np.array_equal(counters(s) - c0, o.counters)
+        log(f"lattice: {len(o.dyn)} bonds, counters {o.counters.tolist()}")
+        assert o.counters[0, 1] > 0 and o.counters[0, 2] > 0
 
 
 def test_edge_cases():

@@ -271,6 +271,21 @@ def _frozen(points, types, valence, reactions, L=8.0, seed=3, kT=1.0, bond_k=100
     return o
 
 
+def test_proposal_ties_go_to_the_smallest_tag():
+    """A B site at the origin with six A sites at exactly r0 = 1 and one A at
+    1.05 with the smallest tag: the proposal is the closest |r - r0| first,
+    then the smallest tag among the exact ties (reading R3), whatever the
+    geometric order of the tied sites."""
+    pts = [(0, 0, 0), (1.05, 0, 0), (0, 0, -1), (0, 1, 0), (-1, 0, 0), (0, 0, 1), (0, -1, 0), (1, 0, 0)]
+    # tags 2..7 sit at the six lattice directions in a scrambled order; tag 1 is off by 0.05
+    o = _frozen(pts, [1] + [0] * 7, [1, 1], [(0, 1, dict(epsilon=1.0, p_on0=1.0, r_max=1.2))])
+    props = o.propose(0, o.occ.copy())
+    assert props[0] == 2
+    assert all(props[k] == 0 for k in range(1, 8))        # each A's only candidate
+    o2 = _frozen(pts[:1] + pts[2:], [1] + [0] * 6, [1, 1], [(0, 1, dict(epsilon=1.0, p_on0=1.0, r_max=1.2))])
+    assert o2.propose(0, o2.occ.copy())[0] == 1           # without the off site: the smallest of the ties
+
+
 def test_frozen_dimer_two_state_chain():
     """One pair at fixed r: forming with p = P0_on e^{-U/kT}, breaking with q = P0_off."""
     r = 1.1
