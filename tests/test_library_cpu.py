@@ -245,3 +245,8 @@ def test_validation_errors_on_host():
         assert _status_of(lambda: db.db_set_matching(s.h, 1, 257)) == "DB_EINVAL"
         db.db_set_matching(s.h, 3, 0)
     assert _status_of(lambda: db.db_create(0, 1, 5.0, 1)) == "DB_EINVAL"
+    # tags and indices are 24-bit words: n < 2^24
+    assert _status_of(lambda: db.db_create(2 ** 24, 1, 500.0, 1)) == "DB_EINVAL"
+    assert _status_of(lambda: db.db_create(10, 0, 5.0, 1)) == "DB_EINVAL"
+    assert _status_of(lambda: db.db_create(10, 9, 5.0, 1)) == "DB_EINVAL"
+    assert _status_of(lambda: db.db_create(10, 1, float("nan"), 1)) == "DB_EINVAL"
