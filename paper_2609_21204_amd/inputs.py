@@ -283,7 +283,7 @@ def gel_lattice(seed=1, n=200000, density=0.3, eps_ab=8.0, eps_ac=4.0):
     pos = (ijk + 0.5) * a - 0.5 * L + rng.uniform(-jit, jit, (n, 3))
     n_a = n // 5
     n_b = n // 2
-    tid = np.array([0] * n_a + [1] * n_b + [2] * (n - n_a - n_b), dtype=np.uint32)[rng.permutation(n)]
+    tid = np.repeat(np.arange(3, dtype=np.uint32), [n_a, n_b, n - n_a - n_b])[rng.permutation(n)]
     w = _gel(seed, n, density, eps_ab, eps_ac, pos=pos, tid=tid, rng=rng)
     w.name = "gel-lattice"
     return w

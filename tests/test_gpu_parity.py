@@ -247,6 +247,83 @@ def test_matching_under_heavy_contention(matching):
             log(f"seed {seed}: {len(o.dyn)} bonds, counters {o.counters.tolist()}")
 
 
+def _local_oracle(w, pos, tags, bonds):
+    """Oracle of the particles `tags` (the sampled one first) at positions
+    pos[tags] with the dynamic `bonds` (tag_lo, tag_hi, bond_type) among them."""
+    k = len(tags)
+    o = OracleSystem(k, len(w.types), w.L, w.seed)
+    for t, (val, sig, eps, m) in enumerate(w.types):
+        o.set_type(t, val, sig, eps, m)
+    for bt in w.bond_types:
+        o.add_bond_type(*bt)
+    o.set_particles(pos[tags], np.zeros((k, 3)), w.type_id[tags])
+    for r in w.reactions:
+        o.add_reaction(Reaction(**r))
+    o.set_integrator(w.dt, w.kT, w.gamma, w.period)
+    o.commit()
+    where = {int(t): q for q, t in enumerate(tags)}
+    pairs = [(where[int(i)], where[int(j)]) for i, j, _ in bonds]
+    o.set_state(0, pos[tags], np.zeros((k, 3)), pairs, [int(x) for x in bonds[:, 2]])
+    return o
+
+
+def test_largest_system_sampled_forces_and_invariants():
+    """The largest system a handle may hold (n = 2^24 - 1: tags are 24-bit
+    words), gel chemistry on a lattice: 120 steps (12 sweeps, one spatial
+    re-sort).  Forces of 24 sampled particles against the oracle run on each
+    one's neighbourhood (every particle within 2 of it and its bonds, which
+    make up the whole force on it), and invariants that hold at any size:
+    valences, unique bonds, forms - breaks = bonds per reaction, and every
+    bond the last sweep formed lies inside its reaction window at the
+    positions of that sweep (the current ones: the run ends on a sweep)."""
+    n = 2 ** 24 - 1
+    w = inputs.gel_lattice(n=n, seed=3)
+    log(f"case largest system, n={n}")
+    with db.System.from_workload(w) as s:
+        s.step(120)
+        pos = s.positions()
+        frc = s.forces()
+        bonds = s.bonds().astype(np.int64)
+        ob = s.observables()
+        formed, step = s.sweep_events(db.DB_EVENT_FORMED)
+    assert step == 120
+    cap = np.array([t[0] for t in w.types])
+    assert np.all(bonds[:, 0] < bonds[:, 1])
+    key = bonds[:, 0] * n + bonds[:, 1]
+    assert len(np.unique(key)) == len(key)
+    occ = np.bincount(bonds[:, :2].ravel(), minlength=n)
+    assert np.all(occ <= cap[w.type_id])
+    for a, rx in enumerate(w.reactions):
+        nb = int(np.sum(bonds[:, 2] == rx["bond_type"]))
+        assert ob["forms"][a] - ob["breaks"][a] == nb == ob["n_bonds"][a], (a, nb)
+    bt2rx = {rx["bond_type"]: rx for rx in w.reactions}
+    f = formed.astype(np.int64)
+    assert len(f) > 0 and np.all(np.isin(f[:, 0] * n + f[:, 1], key))
+    d = pos[f[:, 1]].astype(np.float64) - pos[f[:, 0]].astype(np.float64)
+    d -= np.rint(d / w.L) * w.L
+    r = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
+    for bt, rx in bt2rx.items():
+        m = f[:, 2] == bt
+        assert np.all((r[m] >= rx["r_min"]) & (r[m] <= rx["r_max"])), bt
+    log(f"largest: {len(bonds)} bonds, last sweep formed {len(f)}, forms {ob['forms'].tolist()}")
+    rng = np.random.default_rng(4)
+    worst = 0.0
+    for t in rng.choice(n, 24, replace=False):
+        dd = pos - pos[t]
+        dd -= np.rint(dd / np.float32(w.L)) * np.float32(w.L)
+        near = np.flatnonzero(np.einsum("ij,ij->i", dd, dd) < 4.0)
+        tags = np.concatenate([[t], near[near != t]])
+        mine = bonds[(bonds[:, 0] == t) | (bonds[:, 1] == t)]
+        assert np.all(np.isin(mine[:, :2], tags))
+        o = _local_oracle(w, pos, tags, mine)
+        f_ref, _ = o.forces(o.x)
+        scale = o.force_contribution_norms(o.x)[0]
+        err = float(np.linalg.norm(frc[t].astype(np.float64) - f_ref[0]))
+        worst = max(worst, err / max(scale, 1e-30))
+        assert err <= FORCE_TOL * scale + FORCE_ABS, (int(t), err, scale)
+    log(f"largest: max |dF|/sum|F_ij| over 24 sampled particles = {worst:.2e}")
+
+
 def test_exact_ties_on_a_lattice_match_oracle():
     """Simple cubic lattice with spacing r0 = 1 (L = 10), A/B checkerboard,
     window to 1.2: every candidate of every site lies at exactly r0, so every
