@@ -1095,10 +1095,19 @@ __global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int 
 // inside a cell) so that the particles of a tile and their bond partners sit
 // close together in memory.  Nothing computed depends on the numbering: random
 // streams and tie-breaks use tags, sums are in fixed point.
-// Buckets are (type, cell) in type-major order, so that consecutive particles
-// (and hence the lanes of a wave) share one type and its valence.
+// Buckets are (cell, type) in cell-major order: a cell's particles stay
+// together whatever their types, so bonded partners (of other types) and
+// neighbours sit next to each other in memory.  (Type-major order, every
+// type in a block of its own, made the step 3 % slower at 200k particles and
+// 6 % at 4 M: a particle's partners then lie in another block.)
+__device__ __forceinline__ void bucket_cell_type(const Params& P, uint32_t b, uint32_t& c, uint32_t& t) {
+    c = b / P.ntypes;
+    t = b - c * P.ntypes;
+}
+
 __device__ __forceinline__ uint32_t bucket_count(const Params& P, const Dev& D, int lst, uint32_t b) {
-    const uint32_t t = b / P.ncell, c = b - t * P.ncell;
+    uint32_t c, t;
+    bucket_cell_type(P, b, c, t);
     uint32_t m = D.ccount[lst][c];
     m = m < P.cellcap ? m : P.cellcap;
     const float4* cp = D.cpos[lst] + (size_t)c * P.cellcap;
@@ -1120,7 +1129,8 @@ __global__ __launch_bounds__(256) void k_cell_scan_blocks(const Params P, const 
 __global__ __launch_bounds__(256) void k_sort_assign(const Params P, const Dev D, int lst) {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= P.ntypes * P.ncell) return;
-    const uint32_t t = b / P.ncell, c = b - t * P.ncell;
+    uint32_t c, t;
+    bucket_cell_type(P, b, c, t);
     uint32_t m = D.ccount[lst][c];
     m = m < P.cellcap ? m : P.cellcap;
     uint32_t at = D.cstart[b] + D.cbsum[blockIdx.x];
@@ -1319,9 +1329,11 @@ __device__ __forceinline__ int propose_site(const Params& P, const Dev& D, int a
 // priority keys (Philox of the MATCH stream), posted with 64-bit atomicMin at
 // both sites for round 1.  A workgroup owns 256 sites, four runs of 64
 // consecutive ones (one per wave) taken from the four quarters of the index
-// range: particles are stored type-major, so contiguous blocks would leave
-// some workgroups with no site of the reaction and others with only such
-// sites, several passes of the scan below in series.  One thread per site
+// range, which evens out the number of sites per workgroup that can propose
+// where they cluster in space (each pass of the scan below over 64 listed
+// sites is a chain of dependent loads; with particles stored in blocks of
+// one type, contiguous workgroups needed up to four passes in series while
+// others had none).  One thread per site
 // clears the site's sweep state and tests whether it can propose (a type of
 // the reaction, free valence); the sites that can are listed in LDS, and
 // then TPP threads per listed site scan its neighbour list.  Full or
