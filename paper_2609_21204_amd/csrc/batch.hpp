@@ -296,4 +296,79 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
     }
 }
 
+// Spatial renumbering of system blockIdx.x inside one workgroup, launched
+// before every chunk of batched steps: what the periodic sort of db_step
+// does over the whole chip.  New indices in (cell, type) order from the
+// current cell list (each thread takes a contiguous run of buckets), every
+// per-particle array permuted with bond partners remapped, the current cell
+// list binned again under the new indices and the neighbour lists rebuilt.
+// Nothing computed depends on the numbering (tags key every decision, sums
+// are exact), so a batched run stays equal to db_step; the sweep's per-site
+// scratch is reset at every sweep and the other position buffer is written
+// before it is read, so neither is permuted.
+__global__ __launch_bounds__(kBatchMaxThreads)
+void k_batch_sort(const BatchItem* __restrict__ items, const BatchState* __restrict__ state) {
+    const BatchItem& B = items[blockIdx.x];
+    const Params& P = B.P;
+    const Dev& D = B.D;
+    const BatchState st = state[blockIdx.x];
+    const int xin = st.cur_x, lst = st.cur_list;
+    const uint32_t tid = threadIdx.x, bs = blockDim.x;
+    const size_t n = P.n;
+    __shared__ StepTabs T;
+    stage_tabs(D, T, tid);
+    const uint32_t nbk = P.ncell * P.ntypes;
+    const uint32_t per = (nbk + bs - 1) / bs;
+    const uint32_t b0 = min(tid * per, nbk), b1 = min(b0 + per, nbk);
+    uint32_t cnt = 0;
+    for (uint32_t b = b0; b < b1; ++b) cnt += bucket_count(P, D, lst, b);
+    uint32_t total;
+    uint32_t at = block_exclusive_scan(cnt, &total);
+    for (uint32_t b = b0; b < b1; ++b) {
+        uint32_t c, t;
+        bucket_cell_type(P, b, c, t);
+        uint32_t m = D.ccount[lst][c];
+        m = m < P.cellcap ? m : P.cellcap;
+        const float4* cp = D.cpos[lst] + (size_t)c * P.cellcap;
+        for (uint32_t k = 0; k < m; ++k)
+            if (slot_type(cp[k]) == t) D.newidx[slot_index(cp[k])] = at++;
+    }
+    __syncthreads();
+    float4* __restrict__ X = D.x[xin];
+    for (uint32_t i = tid; i < n; i += bs) {
+        const uint32_t j = D.newidx[i];
+        if (j >= n) continue;              // only after a cell overflow, already reported
+        D.x_alt[j] = X[i];
+        D.u_alt[j] = D.u[i];
+        D.img_alt[j] = D.img[i];
+        D.img_alt[n + j] = D.img[n + i];
+        D.img_alt[2 * n + j] = D.img[2 * n + i];
+        const uint32_t tg = D.tag[i];
+        D.tag_alt[j] = tg;
+        D.rtag[tg] = j;
+        D.occ_alt[j] = D.occ[i];
+        D.mol_alt[j] = D.mol[i];
+        for (uint32_t k = 0; k < P.cap_max; ++k) D.dyn_alt[k * n + j] = remap_slot(D, D.dyn[k * n + i]);
+        for (uint32_t k = 0; k < P.stat_max; ++k) D.stat_alt[k * n + j] = remap_slot(D, D.stat[k * n + i]);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += bs) {
+        X[i] = D.x_alt[i];
+        D.u[i] = D.u_alt[i];
+        D.img[i] = D.img_alt[i];
+        D.img[n + i] = D.img_alt[n + i];
+        D.img[2 * n + i] = D.img_alt[2 * n + i];
+        D.tag[i] = D.tag_alt[i];
+        D.occ[i] = D.occ_alt[i];
+        D.mol[i] = D.mol_alt[i];
+        for (uint32_t k = 0; k < P.cap_max; ++k) D.dyn[k * n + i] = D.dyn_alt[k * n + i];
+        for (uint32_t k = 0; k < P.stat_max; ++k) D.stat[k * n + i] = D.stat_alt[k * n + i];
+    }
+    for (uint32_t c = tid; c < P.ncell; c += bs) D.ccount[lst][c] = 0u;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += bs) bin_particle_wg(P, D, lst, i, X[i]);
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += bs) nl_build_site(P, T, D, lst, i, X[i]);
+}
+
 }  // namespace dyb

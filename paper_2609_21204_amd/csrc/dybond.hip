@@ -1217,6 +1217,7 @@ static db_status commit_impl(db_system* s) {
     HIPCHK(s, hipMemsetAsync(D.claimed, 0, n, s->stream));
     HIPCHK(s, hipMemsetAsync(D.prop, 0xFF, (size_t)n * 4, s->stream));
     HIPCHK(s, hipMemsetAsync(D.live_count, 0, 16, s->stream));
+    HIPCHK(s, hipMemsetAsync(D.newidx, 0, (size_t)n * 4, s->stream));   // in range before any sort
     HIPCHK(s, hipMemsetAsync(D.nl, 0, (size_t)P.nlmax * n * 4, s->stream));
     HIPCHK(s, hipMemsetAsync(D.nl_cnt, 0, (size_t)n * 4, s->stream));
     s->step = 0;
@@ -1388,6 +1389,10 @@ db_status run_batch(db_system* const* systems, uint32_t count, uint64_t nsteps, 
                 hipStream_t q = g ? R.streams[g - 1] : s0->stream;
                 for (uint64_t done = 0; ok && done < nsteps;) {
                     const uint32_t chunk = (uint32_t)std::min<uint64_t>(kBatchChunk, nsteps - done);
+                    // renumber every system in cell order before each chunk
+                    hipLaunchKernelGGL(k_batch_sort, dim3(spans[g].second), dim3(threads[g]), 0, q,
+                                       (const BatchItem*)(R.items + spans[g].first),
+                                       (const BatchState*)(R.state + spans[g].first));
                     if (full[g])
                         hipLaunchKernelGGL(k_batch<true>, dim3(spans[g].second), dim3(threads[g]), 0, q,
                                            (const BatchItem*)(R.items + spans[g].first), R.state + spans[g].first, chunk);
@@ -1421,6 +1426,7 @@ db_status run_batch(db_system* const* systems, uint32_t count, uint64_t nsteps, 
         s->step += nsteps;
         s->cur_x ^= (int)(nsteps & 1u);
         s->cur_list = (int)((s->cur_list + nsteps) % 3);
+        s->tags_dirty = true;              // renumbered by k_batch_sort
     }
     for (uint32_t k = 0; k < count; ++k) {
         const db_status e = check_errors(systems[k]);

@@ -1147,6 +1147,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const Params P, const Dev 
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     const uint32_t j = D.newidx[i];
+    if (j >= P.n) return;                  // only after a cell overflow, already reported
     const size_t n = P.n;
     D.x_alt[j] = D.x[xin][i];
     D.u_alt[j] = D.u[i];
