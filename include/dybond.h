@@ -290,7 +290,13 @@ DB_API db_status db_get_batch_plan(int device, db_batch_plan* plan);
  * 512, <= 1024, <= 2048, <= 4096, larger).  Starting from 1024 threads in
  * every class, each occupied class in turn, smallest first, tries 256 and
  * 512 threads, and keeps a size when the whole batch then runs at least 2 %
- * faster (device time of trial_steps steps, after one untimed trial).  Every
+ * faster (device time of trial_steps steps, after one untimed trial) than
+ * the plan in hand timed both just before and just after the candidate (the
+ * systems evolve between trials, and with them the cost of a step).
+ * Adjacent classes with the same size are merged in every plan tried and in
+ * the result (each class is a concurrent branch of the batch's graph, which
+ * costs time when it gains nothing), so a batch that gains from no change
+ * gets the one-class default back.  Every
  * trial advances all systems by trial_steps (1..2000): since results do not
  * depend on the plan, the trials are ordinary steps of the run, and
  * *steps_done (may be NULL) receives their number.  The chosen plan is

@@ -333,7 +333,7 @@ def db_batch_autotune(handles, trial_steps):
     arr = (ctypes.c_void_p * len(hs))(*hs)
     p = BatchPlan()
     done = _U64(0)
-    ms = np.zeros(16, dtype=np.float64)
+    ms = np.zeros(32, dtype=np.float64)                  # at most 1 + 4 x 5 timed trials
     st = load().db_batch_autotune(arr, len(hs), trial_steps, ctypes.byref(p), ctypes.byref(done), ms.ctypes.data,
                                   len(ms))
     if st != 0:

@@ -514,9 +514,14 @@ def test_batch_autotuner_keeps_results_and_stores_its_plan():
     try:
         plan, done, ms = db.db_batch_autotune([b.h for b in batch], 40)
         occupied = len({min(k for k, m in enumerate((512, 1024, 2048, 4096, _TOP)) if w.n <= m) for w in ws})
-        assert done == 40 * (2 + 2 * occupied) and len(ms) == 1 + 2 * occupied and min(ms) > 0
-        assert [m for m, _ in plan] == [512, 1024, 2048, 4096, _TOP]
+        # one untimed warm-up, the plan in hand, then per candidate (2 per
+        # occupied class) the candidate and the plan in hand again
+        assert done == 40 * (2 + 4 * occupied) and len(ms) == 1 + 4 * occupied and min(ms) > 0
+        # octave bounds, adjacent classes of equal size merged
+        bounds = [m for m, _ in plan]
+        assert bounds[-1] == _TOP and set(bounds) <= {512, 1024, 2048, 4096, _TOP} and bounds == sorted(bounds)
         assert all(t in (256, 512, 1024) for _, t in plan)
+        assert all(plan[k][1] != plan[k + 1][1] for k in range(len(plan) - 1))
         assert db.db_get_batch_plan(0) == plan
         db.db_step_batch([b.h for b in batch], 25)
         for p in plain:
