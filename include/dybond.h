@@ -207,8 +207,9 @@ DB_API db_status db_set_neighbor_list(db_system* sys, double skin, uint32_t max_
 DB_API db_status db_set_matching(db_system* sys, uint32_t grid_rounds, uint32_t lds_limit);
 
 /* Launch shape of the step kernel and the proposal kernel of the sweep:
- * threads that share one particle (1, 2, 4, 8, 16 or 32; 0 = automatic: 4,
- * or more for small systems so that a launch fills the GPU) and, with 4
+ * threads that share one particle (1, 2, 4, 8, 16 or 32, both kernels; 0 =
+ * automatic: 4 in the step kernel, or more for small systems so that a
+ * launch fills the GPU, and half that in the proposal kernel) and, with 4
  * threads per particle, how many neighbour-list entries each thread loads
  * before its first gather (1, 2 or 4; 0 = automatic: 4; longer lists are
  * then taken in further rounds).  Any shape gives the same result bit for
