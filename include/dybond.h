@@ -190,7 +190,7 @@ DB_API db_status db_set_cell_capacity(db_system* sys, uint32_t slots);
  * r_search + skin (r_search = max(WCA cutoff, r_max of every reaction)),
  * rebuilt on the device whenever some particle has moved by more than
  * skin / 2 since the last build, with at most max_neighbors entries per
- * particle.  skin < 0 selects the default 0.4; max_neighbors == 0 selects
+ * particle.  skin < 0 selects the default 0.3; max_neighbors == 0 selects
  * max(64, 2.5 x the mean neighbour count at the system's density + 32);
  * the skin shrinks automatically when the box holds fewer than 3 cells of
  * side r_search + skin.  A particle with more neighbours makes db_step return
