@@ -52,6 +52,12 @@ struct Timing {
 // 38.2 at 0.4, 39.1 at 0.2 (482.7 vs 495.2 us at 4 M particles, 0.3 vs 0.4).
 constexpr double kDefaultSkin = 0.3;
 
+// Steps between spatial renumberings (at the start of a captured span, so a
+// multiple of the 120-step span): each costs the sort and a list rebuild,
+// and the order decays slowly; 200k gel: 38.4 us per step sorting every 120
+// steps, 37.7 every 240, 37.5 every 480 (4 M particles: 504, 492, 494 us).
+constexpr uint64_t kSortPeriod = 480;
+
 struct db_system {
     // configuration (host)
     uint32_t n = 0, ntypes = 0;
@@ -99,7 +105,8 @@ struct db_system {
     uint32_t match_rounds = 1;             // full-grid matching rounds before the one-workgroup finish
     uint32_t finish_lds = kFinishLds;      // largest live list the finish matches in LDS
     bool tags_dirty = false;               // device tag/rtag changed since the host mirrors were read
-    bool sort_enabled = true;              // renumber particles in cell order every graph span
+    bool sort_enabled = true;              // renumber particles in cell order (every kSortPeriod steps)
+    uint64_t sort_due = 0;                 // step from which the next renumbering is due
 };
 
 namespace {
@@ -640,6 +647,7 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
     HIPCHK(s, hipMemcpyAsync(s->D.rflag, flags, sizeof flags, hipMemcpyHostToDevice, s->stream));
     s->cur_x = 0;
     s->cur_list = 0;
+    s->sort_due = s->step;                 // uploaded in tag order: renumber at the next span
     for (int l = 0; l < 3; ++l) LAUNCH(s, k_clear_counts, std::min(grid_of(P.ncell), 65535u), kBlock, s->P, s->D, l);
     LAUNCH(s, k_bin, grid_of(n), kBlock, s->P, s->D, 0, 0);
     LAUNCH(s, k_nlist, ntiles(P), kTileThreads, s->P, s->D, 0, (int)(s->step % 3));
@@ -798,14 +806,16 @@ db_status run_steps(db_system* s, uint64_t nsteps) {
     while (done < nsteps) {
         const bool aligned = (s->step % s->period) == 0;
         if (s->use_graphs && !s->timing.on && aligned && nsteps - done >= span) {
-            const int key = s->cur_x * 3 + s->cur_list;
+            // graphs with and without the renumbering at their start
+            const bool sort = s->sort_enabled && s->step >= s->sort_due;
+            const int key = (s->cur_x * 3 + s->cur_list) * 2 + (sort ? 1 : 0);
             auto it = s->graphs.find(key);
             if (it == s->graphs.end()) {
                 const uint64_t step0 = s->step;
                 const int x0 = s->cur_x, l0 = s->cur_list;
                 hipGraph_t g;
                 HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-                if (s->sort_enabled) launch_sort(s);
+                if (sort) launch_sort(s);
                 for (uint64_t k = 0; k < span; ++k) launch_step(s);
                 HIPCHK(s, hipStreamEndCapture(s->stream, &g));
                 hipGraphExec_t ge;
@@ -817,11 +827,17 @@ db_status run_steps(db_system* s, uint64_t nsteps) {
                 it = s->graphs.emplace(key, ge).first;
             }
             HIPCHK(s, hipGraphLaunch(it->second, s->stream));
-            if (s->sort_enabled) s->tags_dirty = true;
+            if (sort) {
+                s->tags_dirty = true;
+                s->sort_due = s->step + kSortPeriod;
+            }
             s->step += span;       // span is a multiple of 6: buffers return to (x0, l0)
             done += span;
         } else {
-            if (s->sort_enabled && s->timing.on && aligned && (s->step % span) == 0) launch_sort(s);
+            if (s->sort_enabled && s->timing.on && aligned && (s->step % span) == 0 && s->step >= s->sort_due) {
+                launch_sort(s);
+                s->sort_due = s->step + kSortPeriod;
+            }
             launch_step(s);
             ++done;
         }
