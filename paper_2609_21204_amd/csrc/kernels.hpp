@@ -425,11 +425,14 @@ __device__ __forceinline__ unsigned long long advance_particle(const Params& P, 
 }
 
 constexpr int kTileThreads = 512;
-constexpr int kTileMaxHalo = 1728;      // halo cells of one tile, (t+2)^3 <= 1728 (t <= 10)
-constexpr int kTileMaxEntries = 2048;   // particles staged in LDS per tile
+// The tables of one tile fit 35 KB of LDS, so that four 512-thread
+// workgroups share a CU (twice the tables, 1728 halo cells and 2048 entries,
+// allowed two and made the 200k gel's step 2 % slower).
+constexpr int kTileMaxHalo = 1000;      // halo cells of one tile, (t+2)^3 <= 1000 (t <= 8)
+constexpr int kTileMaxEntries = 1024;   // particles staged in LDS per tile
 constexpr int kTileChunk = (kTileMaxHalo + kTileThreads - 1) / kTileThreads;   // halo cells per thread in the scan
 constexpr int kTileLoads = kTileMaxEntries / kTileThreads;                     // staged entries per thread
-constexpr int kTileMaxCore = 1024;      // core particles whose candidates are dealt out evenly
+constexpr int kTileMaxCore = 512;       // core particles whose candidates are dealt out evenly
 
 // Workgroups are dealt round-robin to the 8 XCDs.  This remaps the workgroup
 // id so that each XCD gets a contiguous run of work items (particles are kept
@@ -571,8 +574,9 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
         for (int q = 0; q < kTileLoads; ++q) {
             const uint32_t e = min(tid + (uint32_t)q * kTileThreads, total - 1u);
             int lo = 0;                       // hoff[0] = 0 <= e < hoff[nh]
+            static_assert(kTileMaxHalo <= 1024, "binary search over at most 1024 halo cells");
 #pragma unroll
-            for (int step = 1024; step >= 1; step >>= 1)
+            for (int step = 512; step >= 1; step >>= 1)
                 if (lo + step < nh && hoff[lo + step] <= e) lo += step;
             hv[q] = lo;
             v[q] = cp[(size_t)hglob[lo] * P.cellcap + (e - hoff[lo])];
