@@ -1335,14 +1335,14 @@ __device__ __forceinline__ int propose_site(const Params& P, const Dev& D, int a
 // both sites for round 1.  A workgroup owns 256 sites, four runs of 64
 // consecutive ones (one per wave) taken from the four quarters of the index
 // range, which evens out the number of sites per workgroup that can propose
-// where they cluster in space (each pass of the scan below over 64 listed
-// sites is a chain of dependent loads; with particles stored in blocks of
-// one type, contiguous workgroups needed up to four passes in series while
-// others had none).  One thread per site
-// clears the site's sweep state and tests whether it can propose (a type of
-// the reaction, free valence); the sites that can are listed in LDS, and
-// then TPP threads per listed site scan its neighbour list.  Full or
-// unreactive sites, most of a bonded system, so cost one thread each.
+// where they cluster in space (each pass of the scan below over 256 / TPP
+// listed sites is a chain of dependent loads; with particles stored in
+// blocks of one type, contiguous workgroups needed up to four passes in
+// series while others had none).  One thread per site clears the site's
+// sweep state and tests whether it can propose (a type of the reaction,
+// free valence); the sites that can are listed in LDS, and then TPP threads
+// per listed site scan its neighbour list.  Full or unreactive sites, most
+// of a bonded system, so cost one thread each.
 template <int TPP>
 __global__ __launch_bounds__(256) void k_propose(const Params P, const Dev D, int slot, int xcur, int sp) {
     constexpr uint32_t kSites = 256, kPerPass = 256 / TPP;
