@@ -80,3 +80,40 @@ def test_events_account_for_the_change_of_the_bond_table():
         seen_f += len(f)
         seen_b += len(b)
     assert seen_f > 0 and seen_b > 0
+
+
+def test_events_across_two_reactions_on_one_pair():
+    """Two reactions on the same A-B pair, each with its own bond type
+    (reading of two reactions on one type pair), valence 1, P_on = P_off = 1,
+    the pair bonded by reaction 0 at the start of the sweep.  Reactions run
+    in the sweep's random order: reaction 0 first breaks the bond, and then
+    reaction 1 forms it again with its own bond type; reaction 1 first finds
+    both sites full, and reaction 0 then only breaks.  Counted by hand for
+    each order."""
+    from oracle.philox import reaction_order
+    pos = POS[:2]
+    seen = set()
+    for key in range(10, 400, 10):
+        o = OracleSystem(2, 2, 10.0, 5)
+        o.set_type(0, 1, 1.0, 1.0, 1.0)
+        o.set_type(1, 1, 1.0, 1.0, 1.0)
+        b0 = o.add_bond_type(BOND_HARMONIC, 100.0, 1.0)
+        b1 = o.add_bond_type(BOND_HARMONIC, 100.0, 1.0)
+        o.set_particles(pos, np.zeros((2, 3)), [0, 1])
+        for bt in (b0, b1):
+            o.add_reaction(Reaction(type_a=0, type_b=1, bond_type=bt, r_min=0.0, r_max=1.3, k_on=math.nan,
+                                    k_off=math.nan, epsilon=0.0, p_on0=1.0, self_avoid=0))
+        o.set_integrator(0.005, 1.0, 1.0, 10)
+        o.commit()
+        o.set_state(0, pos, np.zeros((2, 3)), [(0, 1)], [b0])
+        order = tuple(reaction_order(5, key, 2))
+        o.sweep_frozen(key)
+        f, _ = o.sweep_events("formed")
+        b, _ = o.sweep_events("broken")
+        assert b.tolist() == [[0, 1, b0]]
+        if order == (0, 1):
+            assert f.tolist() == [[0, 1, b1]] and o.bonds().tolist() == [[0, 1, b1]]
+        else:
+            assert f.tolist() == [] and o.bonds().tolist() == []
+        seen.add(order)
+    assert seen == {(0, 1), (1, 0)}

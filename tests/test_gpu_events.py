@@ -128,3 +128,43 @@ def test_tiny_system_certain_forming_and_breaking():
             assert s.bonds().tolist() == ef
         ob = s.observables()
         assert ob["forms"].tolist() == [4] and ob["breaks"].tolist() == [4] and ob["attempts"].tolist() == [4]
+
+
+def test_events_across_two_reactions_on_one_pair_match_oracle():
+    """Two reactions on one A-B pair with their own bond types, P_on =
+    P_off = 1, the pair bonded by reaction 0 when each sweep starts: in one
+    reaction order the bond breaks and forms again with reaction 1's type,
+    in the other it only breaks.  Bonds and both event lists equal the
+    oracle's for sweeps of both orders."""
+    import math
+    from oracle import OracleSystem, Reaction
+    from oracle.dybond import BOND_HARMONIC
+    from oracle.philox import reaction_order
+    pos = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]], np.float32)
+    log("case events, two reactions on one pair")
+    o = OracleSystem(2, 2, 10.0, 5)
+    with db.System(2, 2, 10.0, 5) as s:
+        for t in range(2):
+            db.db_set_type(s.h, t, 1, 1.0, 1.0, 1.0)
+            o.set_type(t, 1, 1.0, 1.0, 1.0)
+        for _ in range(2):
+            db.db_add_bond_type(s.h, db.DB_BOND_HARMONIC, 100.0, 1.0)
+            o.add_bond_type(BOND_HARMONIC, 100.0, 1.0)
+        db.db_set_particles(s.h, pos, np.zeros((2, 3)), [0, 1])
+        o.set_particles(pos, np.zeros((2, 3)), [0, 1])
+        for bt in range(2):
+            db.db_add_reaction(s.h, db.make_reaction(0, 1, bt, 0.0, 1.3, epsilon=0.0, p_on0=1.0, self_avoid=0))
+            o.add_reaction(Reaction(0, 1, bt, 0.0, 1.3, k_on=math.nan, k_off=math.nan, epsilon=0.0, p_on0=1.0,
+                                    self_avoid=0))
+        db.db_commit(s.h)
+        o.set_integrator(0.005, 1.0, 1.0, 10)
+        o.commit()
+        seen = set()
+        for key in range(10, 200, 10):
+            s.set_state(0, pos, np.zeros((2, 3)), [[0, 1]], [0])
+            o.set_state(0, pos, np.zeros((2, 3)), [(0, 1)], [0])
+            s.sweep_frozen(key)
+            o.sweep_frozen(key)
+            assert_same_bonds(s, o, f"two reactions, key {key}")
+            seen.add(tuple(reaction_order(5, key, 2)))
+        assert seen == {(0, 1), (1, 0)}
