@@ -17,6 +17,8 @@ What it computes (paper sections in parentheses):
   rates interpolated between their initial and melted values by
   g(T) = [tanh(lambda (T - T_melt)) + 1] / 2 (Eqs. gT, kT), or slip bonds,
   P_off(r) = P0_off exp(a sqrt(U_b(r)/kT)) (Eq. slip);
+* the bonds each sweep formed and broke (its event lists), in the order the
+  sweep makes them and read out sorted;
 * observables: bond counts, bonded fraction, largest cluster, energies;
 * network analyses of the kind the paper's examples measure on assembled
   gels (Sec. 4): the bond correlation function (the fraction of the bonds of
