@@ -361,6 +361,37 @@ def test_exact_ties_on_a_lattice_match_oracle():
         assert o.counters[0, 1] > 0 and o.counters[0, 2] > 0
 
 
+@pytest.mark.parametrize("n", [40, 1])
+def test_smallest_boxes_match_oracle(n):
+    """Boxes at the three-cell minimum (L = 5 against a list radius of 1.6:
+    each cell's 3 x 3 x 3 stencil is the whole box, every cell once, and
+    most pairs meet across a periodic boundary), dense enough that
+    bonds form and break, and a single particle with no partner: forces, five
+    sweeps with their event lists, and one MD step against the oracle."""
+    log(f"case smallest box, n={n}")
+    w = inputs.small(seed=3, n=n, density=n / 125.0, eps_bond=2.0)
+    assert abs(w.L - 5.0) < 1e-9
+    with db.System.from_workload(w) as s:
+        s.step(33)
+        o = oracle_from_workload(w)
+        sync_oracle(s, o)
+        assert_forces(s, o, f"three cells, n={n}")
+        c0 = counters(s)
+        for key in (1000, 1010, 1020, 7, 2 ** 33 + 5):
+            s.sweep_frozen(key)
+            o.sweep_frozen(key)
+            assert_same_bonds(s, o, f"three cells, n={n}, key {key}")
+        assert np.array_equal(counters(s) - c0, o.counters)
+        if n > 1:
+            assert o.counters[:, 1].sum() > 0 and o.counters[:, 2].sum() > 0, "forming and breaking"
+        sync_oracle(s, o)
+        s.step(1)
+        o.step(1)
+        dpos = o.delta(o.x, s.positions().astype(np.float64))
+        assert np.abs(dpos).max() < 1e-4
+        assert np.allclose(s.velocities().astype(np.float64), o.v, rtol=1e-4, atol=2e-4)
+
+
 def test_edge_cases():
     log("case edge: no reactions")
     w = inputs.small(seed=1)
