@@ -506,6 +506,31 @@ def test_batched_run_across_launch_chunks():
             x.close()
 
 
+def test_batch_with_the_smallest_systems():
+    """A single particle and a three-cell box of 40 particles batched with a
+    512-particle system, in the default plan and with one wave per system,
+    equal db_step bit for bit."""
+    ws = [inputs.small(seed=3, n=1, density=1 / 125.0, eps_bond=2.0),
+          inputs.small(seed=3, n=40, density=40 / 125.0, eps_bond=2.0), inputs.small(seed=8)]
+    for plan in (None, [(_TOP, 64)]):
+        log(f"case batch smallest systems: sizes {[w.n for w in ws]}, plan {plan}")
+        plain = [db.System.from_workload(w) for w in ws]
+        batch = [db.System.from_workload(w) for w in ws]
+        try:
+            for p in plain:
+                p.step(613)
+            if plan is None:
+                db.db_step_batch([b.h for b in batch], 613)
+            else:
+                db.db_step_batch_plan([b.h for b in batch], 613, plan)
+            for k, (p, b) in enumerate(zip(plain, batch)):
+                _assert_same_state(p, b, f"system {k} ({ws[k].n} particles)")
+            assert counters(plain[1])[:, 2].sum() > 0        # the 40-particle box formed and broke bonds
+        finally:
+            for x in plain + batch:
+                x.close()
+
+
 @pytest.mark.parametrize("shape", [(1, 0), (2, 0), (4, 1), (4, 2), (8, 0)])
 def test_step_shape_does_not_change_results(shape):
     """Any launch shape of the step and proposal kernels (threads per
