@@ -62,8 +62,9 @@ from scipy.sparse import coo_matrix
 from scipy.sparse.csgraph import connected_components
 from scipy.spatial import cKDTree
 
-from .philox import (KIND_MATCH, KIND_OFF, KIND_ON, KIND_THERMO, box_muller3,
-                     philox4x32_10, reaction_order, step_words, stream_key, u53)
+from .philox import (KIND_INIT, KIND_MATCH, KIND_OFF, KIND_ON, KIND_THERMO,
+                     box_muller3, philox4x32_10, reaction_order, step_words,
+                     stream_key, u53)
 
 BOND_HARMONIC = 0
 BOND_FENE = 1
@@ -222,10 +223,30 @@ class OracleSystem:
         self.kT = float(kT)
 
     def set_particles(self, pos, vel, types):
+        """Initial state; ``vel=None`` asks for Maxwell-Boltzmann velocities,
+        drawn at commit (see ``maxwell_boltzmann_velocities``)."""
         self.x = np.array(pos, dtype=np.float64).reshape(self.n, 3)
-        self.v = np.array(vel, dtype=np.float64).reshape(self.n, 3)
+        self.v = None if vel is None else np.array(vel, dtype=np.float64).reshape(self.n, 3)
         self.types = np.array(types, dtype=np.int64).reshape(self.n)
         self.img = np.zeros((self.n, 3), dtype=np.int64)
+
+    def maxwell_boltzmann_velocities(self):
+        """Velocities of the set-point temperature with zero total momentum.
+
+        Each Cartesian component of particle t is sqrt(kT / m) g, with three
+        standard normals g from one block of the INIT stream (counter
+        (0, 0, t, 0), Box-Muller as for the thermal noise); then the
+        mass-weighted mean velocity sum_t m_t v_t / sum_t m_t is subtracted,
+        so the total momentum is zero.  The velocities follow the
+        equilibrium distribution of the thermostat the paper's MD runs under
+        (Sec. 2.2 uses the kinetic temperature of these velocities).
+        """
+        k0, k1 = stream_key(self.seed, KIND_INIT)
+        w = philox4x32_10(0, 0, np.arange(self.n, dtype=np.uint64), 0, k0, k1)
+        g = np.stack(box_muller3(*w), axis=1)
+        m = self.mass[self.types][:, None]
+        v = np.sqrt(self.kT / m) * g
+        return v - np.sum(m * v, axis=0) / np.sum(m)
 
     def add_static_bonds(self, pairs, bond_types):
         pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
@@ -246,6 +267,8 @@ class OracleSystem:
         """Validate, close the rate parameters and derive molecule ids."""
         if self.x is None:
             raise OracleError("ESTATE", "particles not set")
+        if self.v is None:
+            self.v = self.maxwell_boltzmann_velocities()
         self.rates = []
         seen_bt = set()
         for rx in self.reactions:
@@ -395,9 +418,13 @@ class OracleSystem:
             F[j] -= fi
         return F, PE
 
-    def force_contribution_norms(self, x):
-        """Per particle, sum over its interactions of |F_ij| (for tolerances)."""
+    def force_contribution_norms(self, x, counts=False):
+        """Per particle, the sum over its interactions (WCA pairs inside the
+        cutoff, static and dynamic bonds) of |F_ij|: the scale of the force
+        tolerances, which a net force that cancels to near zero would not
+        give.  With ``counts`` also the number of those interactions."""
         S = np.zeros(self.n)
+        C = np.zeros(self.n, dtype=np.int64)
         if self.rc_max > 0:
             i, j, d, r = self.pairs_within(x, self.rc_max)
             ti, tj = self.types[i], self.types[j]
@@ -408,12 +435,16 @@ class OracleSystem:
             f = np.abs(4.0 * eps * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r)
             np.add.at(S, i, f)
             np.add.at(S, j, f)
+            np.add.at(C, i, 1)
+            np.add.at(C, j, 1)
         for i, j, bt in self.all_bonds():
             r = float(self.norm(self.delta(x[i], x[j])))
             _, dudr = self.bond_energy_force(bt, r)
             S[i] += abs(dudr)
             S[j] += abs(dudr)
-        return S
+            C[i] += 1
+            C[j] += 1
+        return (S, C) if counts else S
 
     def all_bonds(self):
         """Static bonds followed by dynamic bonds, as (i, j, bond_type)."""
@@ -470,6 +501,10 @@ class OracleSystem:
 
     # -------------------------------------------------------------- sweep
     def current_kT(self):
+        """Temperature of the acceptance factor (Eq. pon): the thermostat's
+        set point, or in kinetic mode the instantaneous kinetic temperature
+        of Sec. 2.2, sum_i m_i |v_i|^2 / (3 N) with k_B = 1 and 3N degrees of
+        freedom (the velocities as they stand when the sweep runs)."""
         if not self.kinetic_T:
             return self.kT
         m = self.mass[self.types]

@@ -1,17 +1,18 @@
 """Counter-based random numbers for the oracle (test infrastructure only).
 
-The paper draws every stochastic decision from a counter-based Philox
-generator keyed by the simulation seed, the time step and a stream identifier
-(binding vs unbinding of each reaction) and counted by the sorted pair of
-particle tags (Sec. 2.5, "GPU implementation").  It does not fix the variant
-or the layout of key and counter; the reading used on both sides is:
+In the paper every random decision of a sweep comes from a counter-based
+Philox generator whose key and counter combine the seed, the step, a stream
+id per reaction and direction, and the two tags of a pair ordered by size
+(Sec. 2.5).  The variant and the placement of these fields in key and
+counter are left open; both sides here use:
 
 * generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), 10 rounds,
   multipliers 0xD2511F53 / 0xCD9E8D57, Weyl key increments
   0x9E3779B9 / 0xBB67AE85;
 * key   = (seed, kind << 24 | reaction << 16 | replica);
 * counter = (step_lo, step_hi, a, b) where (a, b) is (tag, 0) for per-site
-  draws and (min tag, max tag) for per-pair draws.
+  draws and (min tag, max tag) for per-pair draws; the initial velocities
+  use step 0 of the INIT stream.
 
 Everything here is plain integer arithmetic on numpy uint64 arrays holding
 32-bit values, written from the published definition of the round function.
@@ -27,13 +28,14 @@ W0 = 0x9E3779B9
 W1 = 0xBB67AE85
 MASK32 = 0xFFFFFFFF
 
-# Stream kinds (the "identifier distinguishing the binding and unbinding
-# streams of each reaction channel", Sec. 2.5, extended to the other draws).
+# Stream kinds: the per-reaction binding and unbinding streams of Sec. 2.5,
+# plus one stream for each other random draw of the method.
 KIND_THERMO = 1   # Langevin noise, per particle
 KIND_ORDER = 2    # order in which reactions are processed in a sweep (Sec. 2.3)
 KIND_MATCH = 3    # priority of a proposal in the matching phase
 KIND_ON = 4       # acceptance draw of a claimed pair (Eq. pon)
 KIND_OFF = 5      # breaking draw of an existing bond (Eq. pon, P_off)
+KIND_INIT = 6     # initial Maxwell-Boltzmann velocities, per particle
 
 
 def stream_key(seed, kind, reaction=0, replica=0):

@@ -143,6 +143,86 @@ def test_bond_closed_forms():
                   bond=(1, 30.0, 1.5))
 
 
+def test_force_contribution_norms_on_a_hand_built_state():
+    """Sum of contribution magnitudes |F_ij| and their number, per particle,
+    on a state whose contributions are known in closed form: WCA contacts at
+    r = sigma = 1 (|F| = 24 eps / sigma), a static harmonic bond stretched by
+    0.2 (|F| = k |r - r0| = 20) and a dynamic one stretched by 0.3 (30); every
+    other pair lies beyond the WCA cutoff.  Particle 0 sits between two
+    contacts, so its net force cancels while its scale is 48."""
+    pts = [(0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (1.0, 1.2, 0.0), (-1.0, 0.0, 0.0), (-1.0, 0.0, 1.3)]
+    o = OracleSystem(5, 2, 20.0, 1)
+    o.set_type(0, 0, 1.0, 1.0, 1.0)
+    o.set_type(1, 1, 1.0, 1.0, 1.0)
+    o.add_bond_type(0, 100.0, 1.0)                  # static
+    o.add_bond_type(0, 100.0, 1.0)                  # the reaction's
+    o.set_particles(pts, np.zeros((5, 3)), [0, 0, 0, 1, 1])
+    o.add_static_bonds([(1, 2)], [0])
+    o.add_reaction(Reaction(1, 1, 1, 0.0, 1.5, epsilon=2.0, p_on0=0.5, self_avoid=0))
+    o.commit()
+    o.set_state(0, pts, np.zeros((5, 3)), [(3, 4)], [1])
+    S, C = o.force_contribution_norms(o.x, counts=True)
+    assert np.allclose(S, [48.0, 44.0, 20.0, 54.0, 30.0], rtol=1e-12, atol=0)
+    assert C.tolist() == [2, 2, 1, 2, 1]
+    assert np.array_equal(o.force_contribution_norms(o.x), S)
+    F, _ = o.forces(o.x)
+    assert np.abs(F[0]).max() < 1e-12               # the two contacts cancel
+    assert abs(np.linalg.norm(F[1]) - math.hypot(24.0, 20.0)) < 1e-12    # not the scale 44
+
+
+def test_kinetic_temperature_on_hand_built_velocities():
+    """Instantaneous kinetic temperature (Sec. 2.2): sum_i m_i |v_i|^2 / (3N)
+    with k_B = 1.  Masses 1, 2, 0.5 with |v|^2 = 9, 9, 4 give
+    (9 + 18 + 2) / 9; the set-point mode ignores the velocities."""
+    vel = [(1.0, 2.0, 2.0), (0.0, 3.0, 0.0), (2.0, 0.0, 0.0)]
+    for kinetic, want in ((True, 29.0 / 9.0), (False, 1.7)):
+        o = OracleSystem(3, 3, 20.0, 1)
+        for t, m in enumerate((1.0, 2.0, 0.5)):
+            o.set_type(t, 0, 1.0, 1.0, m)
+        o.set_particles([(0, 0, 0), (3, 0, 0), (0, 3, 0)], vel, [0, 1, 2])
+        o.set_integrator(0.005, 1.7, 1.0, 10, kinetic_T=kinetic)
+        o.commit()
+        assert abs(o.current_kT() - want) < 1e-15
+    # swapping the two heavier particles' velocities changes the reading
+    o.v = np.array([vel[0], vel[2], vel[1]], dtype=np.float64)
+    o.kinetic_T = True
+    assert abs(o.current_kT() - (9.0 + 8.0 + 4.5) / 9.0) < 1e-15
+
+
+def test_maxwell_boltzmann_velocities_and_their_temperature():
+    """Velocities drawn for vel=None: zero total momentum, each component of
+    a type of mass m normal with variance kT / m (chi-square and
+    Kolmogorov-Smirnov), and a kinetic temperature equal to kT within its
+    statistical error sqrt(2 / (3N))."""
+    n, kT = 30000, 1.3
+    rng = np.random.default_rng(8)
+    o = OracleSystem(n, 3, 100.0, 4)
+    masses = (1.0, 4.0, 0.25)
+    for t, m in enumerate(masses):
+        o.set_type(t, 0, 1.0, 1.0, m)
+    types = rng.integers(0, 3, n)
+    o.set_particles(rng.uniform(-50, 50, (n, 3)), None, types)
+    o.set_integrator(0.005, kT, 1.0, 10, kinetic_T=True)
+    o.commit()
+    m = np.array(masses)[types][:, None]
+    p = np.sum(m * o.v, axis=0)
+    assert np.abs(p).max() < 1e-9 * np.sum(m * np.abs(o.v))
+    for t, mt in enumerate(masses):
+        z = (o.v[types == t] * math.sqrt(mt / kT)).ravel()
+        k = len(z)
+        assert abs(np.sum(z * z) - k) < 5.0 * math.sqrt(2.0 * k)
+        assert stats.kstest(z, "norm").pvalue > 1e-4
+    assert abs(o.current_kT() - kT) < 4.0 * kT * math.sqrt(2.0 / (3 * n))
+    # independent of the thermostat stream: a different seed gives other draws
+    o2 = OracleSystem(n, 3, 100.0, 5)
+    for t, mt in enumerate(masses):
+        o2.set_type(t, 0, 1.0, 1.0, mt)
+    o2.set_particles(o.x, None, types)
+    o2.set_integrator(0.005, kT, 1.0, 10)
+    o2.commit()
+    assert abs(np.corrcoef(o.v.ravel(), o2.v.ravel())[0, 1]) < 0.02
+
+
 def _mixed_system(seed=11):
     """Dense small system: mixed sigma, FENE chains and harmonic dynamic bonds."""
     rng = np.random.default_rng(seed)
