@@ -248,7 +248,7 @@ def main():
     db.db_kernel_timing(s.h, 1)
     s.step(max(a.profile_steps, 1))
     kern = {}
-    for name in ("k_step", "k_nlist", "k_propose", "k_claim", "k_kill", "k_finish", "k_break",
+    for name in ("k_step", "k_binr", "k_nlist", "k_propose", "k_claim", "k_kill", "k_finish", "k_break",
                  "k_cell_scan_blocks", "k_scan_bsum", "k_sort_assign", "k_sort_scatter", "k_sort_copyback",
                  "k_clear_counts", "k_bin"):
         cnt, ms = db.db_read_kernel_time(s.h, name)

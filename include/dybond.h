@@ -59,13 +59,20 @@ typedef enum {
     DB_EOVERFLOW = 8   /* more particles in one cell than the cell capacity */
 } db_status;
 
-enum { DB_BOND_HARMONIC = 0,   /* U = k/2 (r - r0)^2 */
-       DB_BOND_FENE = 1,       /* U = -k R0^2/2 ln(1 - r^2/R0^2), r0 argument = R0 */
-       DB_BOND_TETHER = 2 };   /* registered with db_add_tether_bond_type */
+/* Bond potentials (Sec. 2.2: the bond of a reaction supplies both the force
+ * and the energy U_b of Eq. pon). */
+typedef enum {
+    DB_BOND_HARMONIC = 0,      /* U = k/2 (r - r0)^2 */
+    DB_BOND_FENE = 1,          /* U = -k R0^2/2 ln(1 - r^2/R0^2), r0 argument = R0 */
+    DB_BOND_TETHER = 2         /* registered with db_add_tether_bond_type */
+} db_bond_kind;
 
-enum { DB_KT_SETPOINT = 0,     /* acceptance uses the thermostat set point kT */
-       DB_KT_KINETIC = 1 };    /* acceptance uses the instantaneous kinetic temperature
+/* Temperature T of the acceptance factor exp(-U_b / kT) of Eq. pon. */
+typedef enum {
+    DB_KT_SETPOINT = 0,        /* the thermostat set point kT */
+    DB_KT_KINETIC = 1          /* the instantaneous kinetic temperature
                                   sum(m v^2) / (3N) at the sweep (Sec. 2.2) */
+} db_kt_source;
 
 #define DB_MAX_REACTIONS 8
 
@@ -111,21 +118,39 @@ DB_API db_status db_create(uint32_t n, uint32_t n_types, double box_L, uint32_t 
 /* Free the handle and all its host and device memory.  NULL is ignored. */
 DB_API void db_destroy(db_system* sys);
 
-/* Per-type parameters: valence (maximum number of dynamic bonds of a site of
- * this type; 0 = not reactive), WCA sigma and epsilon (sigma_ij is the
- * arithmetic mean, eps_ij the geometric mean; sigma 0 switches WCA off for
- * the type), and mass (> 0).  Defaults: valence 0, sigma 1, eps 1, mass 1. */
+/* Per-type parameters (Sec. 2.1: reactive sites are particles of a type;
+ * the paper's sites hold one dynamic bond, the valence generalises that to
+ * a cap of `valence` dynamic bonds per site): valence (0 = not reactive,
+ * at most 8), WCA sigma and epsilon (sigma_ij is the arithmetic mean,
+ * eps_ij the geometric mean; sigma 0 switches WCA off for the type), and
+ * mass (> 0).  Defaults: valence 0, sigma 1, eps 1, mass 1.  Host only.
+ * Errors: DB_EINVAL (type out of range, bad value), DB_ESTATE (after
+ * db_commit). */
 DB_API db_status db_set_type(db_system* sys, uint32_t type, uint32_t valence, double wca_sigma,
                       double wca_eps, double mass);
 
-/* Initial state in tag order: pos3[3n] in [-L/2, L/2), vel3[3n], type[n] < n_types.
- * All three pointers are required. */
+/* Initial state of the particles (Sec. 2.1: the system whose sites react),
+ * in tag order: pos3[3n] in [-L/2, L/2) (x, y, z per particle), vel3[3n]
+ * and type[n] < n_types; the arrays are copied.  vel3 == NULL asks for
+ * Maxwell-Boltzmann velocities at the set-point kT with zero total
+ * momentum, drawn by db_validate / db_commit from the INIT random stream
+ * (component c of tag t is sqrt(kT / m) g_c, g three Box-Muller normals of
+ * the Philox block (0, 0, t, 0); then the mass-weighted mean velocity is
+ * subtracted), so they follow the integrator's parameters whatever the
+ * order of the set-up calls.  Host only.  Errors: DB_EINVAL (pos3 or type
+ * NULL, a position outside the box, a type out of range), DB_ESTATE (after
+ * db_commit: use db_set_state). */
 DB_API db_status db_set_particles(db_system* sys, const float* pos3, const float* vel3,
                            const uint32_t* type);
 
-/* Register a bond type (kind DB_BOND_HARMONIC or DB_BOND_FENE, stiffness k,
- * rest length r0 or FENE maximum extension R0); *id receives its index. */
-DB_API db_status db_add_bond_type(db_system* sys, int kind, double k, double r0, uint32_t* id);
+/* Register a bond type (Sec. 2.2: the bond potential a reaction forms is
+ * also the U_b(r) of its acceptance, Eq. pon, and its minimum is the target
+ * length r0 of the proposal rule, Sec. 2.3): kind DB_BOND_HARMONIC or
+ * DB_BOND_FENE, stiffness k >= 0, rest length r0 >= 0 (harmonic) or FENE
+ * maximum extension R0 > 0; *id (may be NULL) receives its index.  Host
+ * only.  Errors: DB_EINVAL (bad kind or value, more than 8 bond types),
+ * DB_ESTATE (after db_commit). */
+DB_API db_status db_add_bond_type(db_system* sys, db_bond_kind kind, double k, double r0, uint32_t* id);
 
 /* Register a tether bond type (Sec. 2.2 names it among the bond potentials
  * a reaction may use): U(r) = U_att + U_rep with
@@ -138,13 +163,21 @@ DB_API db_status db_add_bond_type(db_system* sys, int kind, double k, double r0,
 DB_API db_status db_add_tether_bond_type(db_system* sys, double k_b, double l_min, double l_c1, double l_c0,
                                          double l_max, uint32_t* id);
 
-/* Add m static (never-breaking) bonds: tag_pairs[2m] and bond_types[m].
- * Static bonds define the molecules used by self_avoid (Sec. 2.4). */
+/* Add m static (never-breaking) bonds: tag_pairs[2m] and bond_types[m]
+ * (copied).  Static bonds define the molecules used by self_avoid
+ * (Sec. 2.4).  Host only; checked by db_validate (tags, bond types, at most
+ * 8 static bonds per particle).  Errors: DB_EINVAL (NULL arrays with m > 0),
+ * DB_ESTATE (after db_commit). */
 DB_API db_status db_add_static_bonds(db_system* sys, const uint32_t* tag_pairs,
                               const uint32_t* bond_types, uint64_t m);
 
-/* Register a reaction (copied); *id receives its index (processing order is
- * redrawn at random every sweep, Sec. 2.3). */
+/* Register a reaction channel (Sec. 2.1, keyed by its type pair as in
+ * Sec. 2.6; the descriptor is copied); *id (may be NULL) receives its
+ * index.  The processing order of the reactions is redrawn at random every
+ * sweep (Sec. 2.3).  Rates are closed by db_validate (Eq. epsilon, Eq.
+ * probs).  Host only.  Errors: DB_EINVAL (NULL descriptor, more than 8
+ * reactions), DB_ESTATE (after db_commit); the descriptor's values are
+ * checked by db_validate. */
 DB_API db_status db_add_reaction(db_system* sys, const db_reaction_desc* desc, uint32_t* id);
 
 /* Rate modifiers of a reaction (Sec. 2.4; at most one per reaction, the two
@@ -168,11 +201,14 @@ DB_API db_status db_set_reaction_melting(db_system* sys, uint32_t reaction, doub
                                          double k_on_melt, double k_off_melt);
 DB_API db_status db_set_reaction_slip(db_system* sys, uint32_t reaction, double a);
 
-/* Integrator: time step dt > 0, thermostat kT >= 0, friction gamma >= 0,
- * sweep period n >= 1 (the n of Eq. probs), temperature source for the
- * acceptance factor (DB_KT_SETPOINT or DB_KT_KINETIC).  Defaults 0.005, 1, 1, 10. */
+/* Integrator and sweep trigger (Sec. 2.3: a sweep runs every n MD steps,
+ * between the position update and the force; Eq. probs: P0 = k n dt):
+ * time step dt > 0, Langevin thermostat kT >= 0, friction gamma >= 0,
+ * sweep period n >= 1, temperature of the acceptance factor (Eq. pon,
+ * Sec. 2.2).  Defaults 0.005, 1, 1, 10, DB_KT_SETPOINT.  Host only.
+ * Errors: DB_EINVAL (value out of range), DB_ESTATE (after db_commit). */
 DB_API db_status db_set_integrator(db_system* sys, double dt, double kT, double gamma,
-                            uint32_t sweep_period, int kt_source);
+                            uint32_t sweep_period, db_kt_source kt_source);
 
 /* Change the set-point temperature kT (>= 0), before or after db_commit:
  * the thermostat's noise, the acceptance factor and the melting modifier
@@ -232,15 +268,24 @@ DB_API db_status db_validate(db_system* sys);
 DB_API db_status db_get_reaction(const db_system* sys, uint32_t id, db_reaction_desc* resolved,
                           double* p_on0, double* p_off0);
 
-/* db_validate, then allocate device memory, upload the state and compute the
- * initial forces.  Errors as db_validate, plus DB_EDEVICE/DB_ENOMEM, DB_EBOND
- * (FENE bond already overstretched). */
+/* db_validate (rate closure, Eq. epsilon and Eq. probs, with P0 <= 1
+ * required; molecules as the components of the static bonds, Sec. 2.4),
+ * then allocate device memory on the handle's device, upload the state,
+ * build the neighbour list and compute the initial forces.  Device memory
+ * is owned by the handle until db_destroy.  Errors as db_validate, plus
+ * DB_EDEVICE (no device, HIP error), DB_ENOMEM, DB_EBOND (a bond already
+ * outside its range), DB_EOVERFLOW (cell or neighbour capacity),
+ * DB_ESTATE (already committed). */
 DB_API db_status db_commit(db_system* sys);
 
-/* Advance n_steps time steps (sweeps included at every step s with
- * s % sweep_period == 0, after the position update and before the forces).
- * Synchronous: returns when the GPU work is done.  DB_EBOND / DB_EOVERFLOW
- * leave the state invalid (DB_ESTATE) until db_set_state. */
+/* Advance n_steps Langevin MD time steps (BAOAB) with the bonding sweep of
+ * Sec. 2.3 at every step s with s % sweep_period == 0, after the position
+ * update and before the forces at the new positions; each sweep forms bonds
+ * with P_on = P0_on exp(-U_b(r)/kT) and breaks the bonds present at its
+ * start with P0_off (Eq. pon, Eq. probs).  Synchronous: returns when the
+ * GPU work is done.  Errors: DB_ESTATE (not committed, invalid state),
+ * DB_EDEVICE; DB_EBOND / DB_EOVERFLOW leave the state invalid (DB_ESTATE)
+ * until db_set_state. */
 DB_API db_status db_step(db_system* sys, uint64_t n_steps);
 
 /* Launch plan of a batch (db_step_batch): the systems fall into size
@@ -308,9 +353,13 @@ DB_API db_status db_batch_autotune(db_system* const* systems, uint32_t count, ui
                                    db_batch_plan* best, uint64_t* steps_done, double* trial_ms,
                                    uint32_t trial_len);
 
-/* One bonding sweep at the current positions with step key `step_key`
- * (random streams keyed as for a sweep at that step); particles do not move,
- * velocities are unchanged, the step counter is unchanged. */
+/* One bonding sweep of Sec. 2.3 (proposal, greedy matching, acceptance by
+ * Eq. pon, breaking of the bonds present at its start; reactions in the
+ * random order of that step) at the current positions, with the random
+ * streams keyed as for a sweep at step `step_key`; particles do not move,
+ * velocities are unchanged, the step counter is unchanged.  Synchronous.
+ * Errors: DB_ESTATE, DB_EDEVICE, DB_EBOND (a reaction's bond out of range
+ * in the forces evaluated after the sweep). */
 DB_API db_status db_sweep_frozen(db_system* sys, uint64_t step_key);
 
 /* Replace the dynamic state: step counter, pos3[3n], vel3[3n] (tag order) and
@@ -321,19 +370,29 @@ DB_API db_status db_set_state(db_system* sys, uint64_t step, const float* pos3, 
                        const uint32_t* dyn_tag_pairs, const uint32_t* dyn_bond_types,
                        uint64_t m);
 
-/* Positions pos3[3n] in [-L/2, L/2) (tag order); image3[3n] (may be NULL)
- * receives the periodic image counters. */
+/* Positions pos3[3n] in [-L/2, L/2) (tag order, caller's buffer);
+ * image3[3n] (may be NULL) receives the periodic image counters.  Before
+ * db_commit: the positions given to db_set_particles (images 0), no GPU
+ * touched.  Errors: DB_EINVAL (pos3 NULL), DB_ESTATE, DB_EDEVICE. */
 DB_API db_status db_read_positions(db_system* sys, float* pos3, int32_t* image3);
 
-/* Full-step velocities vel3[3n] (tag order). */
+/* Full-step velocities vel3[3n] (tag order, caller's buffer).  Before
+ * db_commit: the velocities given to db_set_particles, or those db_validate
+ * drew when it was given NULL (DB_ESTATE before that), no GPU touched.
+ * Errors: DB_EINVAL (vel3 NULL), DB_ESTATE, DB_EDEVICE. */
 DB_API db_status db_read_velocities(db_system* sys, float* vel3);
 
-/* Forces force3[3n] at the current positions and bonds (tag order). */
+/* Forces force3[3n] (tag order, caller's buffer) at the current positions
+ * and bonds: WCA on all pairs plus the static and dynamic bond forces.
+ * Errors: DB_EINVAL (force3 NULL), DB_ESTATE, DB_EDEVICE, DB_EBOND. */
 DB_API db_status db_read_forces(db_system* sys, float* force3);
 
-/* Dynamic bonds, sorted by (tag_lo, tag_hi, bond_type): tag_pairs[2*cap]
- * (tag_lo < tag_hi) and bond_types[cap].  *count receives the number of bonds
- * (also on DB_ETRUNC). */
+/* The dynamic bond table after the last sweep (Sec. 2.5: the table each
+ * sweep edits, read back by tag), sorted by (tag_lo, tag_hi, bond_type):
+ * tag_pairs[2*cap] (tag_lo < tag_hi) and bond_types[cap], caller's
+ * buffers.  *count receives the number of bonds (also on DB_ETRUNC).
+ * Synchronous.  Errors: DB_EINVAL (count NULL, NULL arrays with bonds to
+ * write), DB_ESTATE, DB_EDEVICE, DB_ETRUNC (cap too small). */
 DB_API db_status db_read_bonds(db_system* sys, uint32_t* tag_pairs, uint32_t* bond_types,
                         uint64_t cap, uint64_t* count);
 
@@ -356,7 +415,12 @@ enum { DB_EVENT_FORMED = 0, DB_EVENT_BROKEN = 1 };
 DB_API db_status db_read_sweep_events(db_system* sys, int which, uint32_t* tag_pairs, uint32_t* bond_types,
                                       uint64_t cap, uint64_t* count, uint64_t* sweep_step);
 
-/* Observables of the current state (computed on the device). */
+/* Observables of the current state, computed on the device (the bond
+ * statistics of Sec. 2.2 and the network measures of Sec. 4): bonds and
+ * cumulative attempt / form / break counters per reaction, bonded fraction,
+ * largest-cluster fraction over static + dynamic bonds, potential and
+ * kinetic energy, kinetic temperature.  *out is the caller's.
+ * Synchronous.  Errors: DB_EINVAL (out NULL), DB_ESTATE, DB_EDEVICE. */
 DB_API db_status db_read_observables(db_system* sys, db_observables* out);
 
 /* Network analyses of the bond network, computed on the device from the

@@ -283,8 +283,14 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
         if (tid == 0) D.ke_fix[ke_slot(P, s) ^ 1u] = 0ull;   // the next sweep's slot, as db_step leaves it
     }
     // hand the state back in the form db_step leaves it: step slots, no list
-    // rebuild pending, round-1 key buffer clear
+    // rebuild pending, the cell list of db_step's next build empty, round-1
+    // key buffer clear
     for (uint32_t i = tid; i < n; i += bs) D.best[1][i] = kNoKey;
+    __syncthreads();
+    {
+        uint32_t* __restrict__ cl = D.ccount[D.rflag[3]];
+        for (uint32_t c = tid; c < P.ncell; c += bs) cl[c] = 0u;
+    }
     if (tid == 0) {
         D.stepv[0] = D.stepv[1] = t0 + nsteps;
         D.rflag[0] = D.rflag[1] = D.rflag[2] = 0u;
@@ -317,6 +323,13 @@ void k_batch_sort(const BatchItem* __restrict__ items, const BatchState* __restr
     const size_t n = P.n;
     __shared__ StepTabs T;
     stage_tabs(D, T, tid);
+    // the current positions binned into cell list `lst`, the other two empty
+    // (db_step keeps its cell lists in its own way)
+    for (int l = 0; l < 3; ++l)
+        for (uint32_t c = tid; c < P.ncell; c += bs) D.ccount[l][c] = 0u;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += bs) bin_particle_wg(P, D, lst, i, D.x[xin][i]);
+    __syncthreads();
     const uint32_t nbk = P.ncell * P.ntypes;
     const uint32_t per = (nbk + bs - 1) / bs;
     const uint32_t b0 = min(tid * per, nbk), b1 = min(b0 + per, nbk);
@@ -326,7 +339,7 @@ void k_batch_sort(const BatchItem* __restrict__ items, const BatchState* __restr
     uint32_t at = block_exclusive_scan(cnt, &total);
     for (uint32_t b = b0; b < b1; ++b) {
         uint32_t c, t;
-        bucket_cell_type(P, b, c, t);
+        bucket_cell_type(P, D, b, c, t);
         uint32_t m = D.ccount[lst][c];
         m = m < P.cellcap ? m : P.cellcap;
         const float4* cp = D.cpos[lst] + (size_t)c * P.cellcap;

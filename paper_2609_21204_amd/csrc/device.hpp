@@ -23,7 +23,7 @@ constexpr float kFixScale = 4294967296.0f;     // 2^32: fixed-point force / ener
 constexpr double kFixInv = 1.0 / 4294967296.0;
 
 // Random stream kinds: one stream per purpose, reaction and replica.
-enum : uint32_t { kThermo = 1, kOrder = 2, kMatch = 3, kOn = 4, kOff = 5 };
+enum : uint32_t { kThermo = 1, kOrder = 2, kMatch = 3, kOn = 4, kOff = 5, kInit = 6 };
 
 // Edge states of the matching phase.
 enum : uint8_t { kEdgeNone = 0, kEdgeLive = 1, kEdgeMatched = 2, kEdgeDead = 3 };
@@ -216,7 +216,9 @@ struct Dev {
     uint32_t* nl;          // nlmax x n neighbour indices (slot-major)
     uint32_t* nl_cnt;      // neighbours per particle
     float4* xref;          // positions at the last neighbour-list build
-    uint32_t* rflag;       // neighbour-list rebuild flags of steps t, t+1, t+2 (index step mod 3)
+    uint32_t* rflag;       // neighbour-list rebuild flags of steps t, t+1, t+2 (index step mod 3);
+                           // [3]: the cell list (0 or 1) the next build bins into
+    uint32_t* corder;      // cells in Morton order (the renumbering's cell sequence)
     // spatial reordering (counting sort by cell): new index of every particle,
     // cell offsets, and second copies of every per-particle array
     uint32_t* newidx;

@@ -72,6 +72,7 @@ struct db_system {
     std::vector<float> pos, vel;
     std::vector<uint32_t> type;
     bool have_particles = false;
+    bool vel_given = false;                // false: Maxwell-Boltzmann velocities drawn by validate()
     std::vector<uint32_t> stat_pairs, stat_bt;
     double dt = 0.005, kT = 1.0, gamma = 1.0;
     uint32_t period = 10;
@@ -246,6 +247,40 @@ double effective_skin(const db_system* s, double rsearch) {
     return std::min(s->skin, room);
 }
 
+// Velocities of the set-point temperature kT with zero total momentum, for a
+// db_set_particles call without velocities: component c of tag t is
+// sqrt(kT / m) g_c with three standard normals g from Box-Muller on the block
+// (0, 0, t, 0) of the INIT stream (u1 = (w + 1) / 2^32 in (0, 1],
+// u2 = w' / 2^32), then the mass-weighted mean velocity is subtracted.
+void draw_velocities(db_system* s) {
+    const uint32_t n = s->n;
+    std::vector<double> v(3 * (size_t)n);
+    double px = 0.0, py = 0.0, pz = 0.0, msum = 0.0;
+    const uint32_t k1 = stream_k1(kInit, 0, 0);
+    const double twopi = 2.0 * 3.14159265358979323846;
+    for (uint32_t t = 0; t < n; ++t) {
+        const Word4 w = philox(0u, 0u, t, 0u, s->seed, k1);
+        const double ra = std::sqrt(-2.0 * std::log(((double)w.w0 + 1.0) * 0x1.0p-32));
+        const double ta = twopi * ((double)w.w1 * 0x1.0p-32);
+        const double rb = std::sqrt(-2.0 * std::log(((double)w.w2 + 1.0) * 0x1.0p-32));
+        const double tb = twopi * ((double)w.w3 * 0x1.0p-32);
+        const double m = s->types[s->type[t]].mass, sd = std::sqrt(s->kT / m);
+        v[3 * (size_t)t] = sd * (ra * std::cos(ta));
+        v[3 * (size_t)t + 1] = sd * (ra * std::sin(ta));
+        v[3 * (size_t)t + 2] = sd * (rb * std::cos(tb));
+        px += m * v[3 * (size_t)t];
+        py += m * v[3 * (size_t)t + 1];
+        pz += m * v[3 * (size_t)t + 2];
+        msum += m;
+    }
+    s->vel.resize(3 * (size_t)n);
+    for (uint32_t t = 0; t < n; ++t) {
+        s->vel[3 * (size_t)t] = (float)(v[3 * (size_t)t] - px / msum);
+        s->vel[3 * (size_t)t + 1] = (float)(v[3 * (size_t)t + 1] - py / msum);
+        s->vel[3 * (size_t)t + 2] = (float)(v[3 * (size_t)t + 2] - pz / msum);
+    }
+}
+
 db_status validate(db_system* s) {
     s->validated = false;
     if (!s->have_particles) return fail(s, DB_ESTATE, "particles not set");
@@ -308,6 +343,7 @@ db_status validate(db_system* s) {
         if (++deg[i] > (uint32_t)kMaxStatic || ++deg[j] > (uint32_t)kMaxStatic)
             return fail(s, DB_EINVAL, "more than %d static bonds on one particle", kMaxStatic);
     }
+    if (!s->vel_given) draw_velocities(s);
     s->validated = true;
     return DB_OK;
 }
@@ -391,6 +427,32 @@ void choose_tiles(const db_system* s, Params& P) {
         P.tile[d] = (uint32_t)t;
         P.ntile[d] = (P.nc + (uint32_t)t - 1) / (uint32_t)t;
     }
+}
+
+// The cells of an nc^3 grid (index (z nc + y) nc + x) in Morton order: sorted
+// by the interleaved bits of (x, y, z), x in the lowest bit of each triple.
+std::vector<uint32_t> morton_cells(uint32_t nc) {
+    auto spread = [](uint64_t v) {          // bit b of v moves to bit 3b
+        uint64_t r = 0;
+        for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+        return r;
+    };
+    std::vector<uint64_t> sx(nc), sy(nc), sz(nc);
+    for (uint32_t k = 0; k < nc; ++k) {
+        sx[k] = spread(k);
+        sy[k] = spread(k) << 1;
+        sz[k] = spread(k) << 2;
+    }
+    const uint64_t ncell = (uint64_t)nc * nc * nc;
+    std::vector<uint64_t> key(ncell);     // Morton code (< 2^33 for nc < 2048) above the cell index
+    for (uint64_t c = 0; c < ncell; ++c) {
+        const uint64_t x = c % nc, y = (c / nc) % nc, z = c / ((uint64_t)nc * nc);
+        key[c] = ((sx[x] | sy[y] | sz[z]) << 31) | c;
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<uint32_t> out(ncell);
+    for (uint64_t r = 0; r < ncell; ++r) out[r] = (uint32_t)(key[r] & 0x7FFFFFFFull);
+    return out;
 }
 
 // Melting modifier at temperature T (Eqs. gT, kT): P = P_init (1 - g) + P_melt g,
@@ -643,16 +705,17 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
     // no sweep has run on this state yet: empty event lists, step key all ones
     const uint32_t evc0[4] = {0u, 0u, 0xFFFFFFFFu, 0xFFFFFFFFu};
     HIPCHK(s, hipMemcpyAsync(s->D.evc, evc0, sizeof evc0, hipMemcpyHostToDevice, s->stream));
-    const uint32_t flags[3] = {s->step % 3 == 0, s->step % 3 == 1, s->step % 3 == 2};   // lists built below
+    // lists built below, from cell list 0 (all three cleared)
+    const uint32_t flags[4] = {s->step % 3 == 0, s->step % 3 == 1, s->step % 3 == 2, 0u};
     HIPCHK(s, hipMemcpyAsync(s->D.rflag, flags, sizeof flags, hipMemcpyHostToDevice, s->stream));
-    s->cur_x = 0;
-    s->cur_list = 0;
-    s->sort_due = s->step;                 // uploaded in tag order: renumber at the next span
+    s->cur_x = (int)(s->step & 1u);        // buffer indices follow the step counter
+    s->cur_list = (int)(s->step % 3);
+    s->sort_due = s->step;                 // uploaded in tag order: renumber at the next period boundary
     for (int l = 0; l < 3; ++l) LAUNCH(s, k_clear_counts, std::min(grid_of(P.ncell), 65535u), kBlock, s->P, s->D, l);
-    LAUNCH(s, k_bin, grid_of(n), kBlock, s->P, s->D, 0, 0);
-    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, s->P, s->D, 0, (int)(s->step % 3));
-    LAUNCH(s, k_eval, grid_of(n), kBlock, s->P, s->D, 0, 0, 0u);
-    LAUNCH(s, k_init_u, grid_of(n), kBlock, s->P, s->D, 0, 0u);
+    LAUNCH(s, k_binr, grid_of(n), kBlock, s->P, s->D, s->cur_x, (int)(s->step % 3));
+    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, s->P, s->D, (int)(s->step % 3));
+    LAUNCH(s, k_eval, grid_of(n), kBlock, s->P, s->D, s->cur_x, 0u);
+    LAUNCH(s, k_init_u, grid_of(n), kBlock, s->P, s->D, s->cur_x, 0u);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipStreamSynchronize(s->stream));
     uint32_t err[4];
@@ -731,15 +794,16 @@ void launch_sweep(db_system* s, int xcur, int sp) {
 void launch_sort(db_system* s) {
     const Params& P = s->P;
     const unsigned gc = grid_of(P.ncell), gb = grid_of(P.ncell * P.ntypes), g = grid_of(P.n);
-    const int xc = s->cur_x, lc = s->cur_list;
-    LAUNCH(s, k_cell_scan_blocks, gb, kBlock, P, s->D, lc);
+    const int xc = s->cur_x, f3 = (int)(s->step % 3);
+    LAUNCH(s, k_clear_counts, std::min(gc, 65535u), kBlock, P, s->D, kSortList);
+    LAUNCH(s, k_bin, g, kBlock, P, s->D, xc, kSortList);
+    LAUNCH(s, k_cell_scan_blocks, gb, kBlock, P, s->D, kSortList);
     LAUNCH(s, k_scan_bsum, 1, 1024, s->D.cbsum, gb);
-    LAUNCH(s, k_sort_assign, gb, kBlock, P, s->D, lc);
+    LAUNCH(s, k_sort_assign, gb, kBlock, P, s->D, kSortList);
     LAUNCH(s, k_sort_scatter, g, kBlock, P, s->D, xc);
-    LAUNCH(s, k_sort_copyback, g, kBlock, P, s->D, xc, (int)(s->step % 3));
-    LAUNCH(s, k_clear_counts, std::min(gc, 65535u), kBlock, P, s->D, lc);
-    LAUNCH(s, k_bin, g, kBlock, P, s->D, xc, lc);
-    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, lc, (int)(s->step % 3));
+    LAUNCH(s, k_sort_copyback, g, kBlock, P, s->D, xc, f3);
+    LAUNCH(s, k_binr, g, kBlock, P, s->D, xc, f3);
+    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, f3);
     s->tags_dirty = true;
 }
 
@@ -747,14 +811,13 @@ void launch_sort(db_system* s) {
 void launch_step(db_system* s) {
     const Params& P = s->P;
     const uint64_t t = s->step;
-    const int xin = s->cur_x, lcur = s->cur_list;
-    const int lnext = (lcur + 1) % 3, lclr = (lcur + 2) % 3;
+    const int xin = s->cur_x;
     const int sp = (int)(t & 1);
     const bool sweep = P.nrx > 0 && ((t + 1) % P.period == 0);
     const int ake = (sweep && P.kt_kinetic) ? 1 : 0;
     const unsigned gs = (unsigned)(((uint64_t)P.n * P.tpp_step + kBlock - 1) / kBlock);
     const int f3 = (int)(t % 3);
-#define STEP_AS(...) LAUNCH_AS(s, "k_step", (__VA_ARGS__), gs, kBlock, P, s->D, xin, lnext, lclr, sp, f3, ake)
+#define STEP_AS(...) LAUNCH_AS(s, "k_step", (__VA_ARGS__), gs, kBlock, P, s->D, xin, sp, f3, ake)
     if (P.ext) {
         switch (P.tpp_step) {
             case 1: STEP_AS(k_step1<true>); break;
@@ -783,64 +846,144 @@ void launch_step(db_system* s) {
         }
     }
 #undef STEP_AS
-    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, lnext, (int)((t + 1) % 3));
+    LAUNCH(s, k_binr, grid_of(P.n), kBlock, P, s->D, xin ^ 1, (int)((t + 1) % 3));
+    LAUNCH(s, k_nlist, ntiles(P), kTileThreads, P, s->D, (int)((t + 1) % 3));
     s->cur_x ^= 1;
-    s->cur_list = lnext;
+    s->cur_list = (s->cur_list + 1) % 3;
     s->step = t + 1;
     if (sweep) launch_sweep(s, s->cur_x, (int)((t + 1) & 1));
 }
 
-// Steps per graph: a whole number of sweep periods that also returns the
-// rotating buffers (x: 2, cell lists: 3, step slots: 2, rebuild flags: 3) to
-// where they were.
+// Captured graphs.  The buffer indices of a step are functions of the step
+// counter t (position buffer t mod 2, cell list t mod 3, step slot t mod 2,
+// rebuild-flag slot t mod 3; upload_state and every launcher keep
+// cur_x = t mod 2 and cur_list = t mod 3), and whether a step ends in a
+// sweep is a function of t mod period, so a graph captured at step t replays
+// correctly at any step with the same t mod 6 and the same sweep pattern.
+// Kinds: one step (with or without its sweep), one sweep period from an
+// aligned step, a span of periods (>= 120 steps) from an aligned step, and
+// the spatial renumbering.  The one-step, one-period and renumbering graphs
+// are captured together on the first db_step call, so that any later call,
+// however short, replays graphs only.
+enum : int { kGStep = 0, kGPeriod = 1, kGSpan = 2, kGSort = 3 };
+
+bool sweep_after(const db_system* s, uint64_t t) { return s->P.nrx > 0 && (t + 1) % s->period == 0; }
+
+int graph_key(const db_system* s, int kind, uint64_t t) {
+    const bool sw = kind == kGStep && sweep_after(s, t);
+    return (kind * 6 + (int)(t % 6)) * 2 + (sw ? 1 : 0);
+}
+
+// Steps in a span graph: a whole number of sweep periods, at least 120 (0:
+// none, when the period alone is longer than that).
 uint64_t graph_span(const db_system* s) {
-    uint64_t g = s->period;
-    while (g % 6 != 0) g += s->period;
-    while (g < 120) g *= 2;
-    return g;
+    if (s->period > 120) return 0;
+    return (uint64_t)s->period * ((120 + s->period - 1) / s->period);
+}
+
+// Steps in a period graph (0: none, for periods longer than 120 steps).
+uint64_t graph_period(const db_system* s) { return s->period <= 120 ? s->period : 0; }
+
+// The graph of `kind` at step t, captured (with the host's step state set to
+// t and restored afterwards) when not yet held.
+db_status graph_at(db_system* s, int kind, uint64_t t, hipGraphExec_t* out) {
+    const int key = graph_key(s, kind, t);
+    auto it = s->graphs.find(key);
+    if (it != s->graphs.end()) {
+        *out = it->second;
+        return DB_OK;
+    }
+    const uint64_t step0 = s->step;
+    const int x0 = s->cur_x, l0 = s->cur_list;
+    const bool dirty0 = s->tags_dirty;
+    s->step = t;
+    s->cur_x = (int)(t & 1u);
+    s->cur_list = (int)(t % 3);
+    hipGraph_t g;
+    HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    if (kind == kGSort) {
+        launch_sort(s);
+    } else {
+        const uint64_t k = kind == kGStep ? 1 : kind == kGPeriod ? graph_period(s) : graph_span(s);
+        for (uint64_t q = 0; q < k; ++q) launch_step(s);
+    }
+    HIPCHK(s, hipStreamEndCapture(s->stream, &g));
+    hipGraphExec_t ge;
+    HIPCHK(s, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    HIPCHK(s, hipGraphDestroy(g));
+    // the executable's device-side setup now, not on its first launch (a
+    // short db_step call may be the first to replay it)
+    HIPCHK(s, hipGraphUpload(ge, s->stream));
+    s->step = step0;
+    s->cur_x = x0;
+    s->cur_list = l0;
+    s->tags_dirty = dirty0;
+    s->graphs.emplace(key, ge);
+    *out = ge;
+    return DB_OK;
+}
+
+// Capture every one-step, one-period and renumbering graph a run can need.
+db_status prepare_graphs(db_system* s) {
+    const uint64_t per = s->period, t0 = s->step;
+    for (uint64_t t = t0; t < t0 + 6 * per; ++t) {
+        hipGraphExec_t ge;
+        db_status st = graph_at(s, kGStep, t, &ge);
+        if (st != DB_OK) return st;
+        if (t % per == 0) {
+            if (graph_period(s) && (st = graph_at(s, kGPeriod, t, &ge)) != DB_OK) return st;
+            if (s->sort_enabled && (st = graph_at(s, kGSort, t, &ge)) != DB_OK) return st;
+        }
+    }
+    return DB_OK;
 }
 
 db_status run_steps(db_system* s, uint64_t nsteps) {
-    const uint64_t span = graph_span(s);
+    const uint64_t span = graph_span(s), per = graph_period(s);
+    const bool graphs = s->use_graphs && !s->timing.on;
+    if (graphs && s->graphs.empty()) {
+        const db_status st = prepare_graphs(s);
+        if (st != DB_OK) return st;
+    }
     uint64_t done = 0;
     while (done < nsteps) {
         const bool aligned = (s->step % s->period) == 0;
-        if (s->use_graphs && !s->timing.on && aligned && nsteps - done >= span) {
-            // graphs with and without the renumbering at their start
-            const bool sort = s->sort_enabled && s->step >= s->sort_due;
-            const int key = (s->cur_x * 3 + s->cur_list) * 2 + (sort ? 1 : 0);
-            auto it = s->graphs.find(key);
-            if (it == s->graphs.end()) {
-                const uint64_t step0 = s->step;
-                const int x0 = s->cur_x, l0 = s->cur_list;
-                hipGraph_t g;
-                HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-                if (sort) launch_sort(s);
-                for (uint64_t k = 0; k < span; ++k) launch_step(s);
-                HIPCHK(s, hipStreamEndCapture(s->stream, &g));
+        // renumbering at the first sweep-period boundary once it is due
+        if (aligned && s->sort_enabled && s->step >= s->sort_due) {
+            if (graphs) {
                 hipGraphExec_t ge;
-                HIPCHK(s, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-                HIPCHK(s, hipGraphDestroy(g));
-                s->step = step0;
-                s->cur_x = x0;
-                s->cur_list = l0;
-                it = s->graphs.emplace(key, ge).first;
-            }
-            HIPCHK(s, hipGraphLaunch(it->second, s->stream));
-            if (sort) {
-                s->tags_dirty = true;
-                s->sort_due = s->step + kSortPeriod;
-            }
-            s->step += span;       // span is a multiple of 6: buffers return to (x0, l0)
-            done += span;
-        } else {
-            if (s->sort_enabled && s->timing.on && aligned && (s->step % span) == 0 && s->step >= s->sort_due) {
+                const db_status st = graph_at(s, kGSort, s->step, &ge);
+                if (st != DB_OK) return st;
+                HIPCHK(s, hipGraphLaunch(ge, s->stream));
+            } else {
                 launch_sort(s);
-                s->sort_due = s->step + kSortPeriod;
             }
+            s->tags_dirty = true;
+            s->sort_due = s->step + kSortPeriod;
+        }
+        if (!graphs) {
             launch_step(s);
             ++done;
+            continue;
         }
+        const uint64_t left = nsteps - done;
+        int kind = kGStep;
+        uint64_t k = 1;
+        if (aligned && span && left >= span) {
+            kind = kGSpan;
+            k = span;
+        } else if (aligned && per && left >= per) {
+            kind = kGPeriod;
+            k = per;
+        }
+        hipGraphExec_t ge;
+        const db_status st = graph_at(s, kind, s->step, &ge);
+        if (st != DB_OK) return st;
+        HIPCHK(s, hipGraphLaunch(ge, s->stream));
+        s->step += k;
+        s->cur_x = (int)(s->step & 1u);
+        s->cur_list = (int)(s->step % 3);
+        done += k;
     }
     return DB_OK;
 }
@@ -911,21 +1054,23 @@ db_status db_set_type(db_system* s, uint32_t type, uint32_t valence, double sigm
 db_status db_set_particles(db_system* s, const float* pos3, const float* vel3, const uint32_t* type) {
     if (!s) return DB_EINVAL;
     if (s->committed) return fail(s, DB_ESTATE, "use db_set_state after commit");
-    if (!pos3 || !vel3 || !type) return fail(s, DB_EINVAL, "pos3, vel3 and type are required");
+    if (!pos3 || !type) return fail(s, DB_EINVAL, "pos3 and type are required");
     const float half = (float)(0.5 * s->L);
     for (size_t k = 0; k < 3 * (size_t)s->n; ++k)
         if (!(pos3[k] >= -half && pos3[k] < half)) return fail(s, DB_EINVAL, "position %zu outside [-L/2, L/2)", k / 3);
     for (uint32_t i = 0; i < s->n; ++i)
         if (type[i] >= s->ntypes) return fail(s, DB_EINVAL, "type of particle %u out of range", i);
     s->pos.assign(pos3, pos3 + 3 * (size_t)s->n);
-    s->vel.assign(vel3, vel3 + 3 * (size_t)s->n);
+    if (vel3) s->vel.assign(vel3, vel3 + 3 * (size_t)s->n);
+    else s->vel.clear();
+    s->vel_given = vel3 != nullptr;
     s->type.assign(type, type + s->n);
     s->have_particles = true;
     s->validated = false;
     return DB_OK;
 }
 
-db_status db_add_bond_type(db_system* s, int kind, double k, double r0, uint32_t* id) {
+db_status db_add_bond_type(db_system* s, db_bond_kind kind, double k, double r0, uint32_t* id) {
     if (!s) return DB_EINVAL;
     if (s->committed) return fail(s, DB_ESTATE, "parameters are fixed after commit");
     if (kind != DB_BOND_HARMONIC && kind != DB_BOND_FENE) return fail(s, DB_EINVAL, "unknown bond kind");
@@ -1013,7 +1158,7 @@ db_status db_add_reaction(db_system* s, const db_reaction_desc* d, uint32_t* id)
     return DB_OK;
 }
 
-db_status db_set_integrator(db_system* s, double dt, double kT, double gamma, uint32_t period, int kt_source) {
+db_status db_set_integrator(db_system* s, double dt, double kT, double gamma, uint32_t period, db_kt_source kt_source) {
     if (!s) return DB_EINVAL;
     if (s->committed) return fail(s, DB_ESTATE, "integrator is fixed after commit");
     if (!(dt > 0.0) || !(kT >= 0.0) || !(gamma >= 0.0) || period < 1 || !std::isfinite(dt) ||
@@ -1210,6 +1355,7 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.nl_cnt, n);
     DALLOC(s, D.xref, n);
     DALLOC(s, D.rflag, 4);
+    DALLOC(s, D.corder, P.ncell);
     DALLOC(s, D.newidx, n);
     DALLOC(s, D.cstart, (size_t)P.ncell * P.ntypes + 1);
     DALLOC(s, D.cbsum, grid_of(P.ncell * P.ntypes) + 1);
@@ -1234,6 +1380,10 @@ static db_status commit_impl(db_system* s) {
     union_find_mol(s, mol);
     HIPCHK(s, hipMemcpyAsync(D.stat, stat.data(), stat.size() * 4, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(D.mol, mol.data(), n * 4, hipMemcpyHostToDevice, s->stream));
+    {
+        const std::vector<uint32_t> co = morton_cells(P.nc);
+        HIPCHK(s, hipMemcpy(D.corder, co.data(), co.size() * 4, hipMemcpyHostToDevice));
+    }
     HIPCHK(s, hipMemcpyAsync(D.tag, s->tag_h.data(), n * 4, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(D.rtag, s->rtag_h.data(), n * 4, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemsetAsync(D.counters, 0, (size_t)3 * kMaxRx * kCtrSlots * sizeof(unsigned long long), s->stream));
@@ -1584,8 +1734,8 @@ db_status db_sweep_frozen(db_system* s, uint64_t step_key) {
     if (s->P.nrx == 0) return DB_OK;
     HIPCHK(s, hipSetDevice(s->device));
     const unsigned g = grid_of(s->n);
-    const int xc = s->cur_x, lc = s->cur_list;
-    LAUNCH(s, k_eval, g, kBlock, s->P, s->D, xc, lc, 0u);
+    const int xc = s->cur_x;
+    LAUNCH(s, k_eval, g, kBlock, s->P, s->D, xc, 0u);
     const unsigned long long sv[2] = {step_key, step_key};
     const unsigned long long sv_back[2] = {s->step, s->step};
     HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv, sizeof sv, hipMemcpyHostToDevice, s->stream));
@@ -1596,7 +1746,7 @@ db_status db_sweep_frozen(db_system* s, uint64_t step_key) {
     launch_sweep(s, xc, (int)(step_key & 1));
     // both kinetic-energy slots start the next regular sweep cleared
     if (s->P.kt_kinetic) HIPCHK(s, hipMemsetAsync(s->D.ke_fix, 0, 16, s->stream));
-    LAUNCH(s, k_eval, g, kBlock, s->P, s->D, xc, lc, s->n);
+    LAUNCH(s, k_eval, g, kBlock, s->P, s->D, xc, s->n);
     LAUNCH(s, k_fix_u, g, kBlock, s->P, s->D, xc);
     HIPCHK(s, hipMemcpyAsync(s->D.stepv, sv_back, sizeof sv_back, hipMemcpyHostToDevice, s->stream));
     return check_errors(s);
@@ -1639,7 +1789,21 @@ db_status db_set_state(db_system* s, uint64_t step, const float* pos3, const flo
     return upload_state(s, pos3, vel3, pairs, bts, m);
 }
 
+// Before db_commit the read-outs of positions and velocities return the
+// set-up state (host copies; no GPU is touched).
+static db_status read_setup(db_system* s, float* out3, bool velocities, int32_t* image3) {
+    if (!out3) return fail(s, DB_EINVAL, "output is NULL");
+    if (!s->have_particles) return fail(s, DB_ESTATE, "particles not set");
+    if (velocities && !s->vel_given && !s->validated)
+        return fail(s, DB_ESTATE, "velocities not given: they are drawn by db_validate");
+    const std::vector<float>& src = velocities ? s->vel : s->pos;
+    std::memcpy(out3, src.data(), 3 * (size_t)s->n * sizeof(float));
+    if (image3) std::memset(image3, 0, 3 * (size_t)s->n * sizeof(int32_t));
+    return DB_OK;
+}
+
 db_status db_read_positions(db_system* s, float* pos3, int32_t* image3) {
+    if (s && !s->committed && !s->dead) return read_setup(s, pos3, false, image3);
     db_status st = ready(s);
     if (st != DB_OK) return st;
     if (!pos3) return fail(s, DB_EINVAL, "pos3 is NULL");
@@ -1670,7 +1834,7 @@ static db_status read_vec(db_system* s, float* out3, int mode) {
     if (st != DB_OK) return st;
     if (!out3) return fail(s, DB_EINVAL, "output is NULL");
     HIPCHK(s, hipSetDevice(s->device));
-    LAUNCH(s, k_eval, grid_of(s->n), kBlock, s->P, s->D, s->cur_x, s->cur_list, 0u);
+    LAUNCH(s, k_eval, grid_of(s->n), kBlock, s->P, s->D, s->cur_x, 0u);
     LAUNCH(s, k_gather, grid_of(s->n), kBlock, s->P, s->D, s->stage, s->cur_x, mode);
     std::vector<float4> h(s->n);
     HIPCHK(s, hipMemcpyAsync(h.data(), s->stage, s->n * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
@@ -1692,7 +1856,7 @@ static db_status read_vec_device(db_system* s, float* out3, void* stream, int mo
     if (!out3) return fail(s, DB_EINVAL, "output is NULL");
     HIPCHK(s, hipSetDevice(s->device));
     const hipStream_t q = stream ? (hipStream_t)stream : s->stream;
-    if (mode != 0) LAUNCH(s, k_eval, grid_of(s->n), kBlock, s->P, s->D, s->cur_x, s->cur_list, 0u);
+    if (mode != 0) LAUNCH(s, k_eval, grid_of(s->n), kBlock, s->P, s->D, s->cur_x, 0u);
     if (q != s->stream) {
         if (!s->ev_out) HIPCHK(s, hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
         if (!s->ev_back) HIPCHK(s, hipEventCreateWithFlags(&s->ev_back, hipEventDisableTiming));
@@ -1712,7 +1876,10 @@ db_status db_read_positions_device(db_system* s, float* pos3, void* stream) { re
 db_status db_read_velocities_device(db_system* s, float* vel3, void* stream) { return read_vec_device(s, vel3, stream, 1); }
 db_status db_read_forces_device(db_system* s, float* force3, void* stream) { return read_vec_device(s, force3, stream, 2); }
 
-db_status db_read_velocities(db_system* s, float* vel3) { return read_vec(s, vel3, 1); }
+db_status db_read_velocities(db_system* s, float* vel3) {
+    if (s && !s->committed && !s->dead) return read_setup(s, vel3, true, nullptr);
+    return read_vec(s, vel3, 1);
+}
 db_status db_read_forces(db_system* s, float* force3) { return read_vec(s, force3, 2); }
 
 db_status db_read_bonds(db_system* s, uint32_t* pairs, uint32_t* bts, uint64_t cap, uint64_t* count) {
@@ -1882,7 +2049,7 @@ db_status db_read_observables(db_system* s, db_observables* out) {
     HIPCHK(s, hipSetDevice(s->device));
     const unsigned g = grid_of(s->n);
     const Params& P = s->P;
-    LAUNCH(s, k_eval, g, kBlock, P, s->D, s->cur_x, s->cur_list, 0u);
+    LAUNCH(s, k_eval, g, kBlock, P, s->D, s->cur_x, 0u);
     HIPCHK(s, hipMemsetAsync(s->D.red, 0, (4 + kMaxRx) * 8, s->stream));
     LAUNCH(s, k_observe, g, kBlock, P, s->D, s->cur_x);
     // largest cluster

@@ -239,37 +239,19 @@ __device__ __forceinline__ Force3 fix_to_force(const Dev& D, long long fx, long 
                   (float)((double)fz * kFixInv)};
 }
 
-// Total force on particle i at positions X with cell list `lst`; optional
-// per-particle energy (half of each pair and bond energy).  Candidates are
-// screened in FP32 with a safety margin; pairs that survive are evaluated in
-// FP64 with the same cutoff test as the oracle (r < 2^(1/6) sigma_ij).  Each
-// contribution is rounded to 2^-32 and summed in 64-bit integers.
+// Total force on particle i at positions X from its neighbour list (valid
+// for X: every pair within the interaction range is listed until some
+// particle has moved by skin / 2 since the build, and the step that moves it
+// that far rebuilds the lists); optional per-particle energy (half of each
+// pair and bond energy).  Candidates are screened in FP32 with a safety
+// margin; pairs that survive are evaluated in FP64 with the same cutoff test
+// as the oracle (r < 2^(1/6) sigma_ij).  Each contribution is rounded to
+// 2^-32 and summed in 64-bit integers.
 __device__ __forceinline__ Force3 force_on(const Params& P, const Dev& D, const float4* __restrict__ X,
-                                           int lst, uint32_t i, float4 pi, uint32_t ti,
-                                           double* e) {
+                                           uint32_t i, float4 pi, uint32_t ti, double* e) {
     long long fx = 0, fy = 0, fz = 0;
-    const uint32_t* __restrict__ cnt = D.ccount[lst];
-    const float4* __restrict__ cp = D.cpos[lst];
-    const int nc = (int)P.nc;
-    const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
-    for (int oz = -1; oz <= 1; ++oz) {
-        const int z = wrapc(cz + oz, nc);
-        for (int oy = -1; oy <= 1; ++oy) {
-            const int y = wrapc(cy + oy, nc);
-            const int rowbase = (z * nc + y) * nc;
-            for (int ox = -1; ox <= 1; ++ox) {
-                const int c = rowbase + wrapc(cx + ox, nc);
-                uint32_t m = cnt[c];
-                m = m < P.cellcap ? m : P.cellcap;
-                const uint32_t base = (uint32_t)c * P.cellcap;
-                for (uint32_t k = 0; k < m; ++k) {
-                    const float4 pj = cp[base + k];
-                    if (slot_index(pj) == i) continue;
-                    pair_force(P, D, pi, pj, ti, fx, fy, fz, e);
-                }
-            }
-        }
-    }
+    const uint32_t m = D.nl_cnt[i];
+    for (uint32_t k = 0; k < m; ++k) pair_force_xt(P, D, pi, X[D.nl[(size_t)k * P.n + i]], ti, fx, fy, fz, e);
     bond_forces(P, D, X, i, pi, ti, fx, fy, fz, e);
     return fix_to_force(D, fx, fy, fz);
 }
@@ -293,13 +275,29 @@ __global__ void k_bin(const Params P, const Dev D, int xin, int lst) {
     if (i < P.n) bin_particle(P, D, lst, i, D.x[xin][i]);
 }
 
+// Cell lists: lists 0 and 1 take turns holding the positions of the latest
+// neighbour-list build; rflag[3] names the one the next build bins into, which
+// is kept empty (the build clears the other one, and the step after a build
+// switches rflag[3] over).  List 2 serves the spatial renumbering.
+constexpr int kSortList = 2;
+
+// Binning for a neighbour-list build: does nothing unless the rebuild flag
+// `f3` is set (by the step that moved some particle by more than skin / 2,
+// or by a renumbering); then inserts every particle at X into cell list
+// rflag[3].  Steps that need no build pay only this launch, not the binning.
+__global__ void k_binr(const Params P, const Dev D, int xin, int f3) {
+    if (D.rflag[f3] == 0u) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) bin_particle(P, D, (int)D.rflag[3], i, D.x[xin][i]);
+}
+
 // Forces (and per-particle energies) at the current positions into f4[off + i].
-__global__ void k_eval(const Params P, const Dev D, int xin, int lst, uint32_t off) {
+__global__ void k_eval(const Params P, const Dev D, int xin, uint32_t off) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     const float4 pi = D.x[xin][i];
     double e = 0.0;
-    const Force3 f = force_on(P, D, D.x[xin], lst, i, pi, type_of(pi), &e);
+    const Force3 f = force_on(P, D, D.x[xin], i, pi, type_of(pi), &e);
     D.f4[off + i] = make_float4(f.x, f.y, f.z, (float)e);
 }
 
@@ -469,9 +467,11 @@ __device__ __forceinline__ void nl_consider(const Params& P, const Dev& D, const
 // Does nothing unless the rebuild flag `f3` (set by k_step when a particle
 // has moved by more than skin / 2, or by a renumbering) is set; the grid is
 // a few hundred workgroups, so that the launch is cheap when nothing moved
-// that far.
-__global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const Dev D, int lst, int f3) {
+// that far.  Reads cell list rflag[3] (filled by k_binr) and empties the
+// core cells of the other one, which the next build fills.
+__global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const Dev D, int f3) {
     if (D.rflag[f3] == 0u) return;
+    const int lst = (int)D.rflag[3];
     __shared__ float rl2[kMaxTypes * kMaxTypes];   // list radii, indexed by lane-varying type pairs
     __shared__ float4 ent[kTileMaxEntries];
     __shared__ uint32_t hoff[kTileMaxHalo + 1];
@@ -760,6 +760,12 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
         }
     }
     if (over) atomicOr(&D.err[0], kErrNlist);
+    // the other list's cells of this tile's core, for the next build
+    uint32_t* __restrict__ nxt = D.ccount[lst ^ 1];
+    for (int q = (int)tid; q < ex * ey * ez; q += kTileThreads) {
+        const int cz = q / (ex * ey), r = q - cz * ex * ey, cy = r / ex, cx = r - cy * ex;
+        nxt[((z0 + cz) * nc + (y0 + cy)) * nc + (x0 + cx)] = 0u;
+    }
 }
 
 // Copy the step tables (built on the host at commit, kept in device memory)
@@ -875,16 +881,24 @@ __device__ __forceinline__ void bond_force_tab(const Params& P, const StepTabs& 
 // split and the order do not change the result).
 //
 // Integration phase: the first 256 / TPP threads (whole waves) integrate the
-// workgroup's particles, one per thread (advance_particle), bin x_{t+1} into
-// `lnext`, and test the list: a particle farther than skin / 2 from where its
-// list was built sets the flag of step t+1, read by the k_nlist launched right
-// after.  The other waves have retired by then, so no lane idles through the
-// integration.
-//   xin = buffer of x_t, lnext = cell list receiving x_{t+1}, lclr = list
-//   cleared for the step after, sp = t mod 2, f3 = t mod 3.
+// workgroup's particles, one per thread (advance_particle), and test the
+// list: a particle farther than skin / 2 from where its list was built sets
+// the flag of step t+1, read by the k_binr and k_nlist launched right after
+// (which bin x_{t+1} and rebuild the lists only then).  The other waves have
+// retired by then, so no lane idles through the integration.
+//   xin = buffer of x_t, sp = t mod 2, f3 = t mod 3.
 //   QB (if not 0) = list entries per thread issued up front.
+// Thread 0 also retires the rebuild flag of step t (consumed by the k_nlist
+// of step t - 1), switching the cell list of the next build when it was set.
+__device__ __forceinline__ void retire_rebuild_flag(const Dev& D, int f3) {
+    if (D.rflag[f3]) {
+        D.rflag[3] ^= 1u;
+        D.rflag[f3] = 0u;
+    }
+}
+
 template <int TPP, int QB = 0, bool EXT = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_step(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_step(const Params P, const Dev D, int xin, int sp,
                                               int f3, int accum_ke) {
     static_assert(TPP >= 1 && TPP <= 64, "256 threads per workgroup");
     constexpr int PPB = 256 / TPP;                       // particles per workgroup
@@ -928,9 +942,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     const unsigned long long s = D.stepv[sp] + 1ull;
     if (gtid == 0) {
         D.stepv[sp ^ 1] = s;
-        D.rflag[f3] = 0u;               // consumed by the k_nlist of step t
+        retire_rebuild_flag(D, f3);
     }
-    for (uint32_t c = gtid; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
     __syncthreads();
     if (i < P.n) {
         const uint32_t ti = type_of(pi);
@@ -986,7 +999,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         const Force3 F = fix_to_force(D, (long long)fsum[0][tid], (long long)fsum[1][tid], (long long)fsum[2][tid]);
         float4 po;
         ke = advance_particle(P, T, D, xin, i2, p2, t2, F, u2, tag2, s, accum_ke, po);
-        bin_particle(P, D, lnext, i2, po);
         const float4 r = r2;
         const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
         if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[f3 == 2 ? 0 : f3 + 1] = 1u;
@@ -1005,7 +1017,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // on to the integration with its force in registers (no LDS reduction, one
 // barrier).  Same arguments and the same result bit for bit as k_step<TPP>.
 template <bool EXT = false>
-__global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int xin, int lnext, int lclr, int sp,
+__global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int xin, int sp,
                                                int f3, int accum_ke) {
     constexpr int Q = 4, BQ = 4;
     __shared__ StepTabs T;
@@ -1043,9 +1055,8 @@ __global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int 
     const unsigned long long s = D.stepv[sp] + 1ull;
     if (gtid == 0) {
         D.stepv[sp ^ 1] = s;
-        D.rflag[f3] = 0u;               // consumed by the k_nlist of step t
+        retire_rebuild_flag(D, f3);
     }
-    for (uint32_t c = gtid; c < P.ncell; c += gridDim.x * blockDim.x) D.ccount[lclr][c] = 0u;
     __syncthreads();
     unsigned long long ke = 0ull;
     if (live) {
@@ -1084,7 +1095,6 @@ __global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int 
         const Force3 F = fix_to_force(D, fx, fy, fz);
         float4 po;
         ke = advance_particle(P, T, D, xin, i, pi, ti, F, ui, tg, s, accum_ke, po);
-        bin_particle(P, D, lnext, i, po);
         const float dx = mi_delta_f(ri.x, po.x, P), dy = mi_delta_f(ri.y, po.y, P), dz = mi_delta_f(ri.z, po.z, P);
         if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[f3 == 2 ? 0 : f3 + 1] = 1u;
     }
@@ -1095,23 +1105,29 @@ __global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int 
 }
 
 // ------------------------------------------------------------ spatial sort
-// Particles are renumbered in cell order (cells in x-fastest order, slot order
-// inside a cell) so that the particles of a tile and their bond partners sit
-// close together in memory.  Nothing computed depends on the numbering: random
-// streams and tie-breaks use tags, sums are in fixed point.
+// Particles are renumbered in cell order (slot order inside a cell) so that
+// the particles of a tile and their bond partners sit close together in
+// memory.  Nothing computed depends on the numbering: random streams and
+// tie-breaks use tags, sums are in fixed point.
+// Cells are visited in Morton (Z-curve) order of their coordinates (table
+// D.corder, built at commit): any run of consecutive particles then fills a
+// compact block of space, so the neighbours a workgroup gathers, and the run
+// of workgroups one XCD takes, stay within few cache lines and one L2.
 // Buckets are (cell, type) in cell-major order: a cell's particles stay
 // together whatever their types, so bonded partners (of other types) and
 // neighbours sit next to each other in memory.  (Type-major order, every
 // type in a block of its own, made the step 3 % slower at 200k particles and
 // 6 % at 4 M: a particle's partners then lie in another block.)
-__device__ __forceinline__ void bucket_cell_type(const Params& P, uint32_t b, uint32_t& c, uint32_t& t) {
-    c = b / P.ntypes;
-    t = b - c * P.ntypes;
+__device__ __forceinline__ void bucket_cell_type(const Params& P, const Dev& D, uint32_t b, uint32_t& c,
+                                                 uint32_t& t) {
+    const uint32_t r = b / P.ntypes;
+    t = b - r * P.ntypes;
+    c = D.corder[r];
 }
 
 __device__ __forceinline__ uint32_t bucket_count(const Params& P, const Dev& D, int lst, uint32_t b) {
     uint32_t c, t;
-    bucket_cell_type(P, b, c, t);
+    bucket_cell_type(P, D, b, c, t);
     uint32_t m = D.ccount[lst][c];
     m = m < P.cellcap ? m : P.cellcap;
     const float4* cp = D.cpos[lst] + (size_t)c * P.cellcap;
@@ -1134,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_sort_assign(const Params P, const Dev D
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= P.ntypes * P.ncell) return;
     uint32_t c, t;
-    bucket_cell_type(P, b, c, t);
+    bucket_cell_type(P, D, b, c, t);
     uint32_t m = D.ccount[lst][c];
     m = m < P.cellcap ? m : P.cellcap;
     uint32_t at = D.cstart[b] + D.cbsum[blockIdx.x];
@@ -1169,7 +1185,10 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const Params P, const Dev 
 
 __global__ __launch_bounds__(256) void k_sort_copyback(const Params P, const Dev D, int xin, int f3) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) D.rflag[f3] = 1u;    // indices changed: the next step rebuilds the neighbour lists
+    if (i == 0) {                    // indices changed: rebuild the neighbour lists now
+        retire_rebuild_flag(D, f3);  // (a build that just ran leaves the other cell list empty)
+        D.rflag[f3] = 1u;
+    }
     if (i >= P.n) return;
     const size_t n = P.n;
     D.x[xin][i] = D.x_alt[i];

@@ -172,8 +172,9 @@ def db_set_type(h, t, valence, sigma, eps, mass):
 
 
 def db_set_particles(h, pos, vel, types):
+    """vel=None: Maxwell-Boltzmann velocities drawn by the library."""
     p, pp = _buf(pos, np.float32)
-    v, vp = _buf(vel, np.float32)
+    v, vp = (None, None) if vel is None else _buf(vel, np.float32)
     t, tp = _buf(types, np.uint32)
     _check(h, load().db_set_particles(h, pp, vp, tp))
 

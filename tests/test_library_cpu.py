@@ -250,3 +250,42 @@ def test_validation_errors_on_host():
     assert _status_of(lambda: db.db_create(10, 0, 5.0, 1)) == "DB_EINVAL"
     assert _status_of(lambda: db.db_create(10, 9, 5.0, 1)) == "DB_EINVAL"
     assert _status_of(lambda: db.db_create(10, 1, float("nan"), 1)) == "DB_EINVAL"
+
+
+def test_velocities_drawn_for_null_match_the_oracle_on_host():
+    """db_set_particles with vel3 = NULL: db_validate draws Maxwell-Boltzmann
+    velocities (set-point kT, zero momentum) from the INIT stream, readable
+    before db_commit without a GPU; they equal the oracle's draws rounded to
+    FP32, and their moments are those of the distribution."""
+    from helpers import oracle_from_workload
+    w = inputs.small(seed=5)
+    w.vel = None
+    w.types = [(1, 1.0, 1.0, 1.0), (1, 1.0, 1.0, 3.0)]      # unequal masses
+    s = db.System.from_workload(w, commit=False)
+    st = db.load().db_read_velocities(s.h, np.empty((w.n, 3), np.float32).ctypes.data_as(db._P))
+    assert st == db.DB_ESTATE                                # not drawn before validation
+    db.db_validate(s.h)
+    v = db.db_read_velocities(s.h, w.n).astype(np.float64)
+    pos = db.db_read_positions(s.h, w.n)
+    assert np.array_equal(pos, np.asarray(w.pos, np.float32))
+    o = oracle_from_workload(w)
+    assert np.allclose(v, o.v, rtol=2e-7, atol=1e-7)
+    m = np.where(w.type_id == 1, 3.0, 1.0)[:, None]
+    assert np.abs(np.sum(m * v, axis=0)).max() < 1e-4
+    ke = np.sum(m * v * v) / (3 * w.n)
+    assert abs(ke - w.kT) < 4.0 * math.sqrt(2.0 / (3 * w.n))
+    # the draw follows the set-point temperature given to the integrator
+    db.db_set_integrator(s.h, w.dt, 2.0 * w.kT, w.gamma, w.period)
+    db.db_validate(s.h)
+    v2 = db.db_read_velocities(s.h, w.n).astype(np.float64)
+    assert np.allclose(v2, math.sqrt(2.0) * v, rtol=1e-6, atol=1e-6)
+    s.close()
+
+
+def test_enum_arguments_are_checked():
+    w = inputs.small(seed=1)
+    s = db.System.from_workload(w, commit=False)
+    lib = db.load()
+    assert lib.db_add_bond_type(s.h, 7, 1.0, 1.0, None) == db.DB_EINVAL
+    assert lib.db_set_integrator(s.h, 0.005, 1.0, 1.0, 10, 2) == db.DB_EINVAL
+    s.close()
