@@ -3,7 +3,8 @@
  *
  * One time step (db_step) of a periodic, cubic, coarse-grained particle system:
  *   - Langevin integration (BAOAB) of positions and velocities;
- *   - a cell-list neighbour structure rebuilt every step;
+ *   - a neighbour list with a skin, rebuilt from a cell list on the steps
+ *     after which some particle has moved by more than half the skin;
  *   - WCA pair forces on all pairs plus harmonic / FENE bond forces;
  *   - every `sweep_period` steps, a bonding sweep that forms and breaks
  *     dynamic bonds between partner species under per-site valence caps,
@@ -247,8 +248,10 @@ DB_API db_status db_set_matching(db_system* sys, uint32_t grid_rounds, uint32_t 
  * automatic: 4 in the step kernel, or more for small systems so that a
  * launch fills the GPU, and half that in the proposal kernel) and, with 4
  * threads per particle, how many neighbour-list entries each thread loads
- * before its first gather (1, 2 or 4; 0 = automatic: 4; longer lists are
- * then taken in further rounds).  Any shape gives the same result bit for
+ * before its first gather (1, 2 or 4; 0 = automatic: 1; the next three
+ * entries per thread of a longer list are loaded with the first gathers,
+ * where the list has them, and any beyond in further rounds).  Any shape
+ * gives the same result bit for
  * bit (forces are summed exactly); it changes only the speed.  May be
  * called before or after db_commit.  Errors: DB_EINVAL, DB_EDEVICE. */
 DB_API db_status db_set_step_shape(db_system* sys, uint32_t threads_per_particle, uint32_t list_batch);
@@ -464,6 +467,14 @@ DB_API db_status db_cluster_sizes(db_system* sys, uint64_t* hist, uint32_t len, 
 DB_API db_status db_read_positions_device(db_system* sys, float* dev_pos3, void* hip_stream);
 DB_API db_status db_read_velocities_device(db_system* sys, float* dev_vel3, void* hip_stream);
 DB_API db_status db_read_forces_device(db_system* sys, float* dev_force3, void* hip_stream);
+
+/* Number of neighbour-list builds the system's steps have made since
+ * db_commit (its initial build included; a build runs after every step that
+ * moved some particle by more than half the skin, and after every spatial
+ * renumbering; batched steps are not counted): the rebuild rate that the
+ * list's cost is spread over.  Synchronous.  Errors: DB_EINVAL (builds
+ * NULL), DB_ESTATE, DB_EDEVICE. */
+DB_API db_status db_read_list_builds(db_system* sys, uint64_t* builds);
 
 /* Current step counter (host mirror). */
 DB_API uint64_t db_get_step(const db_system* sys);

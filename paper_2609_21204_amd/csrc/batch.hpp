@@ -142,7 +142,7 @@ __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T
     }
     if (m > P.nlmax) atomicOr(&D.err[0], kErrNlist);
     D.nl_cnt[i] = m < P.nlmax ? m : P.nlmax;
-    D.xref[i] = pi;
+    D.xref[i] = xref_pack(P, pi);
 }
 
 // n steps of system blockIdx.x.  Per step, as db_step: forces at x_t + BAOAB
@@ -184,14 +184,12 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
         for (uint32_t i = tid; i < n; i += bs) {
             const float4 pi = X[i];
             const float4 ui = D.u[i];
-            const uint32_t tg = D.tag[i];
-            const float4 r = D.xref[i];
+            const uint2 r = D.xref[i];
             const Force3 F = force_site<EXT>(P, T, D, X, i, pi);
             float4 po;
-            ke += advance_particle(P, T, D, xin, i, pi, type_of(pi), F, ui, tg, s, ake, po);
+            ke += advance_particle(P, T, D, xin, i, pi, type_of(pi), F, ui, __float_as_uint(ui.w), s, ake, po);
             bin_particle_wg(P, D, lnext, i, po);
-            const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
-            if (dx * dx + dy * dy + dz * dz > P.disp2) flag[k % 3] = 1u;
+            if (moved_past_skin(P, r, po)) flag[k % 3] = 1u;
         }
         if (ake) {
             for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);

@@ -125,7 +125,8 @@ struct Params {
     uint32_t tpp_step;                 // threads per particle in k_step
     uint32_t qb_step;                  // list entries per thread issued up front in k_step (0: by TPP)
     uint32_t ext;                      // tether bonds or rate modifiers present: kernels in their full variant
-    float disp2;                       // (skin / 2 - 1e-4)^2: displacement that triggers a rebuild
+    float disp2;                       // (skin / 2 - 1e-4 - packing error of xref)^2: displacement that triggers a rebuild
+    float xq, xqinv;                   // 2^21 / L and L / 2^21: the 21-bit grid of the packed build positions
     uint32_t nlmax;                    // neighbour-list slots per particle
     uint32_t evcap[2];                 // capacity of the formed / broken event lists of a sweep
     double kT;
@@ -215,9 +216,10 @@ struct Dev {
     uint32_t* parent;      // union-find parents (cluster observable)
     uint32_t* nl;          // nlmax x n neighbour indices (slot-major)
     uint32_t* nl_cnt;      // neighbours per particle
-    float4* xref;          // positions at the last neighbour-list build
+    uint2* xref;           // positions at the last neighbour-list build, 21 bits per axis (xref_pack)
     uint32_t* rflag;       // neighbour-list rebuild flags of steps t, t+1, t+2 (index step mod 3);
-                           // [3]: the cell list (0 or 1) the next build bins into
+                           // [3]: the cell list (0 or 1) the next build bins into;
+                           // [4]: neighbour-list builds by db_step since commit
     uint32_t* corder;      // cells in Morton order (the renumbering's cell sequence)
     // spatial reordering (counting sort by cell): new index of every particle,
     // cell offsets, and second copies of every per-particle array
@@ -282,6 +284,31 @@ __device__ __forceinline__ float mi_delta_f(float xi, float xj, const Params& P)
     float d = xj - xi;
     if (fabsf(d) > P.halfLf) d -= P.Lf * rintf(d * (1.0f / P.Lf));
     return d;
+}
+
+// Position at the last neighbour-list build, kept only for the rebuild test:
+// each coordinate as a 21-bit cell index of a grid of spacing L / 2^21 over
+// [-L/2, L/2), the three packed into 63 bits (8 bytes instead of 16).
+__device__ __forceinline__ uint2 xref_pack(const Params& P, float4 p) {
+    auto q = [&](float x) {
+        const int v = (int)((x + P.halfLf) * P.xq);
+        return (unsigned long long)(v < 0 ? 0 : (v > 0x1FFFFF ? 0x1FFFFF : v));
+    };
+    const unsigned long long b = q(p.x) | (q(p.y) << 21) | (q(p.z) << 42);
+    return make_uint2((uint32_t)b, (uint32_t)(b >> 32));
+}
+
+// Has the particle at p moved farther than skin / 2 from its packed build
+// position r?  The grid point is the centre of r's grid cell, at most
+// sqrt(3) L / 2^22 (plus FP32 rounding) from where the list was built; the
+// host takes that off the threshold disp2, so a true displacement beyond
+// skin / 2 always triggers (a rebuild may come slightly early, which changes
+// nothing computed: the lists only have to contain every pair in range).
+__device__ __forceinline__ bool moved_past_skin(const Params& P, uint2 r, float4 p) {
+    const unsigned long long b = (unsigned long long)r.x | ((unsigned long long)r.y << 32);
+    auto c = [&](unsigned long long v) { return ((float)(v & 0x1FFFFFull) + 0.5f) * P.xqinv - P.halfLf; };
+    const float dx = mi_delta_f(c(b), p.x, P), dy = mi_delta_f(c(b >> 21), p.y, P), dz = mi_delta_f(c(b >> 42), p.z, P);
+    return dx * dx + dy * dy + dz * dz > P.disp2;
 }
 
 // Event counters (attempts, forms, breaks per reaction) are spread over

@@ -629,7 +629,13 @@ void fill_params(db_system* s) {
     P.tpp_step = s->tpp_user ? s->tpp_user : auto_tpp(s->n);
     P.tpp = s->tpp_user ? s->tpp_user : std::max(1u, auto_tpp(s->n) / 2);
     P.qb_step = P.tpp_step == 4 ? s->qb_user : 0u;
-    P.disp2 = (float)std::max(0.0, (0.5 * skin - 1e-4) * (0.5 * skin - 1e-4));
+    // build positions are packed to a 21-bit grid (xref_pack): the test takes
+    // the grid's half spacing and the FP32 rounding of its decoding off skin / 2
+    P.xq = (float)(2097152.0 / s->L);
+    P.xqinv = (float)(s->L / 2097152.0);
+    const double qerr = std::sqrt(3.0) * (s->L / 4194304.0 + s->L * 0x1.0p-22) * 1.01;
+    const double thr = std::max(0.0, 0.5 * skin - 1e-4 - qerr);
+    P.disp2 = (float)(thr * thr);
     // neighbour slots: room for 2.5x the mean count of an ideal gas at this
     // density plus 32, at least 64 (or exactly what the caller asked for)
     const double mean_nb = 4.18879020478639 * rlist * rlist * rlist * (double)s->n / (s->L * s->L * s->L);
@@ -669,7 +675,9 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
         const uint32_t ty = s->type[t];
         std::memcpy(&tb, &ty, 4);
         xs[i] = make_float4(pos3[3 * t], pos3[3 * t + 1], pos3[3 * t + 2], tb);
-        vs[i] = make_float4(vel3[3 * t], vel3[3 * t + 1], vel3[3 * t + 2], 0.f);
+        float tg;                          // the tag rides in u's w word
+        std::memcpy(&tg, &t, 4);
+        vs[i] = make_float4(vel3[3 * t], vel3[3 * t + 1], vel3[3 * t + 2], tg);
     }
     std::vector<uint32_t> dyn((size_t)P.cap_max * n, kEmpty);
     std::vector<uint8_t> occ(n, 0);
@@ -823,8 +831,8 @@ void launch_step(db_system* s) {
             case 1: STEP_AS(k_step1<true>); break;
             case 2: STEP_AS(k_step<2, 0, true>); break;
             case 4:
-                if (P.qb_step == 1) STEP_AS(k_step<4, 1, true>);
-                else if (P.qb_step == 2) STEP_AS(k_step<4, 2, true>);
+                if (P.qb_step == 2) STEP_AS(k_step<4, 2, true>);
+                else if (P.qb_step == 4) STEP_AS(k_step<4, 4, true>);
                 else STEP_AS(k_step<4, 0, true>);
                 break;
             case 8: STEP_AS(k_step<8, 0, true>); break;
@@ -836,8 +844,8 @@ void launch_step(db_system* s) {
             case 1: STEP_AS(k_step1<false>); break;
             case 2: STEP_AS(k_step<2, 0, false>); break;
             case 4:
-                if (P.qb_step == 1) STEP_AS(k_step<4, 1, false>);
-                else if (P.qb_step == 2) STEP_AS(k_step<4, 2, false>);
+                if (P.qb_step == 2) STEP_AS(k_step<4, 2, false>);
+                else if (P.qb_step == 4) STEP_AS(k_step<4, 4, false>);
                 else STEP_AS(k_step<4, 0, false>);
                 break;
             case 8: STEP_AS(k_step<8, 0, false>); break;
@@ -1245,7 +1253,7 @@ db_status db_set_step_shape(db_system* s, uint32_t tpp, uint32_t list_batch) {
 db_status db_get_step_shape(const db_system* s, uint32_t* tpp, uint32_t* list_batch) {
     if (!s || !tpp || !list_batch) return DB_EINVAL;
     *tpp = s->committed ? s->P.tpp_step : s->tpp_user;
-    *list_batch = s->committed ? (s->P.qb_step ? s->P.qb_step : (s->P.tpp_step < 4 ? 4u : std::max(1u, 16u / s->P.tpp_step)))
+    *list_batch = s->committed ? (s->P.qb_step ? s->P.qb_step : (s->P.tpp_step == 1 ? 4u : std::max(1u, 4u / s->P.tpp_step)))
                                : s->qb_user;
     return DB_OK;
 }
@@ -1354,7 +1362,8 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.nl, (size_t)P.nlmax * n);
     DALLOC(s, D.nl_cnt, n);
     DALLOC(s, D.xref, n);
-    DALLOC(s, D.rflag, 4);
+    DALLOC(s, D.rflag, 8);
+    HIPCHK(s, hipMemsetAsync(D.rflag, 0, 8 * sizeof(uint32_t), s->stream));
     DALLOC(s, D.corder, P.ncell);
     DALLOC(s, D.newidx, n);
     DALLOC(s, D.cstart, (size_t)P.ncell * P.ntypes + 1);
@@ -2090,6 +2099,18 @@ db_status db_read_observables(db_system* s, db_observables* out) {
 }
 
 uint64_t db_get_step(const db_system* s) { return s ? s->step : 0; }
+
+db_status db_read_list_builds(db_system* s, uint64_t* builds) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!builds) return fail(s, DB_EINVAL, "builds is NULL");
+    HIPCHK(s, hipSetDevice(s->device));
+    uint32_t c = 0;
+    HIPCHK(s, hipMemcpyAsync(&c, s->D.rflag + 4, 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *builds = c;
+    return DB_OK;
+}
 
 const char* db_last_error(const db_system* s) { return s ? s->err.c_str() : g_create_error.c_str(); }
 

@@ -369,8 +369,9 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
 // Rest of one BAOAB step for particle i once its force F at x_t is known:
 // closing half kick of step t-1 (B), opening half kick (B), half drift (A),
 // Ornstein-Uhlenbeck velocity update with Philox Gaussians (O), half drift
-// (A), wrap into [-L/2, L/2), then write x_{t+1} (returned in po; the caller
-// bins it).  Returns m v^2 in 2^-32 fixed point when accum_ke is set.
+// (A), wrap into [-L/2, L/2), then write x_{t+1} (returned in po) and u
+// (with the particle's tag in its w word, where the next step reads it).
+// Returns m v^2 in 2^-32 fixed point when accum_ke is set.
 template <class Tabs>
 __device__ __forceinline__ unsigned long long advance_particle(const Params& P, const Tabs& T, const Dev& D, int xin,
                                                                uint32_t i, float4 pi, uint32_t ti,
@@ -416,7 +417,7 @@ __device__ __forceinline__ unsigned long long advance_particle(const Params& P, 
     }
     po = make_float4(x, y, z, __uint_as_float(ti));
     D.x[xin ^ 1][i] = po;
-    D.u[i] = make_float4(vx, vy, vz, 0.0f);
+    D.u[i] = make_float4(vx, vy, vz, __uint_as_float(tag));   // the tag rides in the w word
     if (!accum_ke) return 0ull;
     const double v2 = ((double)vx * vx + (double)vy * vy) + (double)vz * vz;
     return (unsigned long long)rint((double)T.mass[ti] * v2 * 4294967296.0);
@@ -472,6 +473,7 @@ __device__ __forceinline__ void nl_consider(const Params& P, const Dev& D, const
 __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const Dev D, int f3) {
     if (D.rflag[f3] == 0u) return;
     const int lst = (int)D.rflag[3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&D.rflag[4], 1u);   // builds so far
     __shared__ float rl2[kMaxTypes * kMaxTypes];   // list radii, indexed by lane-varying type pairs
     __shared__ float4 ent[kTileMaxEntries];
     __shared__ uint32_t hoff[kTileMaxHalo + 1];
@@ -700,7 +702,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
                 const uint32_t m = pcnt[q];
                 over |= m > P.nlmax;
                 D.nl_cnt[slot_index(pi)] = m < P.nlmax ? m : P.nlmax;
-                D.xref[slot_index(pi)] = pi;
+                D.xref[slot_index(pi)] = xref_pack(P, pi);
             }
         } else {
             for (uint32_t q = tid; q < ncore; q += kTileThreads) {
@@ -729,7 +731,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
                 }
                 over |= m > P.nlmax;
                 D.nl_cnt[i] = m < P.nlmax ? m : P.nlmax;
-                D.xref[i] = pi;
+                D.xref[i] = xref_pack(P, pi);
             }
         }
     } else {
@@ -755,7 +757,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
                         }
                 over |= m > P.nlmax;
                 D.nl_cnt[i] = m < P.nlmax ? m : P.nlmax;
-                D.xref[i] = pi;
+                D.xref[i] = xref_pack(P, pi);
             }
         }
     }
@@ -903,7 +905,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     static_assert(TPP >= 1 && TPP <= 64, "256 threads per workgroup");
     constexpr int PPB = 256 / TPP;                       // particles per workgroup
     constexpr uint32_t kIntThreads = PPB > 64 ? PPB : 64;   // whole waves that integrate
-    constexpr int Q = QB ? QB : (TPP < 4 ? 4 : (16 / TPP > 1 ? 16 / TPP : 1));   // list entries per thread issued up front
+    constexpr int Q = QB ? QB : (4 / TPP > 1 ? 4 / TPP : 1);   // list entries per thread issued up front
+    constexpr int QX = 8 / TPP > 1 ? 8 / TPP : 1;              // further entries per thread, issued with the gathers
     constexpr int BQ = 8 / TPP > 1 ? 8 / TPP : 1;       // bond slots per thread issued up front
     __shared__ StepTabs T;
     __shared__ unsigned long long fsum[3][PPB];
@@ -955,14 +958,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         for (int q = 0; q < Q; ++q) pj[q] = X[lane + (uint32_t)q * TPP < m ? nb[q] : i];
 #pragma unroll
         for (int q = 0; q < BQ; ++q) pb[q] = X[bw[q] != kEmpty ? (bw[q] & kIdxMask) : i];
+        // list rows past the first Q per thread, only where the list has them
+        uint32_t nx[QX];
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const uint32_t k = lane + (uint32_t)(Q + q) * TPP;
+            nx[q] = k < m ? D.nl[k * n + i] : i;
+        }
         long long fx = 0, fy = 0, fz = 0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const uint32_t k = lane + (uint32_t)q * TPP;
             if (k < m) pair_force_tab(P, T, D.err, pi, pj[q], ti, fx, fy, fz);
         }
-        for (uint32_t k = lane + (uint32_t)Q * TPP; k < m; k += TPP)
-            pair_force_tab(P, T, D.err, pi, X[D.nl[k * n + i]], ti, fx, fy, fz);
+        // longer lists (a few particles per wave): their next entries were
+        // loaded together with the first gathers, their positions now
+        if (m > (uint32_t)(Q * TPP)) {
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                const uint32_t k = lane + (uint32_t)(Q + q) * TPP;
+                if (k < m) pair_force_tab(P, T, D.err, pi, X[nx[q]], ti, fx, fy, fz);
+            }
+            for (uint32_t k = lane + (uint32_t)(Q + QX) * TPP; k < m; k += TPP)
+                pair_force_tab(P, T, D.err, pi, X[D.nl[k * n + i]], ti, fx, fy, fz);
+        }
         auto bond = [&](uint32_t b, uint32_t w, float4 pw) {
             const uint32_t j = w & kIdxMask;
             if (b < P.stat_max) bond_force_tab<EXT>(P, T, D, pi, pw, w >> 24, i, j, fx, fy, fz);
@@ -983,13 +1002,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     // the integrating wave fetches its particles' state before the barrier
     const uint32_t i2 = base + tid;
     const bool own = tid < (uint32_t)PPB && i2 < P.n;
-    float4 p2 = make_float4(0.f, 0.f, 0.f, 0.f), u2 = p2, r2 = p2;
-    uint32_t tag2 = 0;
+    float4 p2 = make_float4(0.f, 0.f, 0.f, 0.f), u2 = p2;
+    uint2 r2 = make_uint2(0u, 0u);
     if (own) {
         p2 = X[i2];
         u2 = D.u[i2];
         r2 = D.xref[i2];
-        tag2 = D.tag[i2];
     }
     __syncthreads();
     if (tid >= kIntThreads) return;
@@ -998,10 +1016,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         const uint32_t t2 = type_of(p2);
         const Force3 F = fix_to_force(D, (long long)fsum[0][tid], (long long)fsum[1][tid], (long long)fsum[2][tid]);
         float4 po;
-        ke = advance_particle(P, T, D, xin, i2, p2, t2, F, u2, tag2, s, accum_ke, po);
-        const float4 r = r2;
-        const float dx = mi_delta_f(r.x, po.x, P), dy = mi_delta_f(r.y, po.y, P), dz = mi_delta_f(r.z, po.z, P);
-        if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[f3 == 2 ? 0 : f3 + 1] = 1u;
+        ke = advance_particle(P, T, D, xin, i2, p2, t2, F, u2, __float_as_uint(u2.w), s, accum_ke, po);
+        if (moved_past_skin(P, r2, po)) D.rflag[f3 == 2 ? 0 : f3 + 1] = 1u;
     }
     if (accum_ke) {
         for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
@@ -1028,8 +1044,9 @@ __global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int 
     const float4* __restrict__ X = D.x[xin];
     const uint32_t nslot = P.stat_max + P.cap_max;
     const bool live = i < P.n;
-    float4 pi = make_float4(0.f, 0.f, 0.f, 0.f), ui = pi, ri = pi;
-    uint32_t tg = 0, m = 0;
+    float4 pi = make_float4(0.f, 0.f, 0.f, 0.f), ui = pi;
+    uint2 ri = make_uint2(0u, 0u);
+    uint32_t m = 0;
     uint32_t nb[Q], bw[BQ];
 #pragma unroll
     for (int q = 0; q < Q; ++q) nb[q] = 0u;
@@ -1039,7 +1056,6 @@ __global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int 
         pi = X[i];
         ui = D.u[i];
         ri = D.xref[i];
-        tg = D.tag[i];
         m = D.nl_cnt[i];
 #pragma unroll
         for (int q = 0; q < Q; ++q)
@@ -1094,9 +1110,8 @@ __global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int 
         }
         const Force3 F = fix_to_force(D, fx, fy, fz);
         float4 po;
-        ke = advance_particle(P, T, D, xin, i, pi, ti, F, ui, tg, s, accum_ke, po);
-        const float dx = mi_delta_f(ri.x, po.x, P), dy = mi_delta_f(ri.y, po.y, P), dz = mi_delta_f(ri.z, po.z, P);
-        if (dx * dx + dy * dy + dz * dz > P.disp2) D.rflag[f3 == 2 ? 0 : f3 + 1] = 1u;
+        ke = advance_particle(P, T, D, xin, i, pi, ti, F, ui, __float_as_uint(ui.w), s, accum_ke, po);
+        if (moved_past_skin(P, ri, po)) D.rflag[f3 == 2 ? 0 : f3 + 1] = 1u;
     }
     if (accum_ke) {
         for (int off = 32; off >= 1; off >>= 1) ke += __shfl_xor(ke, off, 64);
@@ -1790,15 +1805,6 @@ __global__ __launch_bounds__(256) void k_break(const Params P, const Dev D, int 
 }
 
 // ------------------------------------------------------------ I/O kernels
-// Scatter tag-ordered staging float4 into index order.
-__global__ void k_scatter_pos(const Params P, const Dev D, const float4* __restrict__ stage, int xdst) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < P.n) D.x[xdst][D.rtag[t]] = stage[t];
-}
-__global__ void k_scatter_vel(const Params P, const Dev D, const float4* __restrict__ stage) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < P.n) D.u[D.rtag[t]] = stage[t];
-}
 // Gather index-ordered float4 (positions, u, or f4 + h F/m) into tag order.
 // mode 0: positions, 1: full-step velocities (u + h F/m, F in f4), 2: forces (f4)
 __global__ void k_gather(const Params P, const Dev D, float4* __restrict__ out, int xin, int mode) {

@@ -109,6 +109,7 @@ _SIGS = {
     "db_read_velocities_device": (_I, [_P, _P, _P]),
     "db_read_forces_device": (_I, [_P, _P, _P]),
     "db_get_step": (_U64, [_P]),
+    "db_read_list_builds": (_I, [_P, ctypes.POINTER(_U64)]),
     "db_last_error": (ctypes.c_char_p, [_P]),
     "db_set_stream": (_I, [_P, _P]),
     "db_kernel_timing": (_I, [_P, _I]),
@@ -461,6 +462,12 @@ def db_read_velocities_device(h, dev_ptr, stream=None):
 
 def db_read_forces_device(h, dev_ptr, stream=None):
     _check(h, load().db_read_forces_device(h, dev_ptr, stream))
+
+
+def db_read_list_builds(h):
+    c = _U64()
+    _check(h, load().db_read_list_builds(h, ctypes.byref(c)))
+    return c.value
 
 
 def db_get_step(h):
