@@ -399,6 +399,21 @@ DB_API db_status db_read_forces(db_system* sys, float* force3);
 DB_API db_status db_read_bonds(db_system* sys, uint32_t* tag_pairs, uint32_t* bond_types,
                         uint64_t cap, uint64_t* count);
 
+/* db_read_bonds for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same result and conventions as db_read_bonds, but the device staging
+ * of the sorted table goes through one fixed array the library holds on
+ * each device until the process ends (12 MiB: DB_NOALLOC_BONDS_MAX bonds),
+ * so the call makes no device allocation and frees nothing.  Every call on
+ * a device shares that device's array: calls that overlap on one device (on
+ * several handles or threads at once) race and must not be made.  Errors:
+ * as db_read_bonds, plus DB_ENOMEM when the system holds more than
+ * DB_NOALLOC_BONDS_MAX bonds (*count receives their number; read them with
+ * db_read_bonds). */
+#define DB_NOALLOC_BONDS_MAX (1u << 20)
+DB_API db_status db_read_bonds_noalloc(db_system* sys, uint32_t* tag_pairs, uint32_t* bond_types,
+                                       uint64_t cap, uint64_t* count);
+
 /* Bonds formed and broken by the most recent bonding sweep (Sec. 2.3: the
  * formation pass of each reaction, then the breaking of the bonds of that
  * reaction present when the sweep began), recorded on the device while the

@@ -21,6 +21,14 @@
 #include "kernels.hpp"
 #include "batch.hpp"
 
+// Staging array of db_read_bonds_noalloc: the bond table as kNoAllocBonds
+// tag pairs followed by kNoAllocBonds bond types (12 MiB).  Each device the
+// library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns for that
+// device (scratch_on), never through the name.
+constexpr uint32_t kNoAllocBonds = 1u << 20;
+static __device__ __align__(256) uint32_t scratch[3 * kNoAllocBonds];
+
 using namespace dyb;
 
 namespace {
@@ -1914,6 +1922,53 @@ db_status db_read_bonds(db_system* s, uint32_t* pairs, uint32_t* bts, uint64_t c
     HIPCHK(s, hipMemcpyAsync(bts, db, (size_t)total * 4, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipFreeAsync(dp, s->stream));
     HIPCHK(s, hipFreeAsync(db, s->stream));
+    return check_errors(s);
+}
+
+// Device address of `scratch` on each device, looked up once per device
+// (with that device current) on the first db_read_bonds_noalloc call there.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch[kMaxDevices] = {};
+
+static db_status scratch_on(db_system* s, uint32_t** out) {
+    if (s->device < 0 || s->device >= kMaxDevices) return fail(s, DB_EDEVICE, "device %d out of range", s->device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[s->device]) {
+        void* p = nullptr;
+        HIPCHK(s, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch[s->device] = (uint32_t*)p;
+    }
+    *out = g_scratch[s->device];
+    return DB_OK;
+}
+
+db_status db_read_bonds_noalloc(db_system* s, uint32_t* pairs, uint32_t* bts, uint64_t cap, uint64_t* count) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!count) return fail(s, DB_EINVAL, "count is NULL");
+    HIPCHK(s, hipSetDevice(s->device));
+    uint32_t* sp = nullptr;
+    st = scratch_on(s, &sp);
+    if (st != DB_OK) return st;
+    const unsigned nb = grid_of(s->n);
+    LAUNCH(s, k_rows_count, nb, kBlock, s->P, s->D, s->cur_x, s->bsum);
+    LAUNCH(s, k_scan_bsum, 1, 1024, s->bsum, nb);
+    uint32_t total = 0;
+    HIPCHK(s, hipMemcpyAsync(&total, s->bsum + nb, 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *count = total;
+    if (total > cap) return fail(s, DB_ETRUNC, "%u bonds, capacity %llu", total, (unsigned long long)cap);
+    if (total > kNoAllocBonds)
+        return fail(s, DB_ENOMEM, "%u bonds exceed the %u of the fixed staging array (use db_read_bonds)", total,
+                    kNoAllocBonds);
+    if (total == 0) return DB_OK;
+    if (!pairs || !bts) return fail(s, DB_EINVAL, "NULL output arrays");
+    uint32_t* const dp = sp;                      // tag pairs
+    uint32_t* const dt = sp + 2 * (size_t)kNoAllocBonds;   // bond types
+    LAUNCH(s, k_rows_emit, nb, kBlock, s->P, s->D, s->cur_x, s->bsum, dp, dt);
+    HIPCHK(s, hipMemcpyAsync(pairs, dp, (size_t)total * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(bts, dt, (size_t)total * 4, hipMemcpyDeviceToHost, s->stream));
     return check_errors(s);
 }
 

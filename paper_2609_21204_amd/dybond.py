@@ -99,6 +99,7 @@ _SIGS = {
     "db_read_velocities": (_I, [_P, _P]),
     "db_read_forces": (_I, [_P, _P]),
     "db_read_bonds": (_I, [_P, _P, _P, _U64, ctypes.POINTER(_U64)]),
+    "db_read_bonds_noalloc": (_I, [_P, _P, _P, _U64, ctypes.POINTER(_U64)]),
     "db_read_sweep_events": (_I, [_P, ctypes.c_int, _P, _P, _U64, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "db_read_observables": (_I, [_P, ctypes.POINTER(Observables)]),
     "db_bond_reference": (_I, [_P]),
@@ -378,19 +379,28 @@ def db_read_forces(h, n):
     return f
 
 
-def db_read_bonds(h):
-    """Dynamic bonds as an (m, 3) uint32 array (tag_lo, tag_hi, bond_type)."""
+def _read_bond_table(h, fn):
     cnt = _U64()
-    st = load().db_read_bonds(h, None, None, 0, ctypes.byref(cnt))
+    st = fn(h, None, None, 0, ctypes.byref(cnt))
     if st not in (DB_OK, DB_ETRUNC):
         _check(h, st)
     m = cnt.value
     pairs = np.empty((m, 2), np.uint32)
     bts = np.empty(m, np.uint32)
     if m:
-        _check(h, load().db_read_bonds(h, pairs.ctypes.data_as(_P), bts.ctypes.data_as(_P), m,
-                                       ctypes.byref(cnt)))
+        _check(h, fn(h, pairs.ctypes.data_as(_P), bts.ctypes.data_as(_P), m, ctypes.byref(cnt)))
     return np.concatenate([pairs, bts[:, None]], axis=1).reshape(-1, 3)
+
+
+def db_read_bonds(h):
+    """Dynamic bonds as an (m, 3) uint32 array (tag_lo, tag_hi, bond_type)."""
+    return _read_bond_table(h, load().db_read_bonds)
+
+
+def db_read_bonds_noalloc(h):
+    """db_read_bonds through the library's fixed device staging array (no
+    device allocation inside the call)."""
+    return _read_bond_table(h, load().db_read_bonds_noalloc)
 
 
 def db_read_sweep_events(h, which):
