@@ -82,14 +82,33 @@ def _workload(p, k):
                           p.kind, kT=float(p.kT[k]))
 
 
-def simulate(points, steps=20000, samples=5, plain=False, chunk=1024, device=0, log=None):
+SEED_STRIDE = 100_003     # replica seeds of one point: seed, seed + stride, ...
+
+
+def replicas_of(points, seeds):
+    """Each point repeated `seeds` times with seeds seed + j * SEED_STRIDE
+    (same parameters and N, other initial state and noise); replica
+    j * len(points) + k is seed j of point k."""
+    if seeds == 1:
+        return points
+    idx = np.tile(np.arange(len(points)), seeds)
+    rep = points.take(idx)
+    rep.seed = rep.seed + np.repeat(np.arange(seeds, dtype=np.int64), len(points)) * SEED_STRIDE
+    return rep
+
+
+def simulate(points, steps=20000, samples=5, plain=False, chunk=1024, device=0, log=None, seeds=1):
     """Observables of every point: (len(points), 2) end-of-run averages of
     (bonded fraction, largest-cluster fraction) over `samples` equally spaced
-    reads in the last quarter of a `steps`-step run.
+    reads in the last quarter of a `steps`-step run, averaged over `seeds`
+    replicas of the point (replicas_of), which run in the same batches.
 
     plain=False runs each chunk of replicas together (db_step_batch);
     plain=True runs every replica on its own with db_step.  Both give the
     same trajectory bit for bit, so they differ only in time."""
+    if seeds > 1:
+        per = simulate(replicas_of(points, seeds), steps, samples, plain, chunk, device, log)
+        return per.reshape(seeds, len(points), 2).mean(axis=0)
     span = (steps // 4) // samples
     if span < 1:
         raise ValueError("steps must be at least 4 * samples")
@@ -208,24 +227,30 @@ def hit_rate(values, target=0.5, band=0.1):
 
 def run_workflow(train_replicas=20480, steps=20000, samples=5, points=256, kinds=("chains", "mono"),
                  n_range=N_RANGE, epochs=400, batch=256, pool=65536, uniform_plain=True, seed=1, device=0,
-                 log=print):
+                 log=print, seeds=4, judge_batched=True):
     """Train one network per kind on simulated replicas (equal shares of
-    train_replicas, one in ten held out), then let the first kind's network
-    choose `points` new points near the percolation line and judge each by
-    a plain run.  The uniform sweep it is compared with is `points` uniform
-    points run the plain way (uniform_plain) or else the uniform training
-    replicas themselves (same distribution, batched runs equal plain ones)."""
+    train_replicas, `seeds` replicas per sweep point averaged into its label,
+    one point in ten held out), then let the first kind's network choose
+    `points` new points near the percolation line and judge each by the
+    simulation (the same `seeds` replicas per point, batched when
+    judge_batched: batched runs equal db_step runs bit for bit, so this is
+    the plain method, only faster).  A second, disjoint set of `seeds`
+    replicas of the chosen points gives the noise floor of a label: the
+    spread of two such averages, over sqrt(2) for one of them.  The uniform
+    sweep the chosen points are compared with is `points` uniform points run
+    the same way (uniform_plain) or else the uniform training points."""
     rng = np.random.default_rng(seed)
-    report = {"train_replicas": train_replicas, "steps": steps, "samples": samples, "points": points,
-              "n_range": list(n_range), "epochs": epochs}
+    report = {"train_replicas": train_replicas, "seeds_per_point": seeds, "steps": steps, "samples": samples,
+              "points": points, "n_range": list(n_range), "epochs": epochs}
+    plain_run = not judge_batched
     nets = {}
     uniform_lc = None
     try:
         for ki, kind in enumerate(kinds):
-            count = train_replicas // len(kinds)
+            count = train_replicas // len(kinds) // seeds
             pts = draw_points(rng, count, kind, n_range, seed_base=(seed * 10 + ki) * 1_000_000)
             t0 = time.perf_counter()
-            tgt = simulate(pts, steps, samples, device=device, log=log)
+            tgt = simulate(pts, steps, samples, device=device, log=log, seeds=seeds)
             t_sim = time.perf_counter() - t0
             hold = np.arange(count) % 10 == 0
             net = Surrogate(seed=seed + ki, device=device)
@@ -234,7 +259,8 @@ def run_workflow(train_replicas=20480, steps=20000, samples=5, points=256, kinds
             loss = net.fit(pts.take(~hold), tgt[~hold], epochs=epochs, batch=batch, seed=seed)
             t_fit = time.perf_counter() - t0
             err = np.abs(net.predict(pts.take(hold)) - tgt[hold])
-            report[kind] = {"replicas": count, "simulate_s": t_sim, "train_s": t_fit, "train_loss": loss,
+            report[kind] = {"points": count, "replicas": count * seeds, "simulate_s": t_sim, "train_s": t_fit,
+                            "train_loss": loss,
                             "heldout_mae": err.mean(axis=0).tolist(),
                             "heldout_within_tol": np.mean(err <= TOLERANCE, axis=0).tolist(),
                             "uniform_hit_rate": hit_rate(tgt[:, 1])}
@@ -246,25 +272,30 @@ def run_workflow(train_replicas=20480, steps=20000, samples=5, points=256, kinds
                         seed_base=(seed * 10 + 7) * 1_000_000)
         pred = nets[kind].predict(chosen)
         t0 = time.perf_counter()
-        plain = simulate(chosen, steps, samples, plain=True, device=device)
+        plain = simulate(chosen, steps, samples, plain=plain_run, device=device, seeds=seeds)
         t_judge = time.perf_counter() - t0
         kept, fallback, err = judge(pred, plain)
-        # the same points again with other seeds: how far two replicas of one
-        # point fall apart bounds how close any prediction from these four
-        # inputs can come to a single plain run
+        # the same points again with a disjoint set of seeds: how far two
+        # `seeds`-replica averages of one point fall apart is what remains of
+        # the replica noise in a label (and bounds how close any prediction
+        # from these four inputs can come to one)
         again = chosen.take(np.arange(len(chosen)))
         again.seed = again.seed + 500_000
-        spread = np.abs(simulate(again, steps, samples, device=device) - plain)
+        spread = np.abs(simulate(again, steps, samples, device=device, seeds=seeds) - plain)
         if uniform_plain:
             uni = draw_points(rng, points, kind, n_range, seed_base=(seed * 10 + 8) * 1_000_000)
-            uniform_lc = simulate(uni, steps, samples, plain=True, device=device)[:, 1]
+            uniform_lc = simulate(uni, steps, samples, plain=plain_run, device=device, seeds=seeds)[:, 1]
         h_c, h_u = hit_rate(plain[:, 1]), hit_rate(uniform_lc)
-        report["chosen"] = {"kind": kind, "plain_s": t_judge, "mae": err.mean(axis=0).tolist(),
+        report["chosen"] = {"kind": kind, "judge_s": t_judge,
+                            "judged_by": "db_step_batch runs (bitwise equal to db_step)" if judge_batched
+                            else "db_step runs, one replica after another",
+                            "mae": err.mean(axis=0).tolist(),
                             "within_tol": np.mean(err <= TOLERANCE, axis=0).tolist(),
                             "fallbacks": int(fallback.sum()), "replica_spread": spread.mean(axis=0).tolist(),
+                            "noise_floor": (spread.mean(axis=0) / math.sqrt(2.0)).tolist(),
                             "replica_spread_within_tol": np.mean(spread <= TOLERANCE, axis=0).tolist(),
                             "hit_rate_chosen": h_c, "hit_rate_uniform": h_u,
-                            "uniform_source": "plain runs" if uniform_plain else "training replicas",
+                            "uniform_source": "simulated uniform points" if uniform_plain else "training points",
                             "plain_runs_saved": 1.0 - h_u / h_c if h_c > 0 else 0.0}
         report["_arrays"] = {"pred": pred, "plain": plain, "kept": kept, "fallback": fallback}
         log(f"chosen: { {k: v for k, v in report['chosen'].items()} }")
@@ -285,10 +316,13 @@ if __name__ == "__main__":
     ap.add_argument("--points", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--seeds", type=int, default=4, help="replicas averaged per sweep point")
+    ap.add_argument("--plain-judge", action="store_true",
+                    help="judge with db_step runs one replica after another (same numbers, slower)")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     rep = run_workflow(a.train_replicas, a.steps, a.samples, a.points, epochs=a.epochs, seed=a.seed,
-                       log=lambda m: print(m, flush=True))
+                       log=lambda m: print(m, flush=True), seeds=a.seeds, judge_batched=not a.plain_judge)
     rep.pop("_arrays")
     line = json.dumps(rep)
     print(line)
