@@ -62,6 +62,7 @@ from scipy.sparse import coo_matrix
 from scipy.sparse.csgraph import connected_components
 from scipy.spatial import cKDTree
 
+from .detmath import exp_det, log1p_det, tanh_det
 from .philox import (KIND_INIT, KIND_MATCH, KIND_OFF, KIND_ON, KIND_THERMO,
                      box_muller3, philox4x32_10, reaction_order, step_words,
                      stream_key, u53)
@@ -145,7 +146,7 @@ def resolve_rates(k_on, k_off, epsilon, p_on0, dt, period):
 
 def melt_switch(lam, T_melt, T):
     """g(T) = [tanh(lambda (T - T_melt)) + 1] / 2 (Eq. gT)."""
-    return 0.5 * (math.tanh(lam * (T - T_melt)) + 1.0)
+    return 0.5 * (tanh_det(lam * (T - T_melt)) + 1.0)
 
 
 def melted_probabilities(p_on_init, p_off_init, p_on_melt, p_off_melt, lam, T_melt, T):
@@ -160,7 +161,7 @@ def slip_probability(p_off0, a, U, kT):
     """P_off(r) = P0_off exp(a sqrt(U_b(r) / kT)) (Eq. slip), capped at 1;
     for kT = 0 the factor is 1 when U_b = 0 and unbounded otherwise."""
     if kT > 0.0:
-        return min(1.0, p_off0 * math.exp(a * math.sqrt(U / kT)))
+        return min(1.0, p_off0 * exp_det(a * math.sqrt(U / kT)))
     if U > 0.0 and a > 0.0:
         return 1.0
     return p_off0
@@ -362,15 +363,15 @@ class OracleSystem:
             return (0.5 * k) * (d * d), k * d
         if kind == BOND_FENE:
             x2 = (r * r) / (r0 * r0)
-            return -0.5 * k * r0 * r0 * np.log1p(-x2), k * r / (1.0 - x2)
+            return -0.5 * k * r0 * r0 * log1p_det(-x2), k * r / (1.0 - x2)
         l_min, l_c1, l_c0, l_max = self.bond_kinds[bt][3:]
         U, dU = 0.0, 0.0
         if r > l_c0:                       # attraction beyond l_c0
-            e = math.exp(1.0 / (l_c0 - r))
+            e = exp_det(1.0 / (l_c0 - r))
             U += k * e / (l_max - r)
             dU += k * e * (1.0 / ((l_c0 - r) ** 2 * (l_max - r)) + 1.0 / (l_max - r) ** 2)
         if r < l_c1:                       # repulsion below l_c1
-            e = math.exp(1.0 / (r - l_c1))
+            e = exp_det(1.0 / (r - l_c1))
             U += k * e / (r - l_min)
             dU -= k * e * (1.0 / ((r - l_c1) ** 2 * (r - l_min)) + 1.0 / (r - l_min) ** 2)
         return U, dU
@@ -586,7 +587,7 @@ class OracleSystem:
     def acceptance_probability(self, p_on0, U, kT):
         """P_on = P0_on exp(-U_b/kT) (Eq. pon), capped at 1; kT = 0 reading."""
         if kT > 0.0:
-            return min(1.0, p_on0 * math.exp(-U / kT))
+            return min(1.0, p_on0 * exp_det(-U / kT))
         return p_on0 if U <= 0.0 else 0.0
 
     def pair_u53(self, kind, a, s, i, j):

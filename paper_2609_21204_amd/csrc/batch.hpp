@@ -50,34 +50,58 @@ __device__ __forceinline__ void bin_particle_wg(const Params& P, const Dev& D, i
 }
 
 // Total force on particle i at X (list + bonds), one thread, in 2^-32 fixed
-// point.  List entries are taken 8 at a time with all their loads in flight.
+// point.  The loads that need only i (list length, the first 4 list rows,
+// the first 2 bond words) are issued together, then the positions they
+// name, so that a particle with a short list and few bonds waits for two
+// memory round trips; longer lists are taken 8 entries at a time with all
+// their loads in flight, further bond slots one by one.
 template <bool EXT>
 __device__ __forceinline__ Force3 force_site(const Params& P, const StepTabs& T, const Dev& D,
                                              const float4* __restrict__ X, uint32_t i, float4 pi) {
+    constexpr int QL = 4, QB = EXT ? 1 : 2;   // (the full variant's extra branches leave room for one bond word)
     const size_t n = P.n;
     const uint32_t ti = type_of(pi);
+    const uint32_t nstat = P.stat_max, nslot = P.stat_max + T.cap[ti];
     long long fx = 0, fy = 0, fz = 0;
     const uint32_t m = D.nl_cnt[i];
-    for (uint32_t k0 = 0; k0 < m; k0 += 8) {
-        uint32_t nb[8];
-        float4 pj[8];
+    uint32_t nb[QL], bw[QB];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) nb[q] = D.nl[(size_t)min(k0 + (uint32_t)q, m - 1u) * n + i];
+    for (int q = 0; q < QL; ++q) nb[q] = (uint32_t)q < P.nlmax ? D.nl[(size_t)q * n + i] : i;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) pj[q] = X[nb[q]];
+    for (int q = 0; q < QB; ++q) {
+        const uint32_t b = (uint32_t)q;
+        bw[q] = b < nslot ? (b < nstat ? D.stat[(size_t)b * n + i] : D.dyn[(size_t)(b - nstat) * n + i]) : kEmpty;
+    }
+    float4 pj[QL], pb[QB];
+#pragma unroll
+    for (int q = 0; q < QL; ++q) pj[q] = X[(uint32_t)q < m ? nb[q] : i];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) pb[q] = X[bw[q] != kEmpty ? (bw[q] & kIdxMask) : i];
+#pragma unroll
+    for (int q = 0; q < QL; ++q)
+        if ((uint32_t)q < m) pair_force_tab(P, T, D.err, pi, pj[q], ti, fx, fy, fz);
+    for (uint32_t k0 = QL; k0 < m; k0 += 8) {
+        uint32_t nx[8];
+        float4 px[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) nx[q] = D.nl[(size_t)min(k0 + (uint32_t)q, m - 1u) * n + i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) px[q] = X[nx[q]];
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            if (k0 + (uint32_t)q < m) pair_force_tab(P, T, D.err, pi, pj[q], ti, fx, fy, fz);
+            if (k0 + (uint32_t)q < m) pair_force_tab(P, T, D.err, pi, px[q], ti, fx, fy, fz);
     }
-    for (uint32_t b = 0; b < P.stat_max; ++b) {
-        const uint32_t w = D.stat[(size_t)b * n + i];
-        if (w != kEmpty) bond_force_tab<EXT>(P, T, D, pi, X[w & kIdxMask], w >> 24, i, w & kIdxMask, fx, fy, fz);
-    }
-    const uint32_t cap = T.cap[ti];
-    for (uint32_t b = 0; b < cap; ++b) {
-        const uint32_t w = D.dyn[(size_t)b * n + i];
-        if (w != kEmpty)
-            bond_force_tab<EXT>(P, T, D, pi, X[w & kIdxMask], T.rbt[(w >> 24) & 0x7Fu], i, w & kIdxMask, fx, fy, fz);
+    auto bond = [&](uint32_t b, uint32_t w, float4 pw) {
+        const uint32_t j = w & kIdxMask;
+        if (b < nstat) bond_force_tab<EXT>(P, T, D, pi, pw, w >> 24, i, j, fx, fy, fz);
+        else bond_force_tab<EXT>(P, T, D, pi, pw, T.rbt[(w >> 24) & 0x7Fu], i, j, fx, fy, fz);
+    };
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+        if (bw[q] != kEmpty) bond((uint32_t)q, bw[q], pb[q]);
+    for (uint32_t b = QB; b < nslot; ++b) {
+        const uint32_t w = b < nstat ? D.stat[(size_t)b * n + i] : D.dyn[(size_t)(b - nstat) * n + i];
+        if (w != kEmpty) bond(b, w, X[w & kIdxMask]);
     }
     return fix_to_force(D, fx, fy, fz);
 }

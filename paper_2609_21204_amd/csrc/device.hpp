@@ -93,6 +93,95 @@ __host__ __device__ inline int reaction_at(uint32_t seed, uint64_t s, int nrx, i
     return order[slot];
 }
 
+// ---------------------------------------------------------------- decision math
+// exp, log1p and tanh for what decides bonds: the acceptance factor of
+// Eq. pon, the slip factor of Eq. slip, the melting switch of Eq. gT and the
+// FENE and tether bond energies.  Only IEEE-rounded +, -, *, / and exact
+// power-of-two scaling, in a fixed order with contraction off, so every
+// device and the host produce the same bits for the same input (and so does
+// any other implementation of these same steps); a few ulp from the exact
+// functions.
+//   exp:   Cody-Waite reduction (Cody & Waite, 1980): n = rint(x / ln2), ln2
+//          split into a head of 29 bits (n head is exact) and a tail,
+//          r = (x - n head) - n tail; Taylor series of e^r to degree 13 by
+//          Horner; times 2^n.
+//   log1p: 1 + z = m 2^e, m in [sqrt(1/2), sqrt(2)); s = (m - 1)/(m + 1), or
+//          z / (2 + z) when e = 0 (small z keep their bits); log m by the
+//          atanh series 2 (s + s^3/3 + ... + s^23/23) in Horner form in s^2;
+//          plus e head + e tail.
+//   tanh:  1 - 2 / (exp(2|x|) + 1) with the sign of x, 1 beyond |x| = 22.
+constexpr double kLn2Hi = 0x1.62e42fe000000p-1;
+constexpr double kLn2Lo = 0x1.f473de6af278fp-30;
+constexpr double kInvLn2 = 0x1.71547652b82fep+0;
+
+__host__ __device__ inline double exp_det(double x) {
+#pragma clang fp contract(off)
+    if (x != x) return x;
+    if (!(x > -745.5)) return 0.0;
+    if (x > 709.78) return __builtin_huge_val();
+    const double n = rint(x * kInvLn2);
+    const double r = (x - n * kLn2Hi) - n * kLn2Lo;
+    double p = 0x1.6124613a86d09p-33;        // 1/13!
+    p = p * r + 0x1.1eed8eff8d898p-29;       // 1/12!
+    p = p * r + 0x1.ae64567f544e4p-26;       // 1/11!
+    p = p * r + 0x1.27e4fb7789f5cp-22;       // 1/10!
+    p = p * r + 0x1.71de3a556c734p-19;       // 1/9!
+    p = p * r + 0x1.a01a01a01a01ap-16;       // 1/8!
+    p = p * r + 0x1.a01a01a01a01ap-13;       // 1/7!
+    p = p * r + 0x1.6c16c16c16c17p-10;       // 1/6!
+    p = p * r + 0x1.1111111111111p-7;        // 1/5!
+    p = p * r + 0x1.5555555555555p-5;        // 1/4!
+    p = p * r + 0x1.5555555555555p-3;        // 1/3!
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)n);
+}
+
+__host__ __device__ inline double log1p_det(double z) {
+#pragma clang fp contract(off)
+    if (z != z) return z;
+    if (!(z > -1.0)) return z == -1.0 ? -__builtin_huge_val() : __builtin_nan("");
+    const double y = 1.0 + z;
+    int e = 0;
+    double m = frexp(y, &e);
+    if (m < 0x1.6a09e667f3bcdp-1) {          // sqrt(1/2)
+        m = m * 2.0;
+        e -= 1;
+    }
+    double s;
+    if (e == 0) {
+        s = z / (2.0 + z);
+    } else {
+        const double f = m - 1.0;
+        s = f / (2.0 + f);
+    }
+    const double s2 = s * s;
+    double t = 1.0 / 23.0;
+    t = t * s2 + 1.0 / 21.0;
+    t = t * s2 + 1.0 / 19.0;
+    t = t * s2 + 1.0 / 17.0;
+    t = t * s2 + 1.0 / 15.0;
+    t = t * s2 + 1.0 / 13.0;
+    t = t * s2 + 1.0 / 11.0;
+    t = t * s2 + 1.0 / 9.0;
+    t = t * s2 + 1.0 / 7.0;
+    t = t * s2 + 1.0 / 5.0;
+    t = t * s2 + 1.0 / 3.0;
+    const double lm = 2.0 * s + (2.0 * s) * (s2 * t);
+    const double de = (double)e;
+    return de * kLn2Hi + (lm + de * kLn2Lo);
+}
+
+__host__ __device__ inline double tanh_det(double x) {
+#pragma clang fp contract(off)
+    if (x != x) return x;
+    const double a = fabs(x);
+    double t = 1.0;
+    if (a < 22.0) t = 1.0 - 2.0 / (exp_det(2.0 * a) + 1.0);
+    return x < 0.0 ? -t : t;
+}
+
 // ---------------------------------------------------------------- geometry
 // Minimum-image separation x_j - x_i in FP64 from FP32 coordinates.  The
 // evaluation order is fixed and never contracted into FMAs, so that every

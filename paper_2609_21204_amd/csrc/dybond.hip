@@ -95,12 +95,13 @@ struct db_system {
     uint32_t* bsum = nullptr;       // block sums for the bond read-out (nb + 1)
     float4* stage = nullptr;        // tag-ordered staging buffer
     uint32_t* flag = nullptr;       // device flag for iterative kernels
+    uint32_t* err_h = nullptr;      // pinned host copy of the device error words
     uint64_t step = 0;
     int cur_x = 0, cur_list = 0;
     std::vector<uint32_t> tag_h, rtag_h;   // host mirrors of tag / rtag
     std::vector<PairTab> pair_h;           // WCA table uploaded to D.pair
     Timing timing;
-    std::map<int, hipGraphExec_t> graphs;  // keyed by (cur_x, cur_list)
+    std::map<uint64_t, hipGraphExec_t> graphs;   // captured step graphs, by kind and phase (graph_key)
     hipEvent_t ev_out = nullptr, ev_back = nullptr;   // ordering of device-side read-outs
     uint32_t* bref = nullptr;              // reference bond table of the bond correlation (by tag)
     bool have_ref = false;
@@ -467,7 +468,7 @@ std::vector<uint32_t> morton_cells(uint32_t nc) {
 // g = [tanh(lambda (T - T_melt)) + 1] / 2; P0 = k n dt is linear in k.
 double melt_mix_host(double p_init, double p_melt, double lam, double tm, double T) {
 #pragma clang fp contract(off)
-    const double g = 0.5 * (std::tanh(lam * (T - tm)) + 1.0);
+    const double g = 0.5 * (tanh_det(lam * (T - tm)) + 1.0);
     return p_init * (1.0 - g) + p_melt * g;
 }
 
@@ -768,10 +769,13 @@ db_status ensure_cell_capacity(db_system* s, const float* pos3) {
 
 db_status check_errors(db_system* s) {
     HIPCHK(s, hipGetLastError());
+    // the error words come back through a pinned buffer, behind the work on
+    // the stream: one synchronisation per call
+    HIPCHK(s, hipMemcpyAsync(s->err_h, s->D.err, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     flush_timing(s);
     uint32_t err[4];
-    HIPCHK(s, hipMemcpy(err, s->D.err, sizeof err, hipMemcpyDeviceToHost));
+    std::memcpy(err, s->err_h, sizeof err);
     if (err[0] & kErrOverflow) { s->invalid = true; return fail(s, DB_EOVERFLOW, "cell capacity %u exceeded", s->P.cellcap); }
     if (err[0] & kErrFene) { s->invalid = true; return fail(s, DB_EBOND, "bond %u-%u outside its range (FENE r >= R0, tether r outside (l_min, l_max))", err[1], err[2]); }
     if (err[0] & kErrForce) { s->invalid = true; return fail(s, DB_EBOND, "force out of the representable range"); }
@@ -874,21 +878,23 @@ void launch_step(db_system* s) {
 // counter t (position buffer t mod 2, cell list t mod 3, step slot t mod 2,
 // rebuild-flag slot t mod 3; upload_state and every launcher keep
 // cur_x = t mod 2 and cur_list = t mod 3), and whether a step ends in a
-// sweep is a function of t mod period, so a graph captured at step t replays
-// correctly at any step with the same t mod 6 and the same sweep pattern.
-// Kinds: one step (with or without its sweep), one sweep period from an
-// aligned step, a span of periods (>= 120 steps) from an aligned step, and
-// the spatial renumbering.  The one-step, one-period and renumbering graphs
-// are captured together on the first db_step call, so that any later call,
-// however short, replays graphs only.
-enum : int { kGStep = 0, kGPeriod = 1, kGSpan = 2, kGSort = 3 };
+// sweep is a function of t mod period, so a graph of k steps captured at
+// step t replays correctly at any step with the same t mod 6 and t mod
+// period.  Kinds, so that any call replays at most a head, whole periods or
+// spans, and a tail:
+//   head   from an unaligned t to the next multiple of the period;
+//   period one sweep period from an aligned step;
+//   span   whole periods, at least 120 steps, from an aligned step;
+//   tail   1 .. period - 1 steps from an aligned step;
+//   step   one step (calls shorter than the head they start in);
+//   sort   the spatial renumbering.
+// Every graph but the spans is captured on the first db_step call (a few
+// hundred steps' worth of launches), so that later calls, however short,
+// replay graphs only; graphs that inter-graph gaps would otherwise multiply
+// (each replay costs a few microseconds on the GPU) stay few per call.
+enum : int { kGStep = 0, kGPeriod = 1, kGSpan = 2, kGSort = 3, kGHead = 4, kGTail = 5 };
 
 bool sweep_after(const db_system* s, uint64_t t) { return s->P.nrx > 0 && (t + 1) % s->period == 0; }
-
-int graph_key(const db_system* s, int kind, uint64_t t) {
-    const bool sw = kind == kGStep && sweep_after(s, t);
-    return (kind * 6 + (int)(t % 6)) * 2 + (sw ? 1 : 0);
-}
 
 // Steps in a span graph: a whole number of sweep periods, at least 120 (0:
 // none, when the period alone is longer than that).
@@ -897,13 +903,34 @@ uint64_t graph_span(const db_system* s) {
     return (uint64_t)s->period * ((120 + s->period - 1) / s->period);
 }
 
-// Steps in a period graph (0: none, for periods longer than 120 steps).
+// Steps in a period graph (0: none, for periods longer than 120 steps; then
+// heads and tails are not used either).
 uint64_t graph_period(const db_system* s) { return s->period <= 120 ? s->period : 0; }
+
+// Steps the graph of `kind` at step t covers (len: the tail's length).
+uint64_t graph_steps(const db_system* s, int kind, uint64_t t, uint64_t len) {
+    switch (kind) {
+        case kGStep: return 1;
+        case kGPeriod: return graph_period(s);
+        case kGSpan: return graph_span(s);
+        case kGHead: return s->period - t % s->period;
+        case kGTail: return len;
+        default: return 0;
+    }
+}
+
+uint64_t graph_key(const db_system* s, int kind, uint64_t t, uint64_t len) {
+    uint64_t extra = 0;
+    if (kind == kGStep) extra = sweep_after(s, t) ? 1 : 0;
+    else if (kind == kGHead) extra = t % s->period;
+    else if (kind == kGTail) extra = len;
+    return ((uint64_t)kind << 48) | ((t % 6) << 32) | extra;
+}
 
 // The graph of `kind` at step t, captured (with the host's step state set to
 // t and restored afterwards) when not yet held.
-db_status graph_at(db_system* s, int kind, uint64_t t, hipGraphExec_t* out) {
-    const int key = graph_key(s, kind, t);
+db_status graph_at(db_system* s, int kind, uint64_t t, uint64_t len, hipGraphExec_t* out) {
+    const uint64_t key = graph_key(s, kind, t, len);
     auto it = s->graphs.find(key);
     if (it != s->graphs.end()) {
         *out = it->second;
@@ -920,15 +947,13 @@ db_status graph_at(db_system* s, int kind, uint64_t t, hipGraphExec_t* out) {
     if (kind == kGSort) {
         launch_sort(s);
     } else {
-        const uint64_t k = kind == kGStep ? 1 : kind == kGPeriod ? graph_period(s) : graph_span(s);
+        const uint64_t k = graph_steps(s, kind, t, len);
         for (uint64_t q = 0; q < k; ++q) launch_step(s);
     }
     HIPCHK(s, hipStreamEndCapture(s->stream, &g));
     hipGraphExec_t ge;
     HIPCHK(s, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     HIPCHK(s, hipGraphDestroy(g));
-    // the executable's device-side setup now, not on its first launch (a
-    // short db_step call may be the first to replay it)
     HIPCHK(s, hipGraphUpload(ge, s->stream));
     s->step = step0;
     s->cur_x = x0;
@@ -939,18 +964,29 @@ db_status graph_at(db_system* s, int kind, uint64_t t, hipGraphExec_t* out) {
     return DB_OK;
 }
 
-// Capture every one-step, one-period and renumbering graph a run can need.
+// Capture every graph but the spans: lcm(6, period) consecutive steps meet
+// every phase a one-step or head graph can start in, and their aligned steps
+// every phase of the period, tail and renumbering graphs.
 db_status prepare_graphs(db_system* s) {
     const uint64_t per = s->period, t0 = s->step;
-    for (uint64_t t = t0; t < t0 + 6 * per; ++t) {
-        hipGraphExec_t ge;
-        db_status st = graph_at(s, kGStep, t, &ge);
-        if (st != DB_OK) return st;
-        if (t % per == 0) {
-            if (graph_period(s) && (st = graph_at(s, kGPeriod, t, &ge)) != DB_OK) return st;
-            if (s->sort_enabled && (st = graph_at(s, kGSort, t, &ge)) != DB_OK) return st;
+    const uint64_t l6 = 6 / std::gcd<uint64_t>(6, per) * per;
+    hipGraphExec_t ge;
+    db_status st;
+    for (uint64_t t = t0; t < t0 + l6; ++t) {
+        if ((st = graph_at(s, kGStep, t, 0, &ge)) != DB_OK) return st;
+        if (!graph_period(s)) continue;
+        if (t % per != 0) {
+            if ((st = graph_at(s, kGHead, t, 0, &ge)) != DB_OK) return st;
+            continue;
         }
+        if ((st = graph_at(s, kGPeriod, t, 0, &ge)) != DB_OK) return st;
+        if (s->sort_enabled && (st = graph_at(s, kGSort, t, 0, &ge)) != DB_OK) return st;
+        for (uint64_t len = 1; len < per; ++len)
+            if ((st = graph_at(s, kGTail, t, len, &ge)) != DB_OK) return st;
     }
+    if (!graph_period(s) && s->sort_enabled)
+        for (uint64_t t = t0; t < t0 + l6; ++t)
+            if (t % per == 0 && (st = graph_at(s, kGSort, t, 0, &ge)) != DB_OK) return st;
     return DB_OK;
 }
 
@@ -968,7 +1004,7 @@ db_status run_steps(db_system* s, uint64_t nsteps) {
         if (aligned && s->sort_enabled && s->step >= s->sort_due) {
             if (graphs) {
                 hipGraphExec_t ge;
-                const db_status st = graph_at(s, kGSort, s->step, &ge);
+                const db_status st = graph_at(s, kGSort, s->step, 0, &ge);
                 if (st != DB_OK) return st;
                 HIPCHK(s, hipGraphLaunch(ge, s->stream));
             } else {
@@ -984,16 +1020,20 @@ db_status run_steps(db_system* s, uint64_t nsteps) {
         }
         const uint64_t left = nsteps - done;
         int kind = kGStep;
-        uint64_t k = 1;
-        if (aligned && span && left >= span) {
+        uint64_t len = 0;
+        if (per && !aligned) {
+            if (left >= per - s->step % per) kind = kGHead;
+        } else if (aligned && span && left >= span) {
             kind = kGSpan;
-            k = span;
         } else if (aligned && per && left >= per) {
             kind = kGPeriod;
-            k = per;
+        } else if (aligned && per) {
+            kind = kGTail;
+            len = left;
         }
+        const uint64_t k = graph_steps(s, kind, s->step, len);
         hipGraphExec_t ge;
-        const db_status st = graph_at(s, kind, s->step, &ge);
+        const db_status st = graph_at(s, kind, s->step, len, &ge);
         if (st != DB_OK) return st;
         HIPCHK(s, hipGraphLaunch(ge, s->stream));
         s->step += k;
@@ -1049,6 +1089,7 @@ void db_destroy(db_system* s) {
         for (auto e : s->timing.pool) (void)hipEventDestroy(e);
         if (s->ev_out) (void)hipEventDestroy(s->ev_out);
         if (s->ev_back) (void)hipEventDestroy(s->ev_back);
+        if (s->err_h) (void)hipHostFree(s->err_h);
         for (void* p : s->allocs) (void)hipFree(p);
         if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     }
@@ -1386,6 +1427,14 @@ static db_status commit_impl(db_system* s) {
     DALLOC(s, D.stat_alt, (size_t)std::max(P.stat_max, 1u) * n);
     DALLOC(s, s->stage, n);
     DALLOC(s, s->flag, 1);
+    {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(s, DB_ENOMEM, "pinned host allocation failed");
+        }
+        s->err_h = (uint32_t*)h;
+    }
     // static topology, molecule ids, tags
     std::vector<uint32_t> stat((size_t)std::max(P.stat_max, 1u) * n, kEmpty), fillc(n, 0);
     for (size_t k = 0; k < s->stat_bt.size(); ++k) {

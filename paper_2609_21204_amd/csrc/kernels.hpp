@@ -46,12 +46,12 @@ __device__ __forceinline__ double tether_u(double r, double k, double lmin, doub
 #pragma clang fp contract(off)
     double U = 0.0, d = 0.0;
     if (r > lc0) {
-        const double e = exp(1.0 / (lc0 - r));
+        const double e = exp_det(1.0 / (lc0 - r));
         U += k * e / (lmax - r);
         d += k * e * (1.0 / ((lc0 - r) * (lc0 - r) * (lmax - r)) + 1.0 / ((lmax - r) * (lmax - r)));
     }
     if (r < lc1) {
-        const double e = exp(1.0 / (r - lc1));
+        const double e = exp_det(1.0 / (r - lc1));
         U += k * e / (r - lmin);
         d -= k * e * (1.0 / ((r - lc1) * (r - lc1) * (r - lmin)) + 1.0 / ((r - lmin) * (r - lmin)));
     }
@@ -71,7 +71,7 @@ __device__ __forceinline__ double bond_energy(const Params& P, uint32_t bt, doub
     }
     if (kind == 1u) {
         const double x2 = (r * r) / P.bR02[bt];
-        return -0.5 * P.bk[bt] * P.br0[bt] * P.br0[bt] * log1p(-x2);
+        return -0.5 * P.bk[bt] * P.br0[bt] * P.br0[bt] * log1p_det(-x2);
     }
     double du;
     return tether_u(r, P.bk[bt], P.blmin[bt], P.blc1[bt], P.blc0[bt], P.blmax[bt], &du);
@@ -81,7 +81,7 @@ __device__ __forceinline__ double bond_energy(const Params& P, uint32_t bt, doub
 // g = [tanh(lambda (T - T_melt)) + 1] / 2.
 __device__ __forceinline__ double melt_mix(double p_init, double p_melt, double lam, double tm, double T) {
 #pragma clang fp contract(off)
-    const double g = 0.5 * (tanh(lam * (T - tm)) + 1.0);
+    const double g = 0.5 * (tanh_det(lam * (T - tm)) + 1.0);
     return p_init * (1.0 - g) + p_melt * g;
 }
 
@@ -90,7 +90,7 @@ __device__ __forceinline__ double melt_mix(double p_init, double p_melt, double 
 __device__ __forceinline__ double slip_prob(double p0, double a, double U, double kT) {
 #pragma clang fp contract(off)
     if (kT > 0.0) {
-        const double q = p0 * exp(a * sqrt(U / kT));
+        const double q = p0 * exp_det(a * sqrt(U / kT));
         return q < 1.0 ? q : 1.0;
     }
     return (U > 0.0 && a > 0.0) ? 1.0 : p0;
@@ -1479,7 +1479,7 @@ __device__ __forceinline__ bool accept_loaded(const Params& P, const Dev& D, int
     }
     double prob;
     if (kT > 0.0) {
-        prob = pon * exp(-U / kT);
+        prob = pon * exp_det(-U / kT);
         prob = prob < 1.0 ? prob : 1.0;
     } else {
         prob = U <= 0.0 ? pon : 0.0;

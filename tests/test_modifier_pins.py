@@ -209,3 +209,26 @@ def test_melted_probabilities_are_checked():
     with pytest.raises(OracleError) as e:
         _dimers(2, 1.0, dict(k_on=4.0, epsilon=1.0), melt=(5.0, 1.0, 30.0, 0.0))   # 30 n dt > 1
     assert e.value.code == "ERANGE"
+
+
+def test_decision_math_against_the_exact_functions():
+    """The oracle's exp, log1p and tanh of the bond decisions (Cody-Waite
+    exp, atanh-series log1p, tanh from exp) against the correctly rounded
+    library functions: within 1, 3 ulp and 3e-16, and exact where the
+    mathematics is (exp 0 = 1, log1p 0 = 0, tanh 0 = 0, tanh odd, exp of a
+    sum as the product within rounding, e^(ln 2) = 2 within an ulp)."""
+    from oracle.detmath import exp_det, log1p_det, tanh_det
+    rng = np.random.default_rng(5)
+    for x in rng.uniform(-40.0, 40.0, 20000).tolist() + rng.uniform(-1e-3, 1e-3, 2000).tolist():
+        assert abs(exp_det(x) - math.exp(x)) <= math.ulp(math.exp(x))
+    for z in rng.uniform(-0.999, 5.0, 20000).tolist() + rng.uniform(-1e-7, 1e-7, 2000).tolist():
+        ref = math.log1p(z)
+        assert abs(log1p_det(z) - ref) <= 3 * math.ulp(ref)
+    for x in rng.uniform(-25.0, 25.0, 20000).tolist():
+        assert abs(tanh_det(x) - math.tanh(x)) <= 3e-16
+        assert tanh_det(-x) == -tanh_det(x)
+    assert exp_det(0.0) == 1.0 and log1p_det(0.0) == 0.0 and tanh_det(0.0) == 0.0
+    assert abs(exp_det(math.log(2.0)) - 2.0) <= math.ulp(2.0)
+    assert exp_det(-800.0) == 0.0 and tanh_det(30.0) == 1.0
+    for a, b in (np.round(rng.uniform(-5.0, 5.0, (200, 2)) * 2.0 ** 30) / 2.0 ** 30).tolist():   # a + b exact
+        assert abs(exp_det(a + b) - exp_det(a) * exp_det(b)) <= 4 * math.ulp(exp_det(a + b))
