@@ -45,7 +45,7 @@ __device__ __forceinline__ void bin_particle_wg(const Params& P, const Dev& D, i
     const int c = (cell_coord(p.z, P) * (int)P.nc + cell_coord(p.y, P)) * (int)P.nc + cell_coord(p.x, P);
     const uint32_t slot = wg_atomic_add(&D.ccount[lst][c], 1u);
     if (slot < P.cellcap)
-        D.cpos[lst][(size_t)c * P.cellcap + slot] = make_float4(p.x, p.y, p.z, __uint_as_float(i | (type_of(p) << 24)));
+        D.cpos[lst][cell_slot(P, (uint32_t)c, slot)] = make_float4(p.x, p.y, p.z, __uint_as_float(i | (type_of(p) << 24)));
     else atomicOr(&D.err[0], kErrOverflow);
 }
 
@@ -157,7 +157,7 @@ __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T
                         c = cell[q];
                         o = off[q];
                     }
-                f[e] = cp[(size_t)c * cap + (idx - o)];
+                f[e] = cp[cell_slot(P, c, idx - o)];
             }
 #pragma unroll
             for (int e = 0; e < 8; ++e)
@@ -364,9 +364,11 @@ void k_batch_sort(const BatchItem* __restrict__ items, const BatchState* __restr
         bucket_cell_type(P, D, b, c, t);
         uint32_t m = D.ccount[lst][c];
         m = m < P.cellcap ? m : P.cellcap;
-        const float4* cp = D.cpos[lst] + (size_t)c * P.cellcap;
-        for (uint32_t k = 0; k < m; ++k)
-            if (slot_type(cp[k]) == t) D.newidx[slot_index(cp[k])] = at++;
+        const float4* cp = D.cpos[lst];
+        for (uint32_t k = 0; k < m; ++k) {
+            const float4 q = cp[cell_slot(P, c, k)];
+            if (slot_type(q) == t) D.newidx[slot_index(q)] = at++;
+        }
     }
     __syncthreads();
     float4* __restrict__ X = D.x[xin];

@@ -285,7 +285,7 @@ struct Dev {
     uint32_t* stat;        // stat_max x n static slots: partner | bond type << 24
     uint32_t* mol;         // molecule id (static-bond component)
     uint32_t* ccount[3];   // per-cell counts of three rotating cell lists
-    float4* cpos[3];       // per-cell members: position + (index | type << 24) bits, cellcap slots per cell
+    float4* cpos[3];       // per-cell members: position + (index | type << 24) bits, cellcap slots per cell (cell_slot)
     int32_t* prop;         // proposed partner index (-1 none)
     unsigned long long* key;        // matching priority of each proposal
     unsigned long long* best[3];    // per-site minimum key of live incident proposals (3 rotating)
@@ -338,6 +338,15 @@ __device__ __forceinline__ int cell_coord(float x, const Params& P) {
 }
 
 __device__ __forceinline__ int wrapc(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
+
+// Slot k of cell c in a cell list's member array.  Slot-major: the slots k
+// of all cells are contiguous, so that the first slots of a row of
+// neighbouring cells share cache lines (a cell holds about one particle at
+// the densities simulated, so a cell-major block of cellcap slots would
+// bring a mostly empty line per cell).
+__device__ __forceinline__ size_t cell_slot(const Params& P, uint32_t c, uint32_t k) {
+    return (size_t)k * P.ncell + c;
+}
 
 // Round v * 2^32 to the nearest integer (ties to even) with one FMA: adding
 // 1.5 * 2^52 leaves round(v * 2^32) in the low mantissa bits.  Exact for

@@ -261,7 +261,7 @@ __device__ __forceinline__ void bin_particle(const Params& P, const Dev& D, int 
     const int c = (cell_coord(p.z, P) * (int)P.nc + cell_coord(p.y, P)) * (int)P.nc + cell_coord(p.x, P);
     const uint32_t slot = atomicAdd(&D.ccount[lst][c], 1u);
     if (slot < P.cellcap)
-        D.cpos[lst][(size_t)c * P.cellcap + slot] = make_float4(p.x, p.y, p.z, __uint_as_float(i | (type_of(p) << 24)));
+        D.cpos[lst][cell_slot(P, (uint32_t)c, slot)] = make_float4(p.x, p.y, p.z, __uint_as_float(i | (type_of(p) << 24)));
     else atomicOr(&D.err[0], kErrOverflow);
 }
 
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
             for (int step = 512; step >= 1; step >>= 1)
                 if (lo + step < nh && hoff[lo + step] <= e) lo += step;
             hv[q] = lo;
-            v[q] = cp[(size_t)hglob[lo] * P.cellcap + (e - hoff[lo])];
+            v[q] = cp[cell_slot(P, hglob[lo], e - hoff[lo])];
         }
         // threads past the end rewrite the last entry with its own value, so
         // the stores need no branch (which would pull the loads after it)
@@ -738,9 +738,9 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
         for (int h = (int)tid; h < nh; h += kTileThreads) {
             if (!is_core(h)) continue;
             const uint32_t o = hoff[h], m0 = hoff[h + 1] - o;
-            const size_t base = (size_t)hcell(h) * P.cellcap;
+            const uint32_t hc = (uint32_t)hcell(h);
             for (uint32_t k0 = 0; k0 < m0; ++k0) {
-                const float4 pi = cp[base + k0];
+                const float4 pi = cp[cell_slot(P, hc, k0)];
                 const uint32_t i = slot_index(pi);
                 const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
                 uint32_t m = 0;
@@ -751,7 +751,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const De
                             uint32_t mc = cnt[c];
                             mc = mc < P.cellcap ? mc : P.cellcap;
                             for (uint32_t kk = 0; kk < mc; ++kk) {
-                                const float4 pj = cp[(size_t)c * P.cellcap + kk];
+                                const float4 pj = cp[cell_slot(P, (uint32_t)c, kk)];
                                 if (slot_index(pj) != i) nl_consider(P, D, rl2, i, pi, pj, m);
                             }
                         }
@@ -1145,9 +1145,9 @@ __device__ __forceinline__ uint32_t bucket_count(const Params& P, const Dev& D, 
     bucket_cell_type(P, D, b, c, t);
     uint32_t m = D.ccount[lst][c];
     m = m < P.cellcap ? m : P.cellcap;
-    const float4* cp = D.cpos[lst] + (size_t)c * P.cellcap;
+    const float4* cp = D.cpos[lst];
     uint32_t r = 0;
-    for (uint32_t k = 0; k < m; ++k) r += slot_type(cp[k]) == t;
+    for (uint32_t k = 0; k < m; ++k) r += slot_type(cp[cell_slot(P, c, k)]) == t;
     return r;
 }
 
@@ -1169,9 +1169,11 @@ __global__ __launch_bounds__(256) void k_sort_assign(const Params P, const Dev D
     uint32_t m = D.ccount[lst][c];
     m = m < P.cellcap ? m : P.cellcap;
     uint32_t at = D.cstart[b] + D.cbsum[blockIdx.x];
-    const float4* cp = D.cpos[lst] + (size_t)c * P.cellcap;
-    for (uint32_t k = 0; k < m; ++k)
-        if (slot_type(cp[k]) == t) D.newidx[slot_index(cp[k])] = at++;
+    const float4* cp = D.cpos[lst];
+    for (uint32_t k = 0; k < m; ++k) {
+        const float4 q = cp[cell_slot(P, c, k)];
+        if (slot_type(q) == t) D.newidx[slot_index(q)] = at++;
+    }
 }
 
 __device__ __forceinline__ uint32_t remap_slot(const Dev& D, uint32_t w) {
