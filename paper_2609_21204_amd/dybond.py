@@ -137,6 +137,14 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # PyTorch for ROCm carries its own HIP runtime under the soname the
+        # library links against; loaded first, it is the one the library
+        # binds to, so that the process holds a single runtime (a second
+        # copy loaded after the library's would find no device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(lib, name)
