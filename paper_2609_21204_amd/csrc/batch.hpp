@@ -170,7 +170,7 @@ __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T
 }
 
 // n steps of system blockIdx.x.  Per step, as db_step: forces at x_t + BAOAB
-// + binning of x_{t+1} (the list is rebuilt right after a step that moved
+// (x_{t+1} is binned and the list rebuilt right after a step that moved
 // some particle by more than skin / 2), and the bonding sweep at s = t + 1
 // when s is a multiple of the sweep period.  In the sweep, the rounds of the
 // greedy matching alternate two key buffers: post keys at both sites of each
@@ -198,11 +198,10 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
     int xin = st0.cur_x, lcur = st0.cur_list;
     for (uint32_t k = 0; k < nsteps; ++k) {
         const unsigned long long t = t0 + k, s = t + 1;
-        const int lnext = lcur == 2 ? 0 : lcur + 1, lclr = lnext == 2 ? 0 : lnext + 1;
+        const int lnext = lcur == 2 ? 0 : lcur + 1;
         const bool sweep = P.nrx > 0 && (s % P.period) == 0;
         const int ake = (sweep && P.kt_kinetic) ? 1 : 0;
         if (tid == 0) flag[(k + 1) % 3] = 0u;   // last read two steps ago
-        for (uint32_t c = tid; c < P.ncell; c += bs) D.ccount[lclr][c] = 0u;
         const float4* __restrict__ X = D.x[xin];
         unsigned long long ke = 0ull;
         for (uint32_t i = tid; i < n; i += bs) {
@@ -212,7 +211,6 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
             const Force3 F = force_site<EXT>(P, T, D, X, i, pi);
             float4 po;
             ke += advance_particle(P, T, D, xin, i, pi, type_of(pi), F, ui, __float_as_uint(ui.w), s, ake, po);
-            bin_particle_wg(P, D, lnext, i, po);
             if (moved_past_skin(P, r, po)) flag[k % 3] = 1u;
         }
         if (ake) {
@@ -224,7 +222,13 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
         xin ^= 1;
         lcur = lnext;
         if (flag[k % 3]) {
+            // neighbour lists at x_{t+1}: cell list lcur emptied, filled,
+            // then read by the build (steps without a build bin nothing)
             const float4* __restrict__ Xn = D.x[xin];
+            for (uint32_t c = tid; c < P.ncell; c += bs) D.ccount[lcur][c] = 0u;
+            __syncthreads();
+            for (uint32_t i = tid; i < n; i += bs) bin_particle_wg(P, D, lcur, i, Xn[i]);
+            __syncthreads();
             for (uint32_t i = tid; i < n; i += bs) nl_build_site(P, T, D, lcur, i, Xn[i]);
             __syncthreads();
         }
