@@ -30,6 +30,10 @@ struct BatchState {
 };
 
 constexpr int kBatchMaxThreads = 1024;
+// LDS of one batch workgroup: the step tables, a few flags and, in the
+// variant that keeps them there, the positions of its system (16 B each).
+constexpr uint32_t kBatchLdsTotal = 160u * 1024u;
+constexpr uint32_t kBatchLdsStatic = (uint32_t)sizeof(StepTabs) + 256u;
 
 // Workgroup-scope atomic add on global memory: only the owning workgroup
 // touches a system's arrays during a batch launch, so the add can complete
@@ -39,6 +43,21 @@ __device__ __forceinline__ uint32_t wg_atomic_add(uint32_t* p, uint32_t v) {
 }
 __device__ __forceinline__ void wg_atomic_min64(unsigned long long* p, unsigned long long v) {
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Device pointers read from a batch item are generic to the compiler (they
+// come from memory, not from kernel arguments), and generic accesses compile
+// to flat instructions, which also count against the LDS wait counter: a
+// wait for an LDS read (the step tables, positions held in LDS) then waits
+// for every memory load in flight as well.  The pointers of the hot loops
+// pass through the scalar unit and come back typed as global pointers, so
+// that the loads through them compile to global loads.
+template <class T>
+__device__ __forceinline__ T* as_global(T* p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T*)(__attribute__((address_space(1))) T*)(((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ void bin_particle_wg(const Params& P, const Dev& D, int lst, uint32_t i, float4 p) {
@@ -63,14 +82,17 @@ __device__ __forceinline__ Force3 force_site(const Params& P, const StepTabs& T,
     const uint32_t ti = type_of(pi);
     const uint32_t nstat = P.stat_max, nslot = P.stat_max + T.cap[ti];
     long long fx = 0, fy = 0, fz = 0;
-    const uint32_t m = D.nl_cnt[i];
+    const uint32_t* __restrict__ nl = as_global(D.nl);
+    const uint32_t* __restrict__ stat = as_global(D.stat);
+    const uint32_t* __restrict__ dyn = as_global(D.dyn);
+    const uint32_t m = as_global(D.nl_cnt)[i];
     uint32_t nb[QL], bw[QB];
 #pragma unroll
-    for (int q = 0; q < QL; ++q) nb[q] = (uint32_t)q < P.nlmax ? D.nl[(size_t)q * n + i] : i;
+    for (int q = 0; q < QL; ++q) nb[q] = (uint32_t)q < P.nlmax ? nl[(size_t)q * n + i] : i;
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
         const uint32_t b = (uint32_t)q;
-        bw[q] = b < nslot ? (b < nstat ? D.stat[(size_t)b * n + i] : D.dyn[(size_t)(b - nstat) * n + i]) : kEmpty;
+        bw[q] = b < nslot ? (b < nstat ? stat[(size_t)b * n + i] : dyn[(size_t)(b - nstat) * n + i]) : kEmpty;
     }
     float4 pj[QL], pb[QB];
 #pragma unroll
@@ -84,7 +106,7 @@ __device__ __forceinline__ Force3 force_site(const Params& P, const StepTabs& T,
         uint32_t nx[8];
         float4 px[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) nx[q] = D.nl[(size_t)min(k0 + (uint32_t)q, m - 1u) * n + i];
+        for (int q = 0; q < 8; ++q) nx[q] = nl[(size_t)min(k0 + (uint32_t)q, m - 1u) * n + i];
 #pragma unroll
         for (int q = 0; q < 8; ++q) px[q] = X[nx[q]];
 #pragma unroll
@@ -100,7 +122,7 @@ __device__ __forceinline__ Force3 force_site(const Params& P, const StepTabs& T,
     for (int q = 0; q < QB; ++q)
         if (bw[q] != kEmpty) bond((uint32_t)q, bw[q], pb[q]);
     for (uint32_t b = QB; b < nslot; ++b) {
-        const uint32_t w = b < nstat ? D.stat[(size_t)b * n + i] : D.dyn[(size_t)(b - nstat) * n + i];
+        const uint32_t w = b < nstat ? stat[(size_t)b * n + i] : dyn[(size_t)(b - nstat) * n + i];
         if (w != kEmpty) bond(b, w, X[w & kIdxMask]);
     }
     return fix_to_force(D, fx, fy, fz);
@@ -179,7 +201,13 @@ __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T
 // Any workgroup size that is a multiple of 64 up to kBatchMaxThreads gives
 // the same result: particles are dealt out round robin over the threads and
 // every sum is exact.
-template <bool EXT>
+// With LX the positions of the current step are copied into LDS (dynamic
+// LDS of n float4) after every step, and the force, list and sweep passes
+// gather neighbour and partner positions from there: a thread walks its
+// particles one after another, and each neighbour gather that comes from
+// LDS instead of memory shortens that chain by a memory round trip.  The
+// copy is exact, so both variants give the same result.
+template <bool EXT, bool LX>
 __global__ __launch_bounds__(kBatchMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state, uint32_t nsteps) {
     const BatchItem& B = items[blockIdx.x];
@@ -190,24 +218,33 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
     __shared__ StepTabs T;
     __shared__ uint32_t flag[3];          // rebuild flags, one per step mod 3
     __shared__ uint32_t more[3];          // live proposals left, one per matching round mod 3
+    extern __shared__ float4 xs[];        // with LX: the positions of the current step
     const uint32_t tid = threadIdx.x, bs = blockDim.x;
     const uint32_t n = P.n;
     stage_tabs(D, T, tid);
     if (tid < 3) flag[tid] = more[tid] = 0u;
-    __syncthreads();
     int xin = st0.cur_x, lcur = st0.cur_list;
+    if constexpr (LX) {
+        const float4* __restrict__ Xg = D.x[xin];
+        for (uint32_t i = tid; i < n; i += bs) xs[i] = Xg[i];
+    }
+    __syncthreads();
     for (uint32_t k = 0; k < nsteps; ++k) {
         const unsigned long long t = t0 + k, s = t + 1;
         const int lnext = lcur == 2 ? 0 : lcur + 1;
         const bool sweep = P.nrx > 0 && (s % P.period) == 0;
         const int ake = (sweep && P.kt_kinetic) ? 1 : 0;
         if (tid == 0) flag[(k + 1) % 3] = 0u;   // last read two steps ago
-        const float4* __restrict__ X = D.x[xin];
+        const float4* __restrict__ X;
+        if constexpr (LX) X = xs;
+        else X = as_global(D.x[xin]);
+        const float4* __restrict__ U = as_global(D.u);
+        const uint2* __restrict__ XR = as_global(D.xref);
         unsigned long long ke = 0ull;
         for (uint32_t i = tid; i < n; i += bs) {
             const float4 pi = X[i];
-            const float4 ui = D.u[i];
-            const uint2 r = D.xref[i];
+            const float4 ui = U[i];
+            const uint2 r = XR[i];
             const Force3 F = force_site<EXT>(P, T, D, X, i, pi);
             float4 po;
             ke += advance_particle(P, T, D, xin, i, pi, type_of(pi), F, ui, __float_as_uint(ui.w), s, ake, po);
@@ -221,10 +258,18 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
         __syncthreads();
         xin ^= 1;
         lcur = lnext;
+        const float4* __restrict__ Xn;
+        if constexpr (LX) {
+            const float4* __restrict__ Xg = D.x[xin];
+            for (uint32_t i = tid; i < n; i += bs) xs[i] = Xg[i];
+            __syncthreads();
+            Xn = xs;
+        } else {
+            Xn = D.x[xin];
+        }
         if (flag[k % 3]) {
             // neighbour lists at x_{t+1}: cell list lcur emptied, filled,
             // then read by the build (steps without a build bin nothing)
-            const float4* __restrict__ Xn = D.x[xin];
             for (uint32_t c = tid; c < P.ncell; c += bs) D.ccount[lcur][c] = 0u;
             __syncthreads();
             for (uint32_t i = tid; i < n; i += bs) bin_particle_wg(P, D, lcur, i, Xn[i]);
@@ -233,7 +278,7 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
             __syncthreads();
         }
         if (!sweep) continue;
-        const float4* __restrict__ Xs = D.x[xin];
+        const float4* __restrict__ Xs = Xn;
         unsigned long long* const B0 = D.best[0];
         unsigned long long* const B1 = D.best[1];
         for (int slot = 0; slot < (int)P.nrx; ++slot) {

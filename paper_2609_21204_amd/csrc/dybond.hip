@@ -1585,6 +1585,16 @@ db_status run_batch(db_system* const* systems, uint32_t count, uint64_t nsteps, 
         full.push_back(g & 1u);
         order.insert(order.end(), v.begin(), v.end());
     }
+    // Positions in LDS (the LX variant of k_batch) wherever the largest
+    // system of a group fits in the LDS share its workgroup has anyway: the
+    // registers of a step let one 1024-thread workgroup, two of 512 or four
+    // of 256 share a CU.
+    std::vector<size_t> xlds(spans.size(), 0);
+    for (size_t g = 0; g < spans.size(); ++g) {
+        const size_t nmax = systems[order[spans[g].first]]->n;
+        const size_t share = (size_t)kBatchLdsTotal * threads[g] / kBatchMaxThreads;
+        if (nmax * sizeof(float4) + kBatchLdsStatic <= share) xlds[g] = nmax * sizeof(float4);
+    }
     std::vector<BatchItem> items(count);
     std::vector<BatchState> state(count);
     for (uint32_t k = 0; k < count; ++k) {
@@ -1621,6 +1631,16 @@ db_status run_batch(db_system* const* systems, uint32_t count, uint64_t nsteps, 
         for (size_t g = 1; g < spans.size(); ++g) join.push_back(R.event());
         if (!fork || !t_a || !t_b || std::find(join.begin(), join.end(), nullptr) != join.end())
             return dev_fail("event creation failed");
+        // dynamic LDS beyond the default limit for the LX variants (a
+        // runtime that needs no such opt-in may refuse the call: ignored)
+        {
+            const int most = (int)(kBatchLdsTotal - kBatchLdsStatic);
+            if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<false, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, most) != hipSuccess ||
+                hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<true, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, most) != hipSuccess)
+                (void)hipGetLastError();
+        }
         // capture: one branch per occupied group, a chain of launches each
         bool ok = hipStreamBeginCapture(s0->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
@@ -1634,12 +1654,18 @@ db_status run_batch(db_system* const* systems, uint32_t count, uint64_t nsteps, 
                     hipLaunchKernelGGL(k_batch_sort, dim3(spans[g].second), dim3(threads[g]), 0, q,
                                        (const BatchItem*)(R.items + spans[g].first),
                                        (const BatchState*)(R.state + spans[g].first));
-                    if (full[g])
-                        hipLaunchKernelGGL(k_batch<true>, dim3(spans[g].second), dim3(threads[g]), 0, q,
-                                           (const BatchItem*)(R.items + spans[g].first), R.state + spans[g].first, chunk);
+                    const BatchItem* it = R.items + spans[g].first;
+                    BatchState* sg = R.state + spans[g].first;
+                    const dim3 grid(spans[g].second), blk(threads[g]);
+                    const size_t lds = xlds[g];
+                    if (full[g] && lds)
+                        hipLaunchKernelGGL((k_batch<true, true>), grid, blk, lds, q, it, sg, chunk);
+                    else if (full[g])
+                        hipLaunchKernelGGL((k_batch<true, false>), grid, blk, 0, q, it, sg, chunk);
+                    else if (lds)
+                        hipLaunchKernelGGL((k_batch<false, true>), grid, blk, lds, q, it, sg, chunk);
                     else
-                        hipLaunchKernelGGL(k_batch<false>, dim3(spans[g].second), dim3(threads[g]), 0, q,
-                                           (const BatchItem*)(R.items + spans[g].first), R.state + spans[g].first, chunk);
+                        hipLaunchKernelGGL((k_batch<false, false>), grid, blk, 0, q, it, sg, chunk);
                     ok = hipGetLastError() == hipSuccess;
                     done += chunk;
                 }
