@@ -39,7 +39,7 @@ def parse():
     p.add_argument("--n", type=int, default=0, help="particle count for the gel workload (default 200000)")
     p.add_argument("--seed", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-steps", type=int, default=40)
+    p.add_argument("--cpu-steps", type=int, default=20)
     p.add_argument("--equilibrate", type=int, default=5000,
                    help="untimed steps from the initial state before the warm-up (the bonded state is the input)")
     p.add_argument("--tune-steps", type=int, default=200, help="steps per autotuner trial of the batch")

@@ -120,17 +120,24 @@ def test_tether_bonds_with_slip():
         assert_forces(s, o, "tether bonds")
 
 
-def test_batched_runs_with_modifiers_match_plain_runs():
+@pytest.mark.parametrize("plan", [None, [(2 ** 32 - 1, 64)]], ids=["default", "one-wave"])
+def test_batched_runs_with_modifiers_match_plain_runs(plan):
+    """The full kernel variant in the default plan (positions of each system
+    held in LDS) and with one wave per system (too little LDS per workgroup
+    for that: positions read from memory) equals db_step."""
     ws = [_small(4, slip=1.5), _small(5, melt=_melt_half_bound()),
           _small(6, bond=(db.DB_BOND_TETHER, 1.0, 0.5, 0.9, 1.1, 1.5), r_min=0.6, r_max=1.3)]
     kts = [db.DB_KT_SETPOINT, db.DB_KT_KINETIC, db.DB_KT_SETPOINT]
-    log("case batch with modifiers")
+    log(f"case batch with modifiers, plan {plan}")
     plain = [db.System.from_workload(w, kt_source=k) for w, k in zip(ws, kts)]
     batch = [db.System.from_workload(w, kt_source=k) for w, k in zip(ws, kts)]
     try:
         for p in plain:
             p.step(120)
-        db.db_step_batch([b.h for b in batch], 120)
+        if plan is None:
+            db.db_step_batch([b.h for b in batch], 120)
+        else:
+            db.db_step_batch_plan([b.h for b in batch], 120, plan)
         for k, (p, b) in enumerate(zip(plain, batch)):
             _assert_same_state(p, b, f"system {k}")
             assert counters(p)[0, 1] > 0
