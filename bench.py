@@ -307,8 +307,8 @@ def kernel_roofline(alg_bytes, avg_us):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described, not built)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
+                                   "(spatial sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     import numpy as np
     import torch
