@@ -469,8 +469,11 @@ __device__ __forceinline__ void nl_consider(const Params& P, const Dev& D, const
 // has moved by more than skin / 2, or by a renumbering) is set; the grid is
 // a few hundred workgroups, so that the launch is cheap when nothing moved
 // that far.  Reads cell list rflag[3] (filled by k_binr) and empties the
-// core cells of the other one, which the next build fills.
-__global__ __launch_bounds__(kTileThreads) void k_nlist(const Params P, const Dev D, int f3) {
+// core cells of the other one, which the next build fills.  Compiled for 8
+// waves per SIMD (56 VGPRs, four workgroups per CU; at 57 VGPRs only three
+// fit): the build's phases are latency-bound, and the fourth workgroup cut
+// its time by 11 % at 4 M and 16 M particles.
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_nlist(const Params P, const Dev D, int f3) {
     if (D.rflag[f3] == 0u) return;
     const int lst = (int)D.rflag[3];
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&D.rflag[4], 1u);   // builds so far
