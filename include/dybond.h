@@ -5,7 +5,7 @@
  *   - Langevin integration (BAOAB) of positions and velocities;
  *   - a neighbour list with a skin, rebuilt from a cell list on the steps
  *     after which some particle has moved by more than half the skin;
- *   - WCA pair forces on all pairs plus harmonic / FENE bond forces;
+ *   - WCA pair forces on all pairs plus harmonic / FENE / tether bond forces;
  *   - every `sweep_period` steps, a bonding sweep that forms and breaks
  *     dynamic bonds between partner species under per-site valence caps,
  *     consistent with the equilibrium constant K = k_on / k_off = e^eps of

@@ -1,7 +1,8 @@
 // Host side of the C ABI declared in include/dybond.h: configuration,
 // validation and rate closure (Eqs. epsilon and probs), device memory, kernel
-// launches of one time step and of the bonding sweep, graph replay of whole
-// sweep periods, and the read-out paths.
+// launches of one time step and of the bonding sweep, graph replay of any
+// number of steps (captured step, head, period, span and tail graphs), the
+// batched replicas and their autotuner, and the read-out paths.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 

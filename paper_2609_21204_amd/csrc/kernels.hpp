@@ -1,13 +1,18 @@
 // HIP kernels of the dynamic-bonding Langevin MD step (gfx950, wave64).
 //
-// Step structure (one kernel per time step, plus the sweep every n steps):
+// Step structure (three launches per time step, plus the sweep every n
+// steps):
 //
-//   k_step      forces at x_t (27-cell stencil of the cell list of x_t, WCA on
-//               every pair, static and dynamic bonds), closing half kick of the
-//               previous step, then B-A-O-A of BAOAB, wrap, and binning of
-//               x_{t+1} into the next cell list.  Forces are accumulated in
-//               64-bit fixed point, so the sum does not depend on the order in
-//               which neighbours are visited.
+//   k_step      forces at x_t (neighbour list, WCA on every listed pair,
+//               static and dynamic bonds), closing half kick of the previous
+//               step, then B-A-O-A of BAOAB, wrap, and the test whether some
+//               particle has moved more than half the skin since the last
+//               list build.  Forces are accumulated in 64-bit fixed point, so
+//               the sum does not depend on the order in which neighbours are
+//               visited.
+//   k_binr      only after a step that set that flag: x_{t+1} binned into a
+//   k_nlist     cell list, then the neighbour lists rebuilt from it (both
+//               return at once otherwise).
 //   sweep       per reaction (order redrawn every sweep, Sec. 2.3):
 //               k_propose -> (k_claim, k_kill)* -> k_finish -> k_break.
 //               The matching reproduces the sequential greedy matching in
