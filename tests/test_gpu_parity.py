@@ -127,6 +127,25 @@ def test_gel_full_size_sweep_and_sampled_forces():
         assert_forces(s, o, "gel 200k")
 
 
+def test_gel_full_size_sweep_inside_the_timed_configuration():
+    """The 200k gel as the benchmark runs it (default launch shape, graph
+    replay, renumbering every 480 steps): after 4800 steps a 120-step call
+    replays a renumbering and one span graph whose last step ends in a sweep;
+    that sweep equals the oracle's from the same positions and prior bonds,
+    bit for bit.  The bonds before the sweep come from a second system run
+    4919 steps (trajectories do not depend on how steps are split into
+    calls)."""
+    log("case gel 200k, in-step sweep at step 4920")
+    w = inputs.gel(seed=1)
+    with db.System.from_workload(w) as s, db.System.from_workload(w) as s2:
+        s.step(4800)
+        s.step(120)
+        s2.step(4919)
+        b0, c0 = s2.bonds().astype(np.int64), counters(s2)
+        o = assert_in_step_sweep(s, w, b0, c0, 4920, "gel 200k in-step sweep 4920")
+        assert len(o.dyn) > 150000
+
+
 @pytest.mark.parametrize("name", ["small", "telechelic"])
 def test_one_md_step_matches_oracle(name):
     log(f"case step/{name}")
