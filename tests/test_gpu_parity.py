@@ -132,7 +132,8 @@ def test_gel_full_size_sweep_inside_the_timed_configuration():
     replay, renumbering every 480 steps): after 4800 steps a 120-step call
     replays a renumbering and one span graph whose last step ends in a sweep;
     that sweep equals the oracle's from the same positions and prior bonds,
-    bit for bit.  The bonds before the sweep come from a second system run
+    bit for bit, and every particle's force after it is within the force
+    tolerance.  The bonds before the sweep come from a second system run
     4919 steps (trajectories do not depend on how steps are split into
     calls)."""
     log("case gel 200k, in-step sweep at step 4920")
@@ -144,6 +145,7 @@ def test_gel_full_size_sweep_inside_the_timed_configuration():
         b0, c0 = s2.bonds().astype(np.int64), counters(s2)
         o = assert_in_step_sweep(s, w, b0, c0, 4920, "gel 200k in-step sweep 4920")
         assert len(o.dyn) > 150000
+        assert_forces(s, o, "gel 200k at step 4920")      # every particle, the bonded gel
 
 
 @pytest.mark.parametrize("name", ["small", "telechelic"])
