@@ -114,15 +114,23 @@ def sweep_trials_per_particle(w):
 
 
 def host_cpu():
-    model = "unknown"
+    """Host CPU as /proc/cpuinfo names it, with the logical CPUs the OS shows
+    and those this process may run on."""
+    model, mhz = "unknown", None
     try:
         for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
+            if ln.startswith("model name") and model == "unknown":
                 model = ln.split(":", 1)[1].strip()
-                break
-    except OSError:
+            elif ln.startswith("cpu MHz") and mhz is None:
+                mhz = float(ln.split(":", 1)[1])
+    except (OSError, ValueError):
         pass
-    return model
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return (f"{model}" + (f" @ {mhz:.0f} MHz" if mhz else "")
+            + f"; {os.cpu_count()} logical CPUs visible, {usable} usable by this process")
 
 
 def cpu_baseline(w, state, steps):
