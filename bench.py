@@ -291,18 +291,26 @@ def batch_vs_plain(a, db, inputs, torch):
     }
 
 
-def other_configs(db, inputs, torch):
+def other_configs(db, inputs, torch, oracle=True):
     """The small and telechelic workloads on their own (launch-latency bound:
     absolute numbers only): small over its whole 1000-step run from the
-    initial state, telechelic over 2000 steps after 500."""
+    initial state, telechelic over 2000 steps after 500.  With `oracle`, the
+    FP64 oracle (one thread) on the same starting state: the whole 1000
+    small steps, and a 100-step window of telechelic."""
+    import numpy as np
     out = {}
-    for name, equil, steps in (("small", 0, 1000), ("telechelic", 500, 2000)):
+    for name, equil, steps, osteps in (("small", 0, 1000, 1000), ("telechelic", 500, 2000, 100)):
         w = inputs.WORKLOADS[name](seed=1)
         with db.System.from_workload(w) as s:
             s.step(equil)
+            state = (s.step_count, s.positions(), s.velocities(), s.bonds().astype(np.int64))
             dt = timed_steps(s, torch, steps)
             out[name] = {"n_particles": w.n, "steps": steps, "after_steps": equil,
                          "ms_per_step": 1000.0 * dt / steps, "particle_timesteps_per_s": w.n * steps / dt}
+        if oracle:
+            ob = cpu_baseline(w, state, osteps)
+            out[name]["oracle_particle_timesteps_per_s"] = ob["value"]
+            out[name]["oracle_sample"] = ob["sample"]
     return out
 
 
@@ -436,7 +444,7 @@ def main():
                   "T_kin": obs["T_kin"]},
     }
     if a.workload == "gel" and not a.no_other_configs:
-        line["other_configs"] = other_configs(db, inputs, torch)
+        line["other_configs"] = other_configs(db, inputs, torch, oracle=not a.no_cpu_baseline)
     if a.replicas > 0:
         line["batch"] = batch_vs_plain(a, db, inputs, torch)
     if not a.no_cpu_baseline:
