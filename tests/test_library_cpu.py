@@ -289,3 +289,26 @@ def test_enum_arguments_are_checked():
     assert lib.db_add_bond_type(s.h, 7, 1.0, 1.0, None) == db.DB_EINVAL
     assert lib.db_set_integrator(s.h, 0.005, 1.0, 1.0, 10, 2) == db.DB_EINVAL
     s.close()
+
+
+def test_header_is_plain_c_and_the_set_up_calls_work_from_c(tmp_path):
+    """include/dybond.h compiles as C99 with every warning an error, and a C
+    program linked against libdybond.so creates systems, validates them and
+    reads the resolved rates without touching a GPU (tests/c/abi_host.c);
+    the rates it prints equal the oracle's closure bit for bit."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    libdir = os.path.dirname(db.LIB_PATH)
+    exe = str(tmp_path / "abi_host")
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+           os.path.join(ROOT, "tests", "c", "abi_host.c"), "-L", libdir, "-l:libdybond.so",
+           f"-Wl,-rpath,{libdir}", "-lm", "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stderr
+    bt, rx, k_on, k_off, eps, p_on, p_off = res.stdout.split()
+    assert (int(bt), int(rx)) == (0, 0)
+    want = resolve_rates(math.nan, math.nan, 5.0, 1.0, 0.005, 10)
+    assert [float(k_on), float(k_off), float(eps), float(p_on), float(p_off)] == list(want)
