@@ -420,6 +420,54 @@ def test_largest_system_sampled_forces_and_invariants():
     log(f"largest: max |dF|/sum|F_ij| over 24 sampled particles = {worst:.2e}")
 
 
+@pytest.mark.parametrize("spacing,source", [(1.0, "setpoint"), (1.1, "setpoint"), (1.0, "kinetic")])
+def test_zero_temperature_sweeps_match_oracle(spacing, source):
+    """The kT -> 0 limit (reading R6) on the device: an A/B lattice whose
+    nearest partners sit at `spacing` from each other, swept frozen at a
+    set-point kT of 0, or with kinetic temperature and all velocities zero.
+    At spacing r0 = 1 (U_b = 0) pairs form with P0_on = 0.7 and break with
+    P0_off; at 1.1 (U_b = 0.5 > 0) nothing may form.  Bonds, counters and
+    event lists equal the oracle's."""
+    log(f"case zero temperature, spacing {spacing}, {source}")
+    m = 8
+    g = (np.arange(m, dtype=np.float64) - m / 2) * spacing
+    gx, gy, gz = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1).astype(np.float32)
+    typ = ((np.rint(gx / spacing) + np.rint(gy / spacing) + np.rint(gz / spacing)).ravel().astype(np.int64)
+           % 2).astype(np.uint32)
+    perm = np.random.default_rng(8).permutation(len(pos))
+    pos, typ = pos[perm], typ[perm]
+    n, L = len(pos), m * spacing
+    kinetic = source == "kinetic"
+    kT = 1.0 if kinetic else 0.0
+    o = OracleSystem(n, 2, L, 11)
+    with db.System(n, 2, L, 11) as s:
+        for t in range(2):
+            db.db_set_type(s.h, t, 2, 1.0, 1.0, 1.0)
+            o.set_type(t, 2, 1.0, 1.0, 1.0)
+        db.db_add_bond_type(s.h, db.DB_BOND_HARMONIC, 100.0, 1.0)
+        o.add_bond_type(BOND_HARMONIC, 100.0, 1.0)
+        db.db_set_particles(s.h, pos, np.zeros((n, 3)), typ)
+        o.set_particles(pos, np.zeros((n, 3)), typ)
+        db.db_add_reaction(s.h, db.make_reaction(0, 1, 0, 0.0, 1.2, epsilon=1.0, p_on0=0.7, self_avoid=0))
+        o.add_reaction(Reaction(0, 1, 0, 0.0, 1.2, epsilon=1.0, p_on0=0.7, self_avoid=0))
+        db.db_set_integrator(s.h, 0.005, kT, 1.0, 10, db.DB_KT_KINETIC if kinetic else db.DB_KT_SETPOINT)
+        o.set_integrator(0.005, kT, 1.0, 10, kinetic_T=kinetic)
+        db.db_commit(s.h)
+        o.commit()
+        c0 = counters(s)
+        for key in (10, 20, 30, 40, 50):
+            s.sweep_frozen(key)
+            o.sweep_frozen(key)
+            assert_same_bonds(s, o, f"zero temperature key {key}")
+        assert np.array_equal(counters(s) - c0, o.counters)
+        log(f"zero temperature: {len(o.dyn)} bonds, counters {o.counters.tolist()}")
+        if spacing == 1.0:
+            assert o.counters[0, 1] > 0 and o.counters[0, 2] > 0
+        else:
+            assert o.counters[0, 0] > 0 and o.counters[0, 1] == 0
+
+
 def test_exact_ties_on_a_lattice_match_oracle():
     """Simple cubic lattice with spacing r0 = 1 (L = 10), A/B checkerboard,
     window to 1.2: every candidate of every site lies at exactly r0, so every
