@@ -373,6 +373,45 @@ DB_API db_status db_set_state(db_system* sys, uint64_t step, const float* pos3, 
                        const uint32_t* dyn_tag_pairs, const uint32_t* dyn_bond_types,
                        uint64_t m);
 
+/* Checkpoint and exact resume.  Every random number of the method is a pure
+ * function of the seed, the step, the stream and the particle tags (Sec. 2.5:
+ * counter-based Philox keyed by step and tags), so the generator has no
+ * state of its own; the dynamic state is the step counter, positions, the
+ * velocity the integrator carries between steps (BAOAB: the velocity after
+ * the second half drift, before the next step's closing half kick), periodic
+ * image counters, the dynamic bonds and the cumulative attempt / form /
+ * break counters.  A system restored from a checkpoint continues bit for
+ * bit as the saved one would have (positions, velocities, bonds, counters
+ * and sweep events), also under db_step_batch.  db_set_state cannot promise
+ * that: it takes full-step velocities, from which the carried velocity is
+ * recomputed in FP32 (v - h F / m), which can differ from the saved one in
+ * its last bit.
+ *
+ * db_save_checkpoint writes the state of a committed system into buf (the
+ * caller's host memory, `cap` bytes) and sets *size to the checkpoint's size
+ * (48 + 24 reactions + 36 n + 12 m bytes for m dynamic bonds); with cap <
+ * *size nothing is written and DB_ETRUNC is returned (buf may then be NULL,
+ * which makes cap = 0 a size query).  The bytes are self-contained: a header
+ * (magic, format version, n, reactions, step, m, a fingerprint of the
+ * set-up, a hash of the payload), then the counters, positions, carried
+ * velocities and images in tag order, and the bond table; little-endian.
+ * Errors: DB_EINVAL (size NULL, buf NULL with cap >= *size), DB_ESTATE,
+ * DB_ETRUNC, DB_EDEVICE.
+ *
+ * db_load_checkpoint replaces the dynamic state of a committed system that
+ * was set up with the same calls (n, box, seed, types, particle types,
+ * static bonds, bond types, reactions, rate modifiers, integrator settings;
+ * launch shapes, neighbour-list and matching settings may differ), as
+ * db_set_state does: lists are rebuilt, no sweep has run on the new state
+ * (db_read_sweep_events reports none), the bond reference of
+ * db_bond_correlation is kept.  Also allowed on a system left invalid by an
+ * error.  Errors: DB_EINVAL (buf NULL, wrong magic or version, a different
+ * n, reaction count or set-up, a size that does not match the header, a
+ * damaged payload, an invalid state as for db_set_state), DB_ESTATE (not
+ * committed), DB_EOVERFLOW / DB_EBOND (as db_set_state), DB_EDEVICE. */
+DB_API db_status db_save_checkpoint(db_system* sys, void* buf, uint64_t cap, uint64_t* size);
+DB_API db_status db_load_checkpoint(db_system* sys, const void* buf, uint64_t size);
+
 /* Positions pos3[3n] in [-L/2, L/2) (tag order, caller's buffer);
  * image3[3n] (may be NULL) receives the periodic image counters.  Before
  * db_commit: the positions given to db_set_particles (images 0), no GPU

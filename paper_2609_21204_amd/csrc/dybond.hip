@@ -667,9 +667,11 @@ void fill_params(db_system* s) {
 }
 
 // Upload positions/velocities (tag order) and dynamic bonds; rebuild derived
-// device state (cell list, u = v - h F/m).
+// device state (cell list, u = v - h F/m).  With `vel_is_u` the velocities
+// are already the integrator's carried velocity u (a checkpoint), stored as
+// given; img3 (tag order, NULL = zeros) sets the periodic image counters.
 db_status upload_state(db_system* s, const float* pos3, const float* vel3, const uint32_t* pairs,
-                       const uint32_t* bts, uint64_t m) {
+                       const uint32_t* bts, uint64_t m, bool vel_is_u = false, const int32_t* img3 = nullptr) {
     const uint32_t n = s->n;
     if (s->tags_dirty) {
         HIPCHK(s, hipMemcpyAsync(s->tag_h.data(), s->D.tag, n * 4, hipMemcpyDeviceToHost, s->stream));
@@ -708,6 +710,9 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
         occ[ib]++;
     }
     std::vector<int32_t> img(3 * (size_t)n, 0);
+    if (img3)
+        for (uint32_t i = 0; i < n; ++i)
+            for (uint32_t d = 0; d < 3; ++d) img[(size_t)d * n + i] = img3[3 * (size_t)s->tag_h[i] + d];
     HIPCHK(s, hipMemcpyAsync(s->D.x[0], xs.data(), n * sizeof(float4), hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->D.x[1], xs.data(), n * sizeof(float4), hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->D.u, vs.data(), n * sizeof(float4), hipMemcpyHostToDevice, s->stream));
@@ -733,7 +738,7 @@ db_status upload_state(db_system* s, const float* pos3, const float* vel3, const
     LAUNCH(s, k_binr, grid_of(n), kBlock, s->P, s->D, s->cur_x, (int)(s->step % 3));
     LAUNCH(s, k_nlist, ntiles(P), kTileThreads, s->P, s->D, (int)(s->step % 3));
     LAUNCH(s, k_eval, grid_of(n), kBlock, s->P, s->D, s->cur_x, 0u);
-    LAUNCH(s, k_init_u, grid_of(n), kBlock, s->P, s->D, s->cur_x, 0u);
+    if (!vel_is_u) LAUNCH(s, k_init_u, grid_of(n), kBlock, s->P, s->D, s->cur_x, 0u);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipStreamSynchronize(s->stream));
     uint32_t err[4];
@@ -1050,6 +1055,92 @@ db_status ready(db_system* s) {
     if (s->dead) return fail(s, DB_EDEVICE, "device error earlier on this handle");
     if (!s->committed) return fail(s, DB_ESTATE, "system not committed");
     if (s->invalid) return fail(s, DB_ESTATE, "state invalid after an error; call db_set_state");
+    return DB_OK;
+}
+
+// Checks shared by db_set_state and db_load_checkpoint: positions inside the
+// box, and dynamic bonds that a reaction of the system could have made
+// (matching types, distinct tags, valences held, each pair once).
+db_status check_state(db_system* s, const float* pos3, const uint32_t* pairs, const uint32_t* bts,
+                             uint64_t m) {
+    const float half = (float)(0.5 * s->L);
+    for (size_t k = 0; k < 3 * (size_t)s->n; ++k)
+        if (!(pos3[k] >= -half && pos3[k] < half)) return fail(s, DB_EINVAL, "position %zu outside [-L/2, L/2)", k / 3);
+    std::vector<int> bt2rx(s->bonds.size(), -1);
+    for (size_t a = 0; a < s->rx.size(); ++a) bt2rx[s->rx[a].bond_type] = (int)a;
+    std::vector<uint32_t> occ(s->n, 0);
+    std::vector<uint64_t> keys;
+    keys.reserve(m);
+    for (uint64_t k = 0; k < m; ++k) {
+        uint32_t a = pairs[2 * k], b = pairs[2 * k + 1];
+        if (a >= s->n || b >= s->n || a == b) return fail(s, DB_EINVAL, "dynamic bond %llu: bad tags", (unsigned long long)k);
+        if (bts[k] >= bt2rx.size() || bt2rx[bts[k]] < 0)
+            return fail(s, DB_EINVAL, "dynamic bond %llu: bond type is not a reaction's", (unsigned long long)k);
+        const auto& d = s->rx[bt2rx[bts[k]]];
+        const uint32_t ta = s->type[a], tb = s->type[b];
+        if (!((ta == d.type_a && tb == d.type_b) || (ta == d.type_b && tb == d.type_a)))
+            return fail(s, DB_EINVAL, "dynamic bond %llu: types do not match its reaction", (unsigned long long)k);
+        if (++occ[a] > s->types[ta].valence || ++occ[b] > s->types[tb].valence)
+            return fail(s, DB_EINVAL, "dynamic bond %llu exceeds a valence", (unsigned long long)k);
+        keys.push_back(((uint64_t)std::min(a, b) << 32) | std::max(a, b));
+    }
+    std::sort(keys.begin(), keys.end());
+    if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) return fail(s, DB_EINVAL, "duplicate dynamic bond");
+    return DB_OK;
+}
+
+// ---------------------------------------------------------------- checkpoints
+// Layout (little-endian): a 48-byte header {magic, version, n, reactions,
+// step, dynamic bonds m, configuration fingerprint, payload hash}, then the
+// payload: cumulative counters (3 x reactions uint64: attempts, forms,
+// breaks), positions (3n float, tag order), the integrator's carried
+// velocities u (3n float), periodic image counters (3n int32), the bond pairs
+// (2m uint32, tag_lo < tag_hi) and their bond types (m uint32).
+constexpr uint32_t kCkptMagic = 0x4B434244u;   // "DBCK"
+constexpr uint32_t kCkptVersion = 1u;
+constexpr uint64_t kCkptHeader = 48;
+
+struct Fnv {
+    uint64_t h = 0xcbf29ce484222325ull;
+    void bytes(const void* p, size_t k) {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t i = 0; i < k; ++i) { h ^= c[i]; h *= 0x100000001b3ull; }
+    }
+    template <class T> void val(T v) { bytes(&v, sizeof v); }
+};
+
+// Everything set up before db_commit (and the integrator settings) that the
+// trajectory depends on; launch shapes, the list skin, cell capacity, the
+// matching schedule and renumbering do not change results and are left out.
+uint64_t config_fingerprint(const db_system* s) {
+    Fnv f;
+    f.val(s->n); f.val(s->ntypes); f.val(s->L); f.val(s->seed);
+    for (const auto& t : s->types) { f.val(t.valence); f.val(t.sigma); f.val(t.eps); f.val(t.mass); }
+    for (const auto& b : s->bonds) {
+        f.val((int32_t)b.kind); f.val(b.k); f.val(b.r0); f.val(b.lmin); f.val(b.lc1); f.val(b.lc0); f.val(b.lmax);
+    }
+    for (const auto& r : s->rx) {
+        f.val(r.type_a); f.val(r.type_b); f.val(r.bond_type); f.val(r.r_min); f.val(r.r_max);
+        f.val(r.k_on); f.val(r.k_off); f.val(r.epsilon); f.val(r.p_on0); f.val(r.self_avoid);
+    }
+    for (const auto& md : s->mods) { f.val((int32_t)md.kind); f.val(md.lam); f.val(md.tm); f.val(md.k_on_m); f.val(md.k_off_m); f.val(md.a); }
+    f.bytes(s->type.data(), s->type.size() * 4);
+    f.bytes(s->stat_pairs.data(), s->stat_pairs.size() * 4);
+    f.bytes(s->stat_bt.data(), s->stat_bt.size() * 4);
+    f.val(s->dt); f.val(s->kT); f.val(s->gamma); f.val(s->period); f.val((int32_t)s->kt_source);
+    return f.h;
+}
+
+uint64_t ckpt_size(uint32_t n, uint32_t nrx, uint64_t m) {
+    return kCkptHeader + 24ull * nrx + 36ull * n + 12ull * m;
+}
+
+db_status sync_tags(db_system* s) {
+    if (!s->tags_dirty) return DB_OK;
+    HIPCHK(s, hipMemcpyAsync(s->tag_h.data(), s->D.tag, s->n * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->rtag_h.data(), s->D.rtag, s->n * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->tags_dirty = false;
     return DB_OK;
 }
 
@@ -1851,35 +1942,132 @@ db_status db_set_state(db_system* s, uint64_t step, const float* pos3, const flo
     if (s->dead) return fail(s, DB_EDEVICE, "device error earlier on this handle");
     if (!s->committed) return fail(s, DB_ESTATE, "system not committed");
     if (!pos3 || !vel3 || (m && (!pairs || !bts))) return fail(s, DB_EINVAL, "NULL arrays");
-    const float half = (float)(0.5 * s->L);
-    for (size_t k = 0; k < 3 * (size_t)s->n; ++k)
-        if (!(pos3[k] >= -half && pos3[k] < half)) return fail(s, DB_EINVAL, "position %zu outside [-L/2, L/2)", k / 3);
-    std::vector<int> bt2rx(s->bonds.size(), -1);
-    for (size_t a = 0; a < s->rx.size(); ++a) bt2rx[s->rx[a].bond_type] = (int)a;
-    std::vector<uint32_t> occ(s->n, 0);
-    std::vector<uint64_t> keys;
-    keys.reserve(m);
-    for (uint64_t k = 0; k < m; ++k) {
-        uint32_t a = pairs[2 * k], b = pairs[2 * k + 1];
-        if (a >= s->n || b >= s->n || a == b) return fail(s, DB_EINVAL, "dynamic bond %llu: bad tags", (unsigned long long)k);
-        if (bts[k] >= bt2rx.size() || bt2rx[bts[k]] < 0)
-            return fail(s, DB_EINVAL, "dynamic bond %llu: bond type is not a reaction's", (unsigned long long)k);
-        const auto& d = s->rx[bt2rx[bts[k]]];
-        const uint32_t ta = s->type[a], tb = s->type[b];
-        if (!((ta == d.type_a && tb == d.type_b) || (ta == d.type_b && tb == d.type_a)))
-            return fail(s, DB_EINVAL, "dynamic bond %llu: types do not match its reaction", (unsigned long long)k);
-        if (++occ[a] > s->types[ta].valence || ++occ[b] > s->types[tb].valence)
-            return fail(s, DB_EINVAL, "dynamic bond %llu exceeds a valence", (unsigned long long)k);
-        keys.push_back(((uint64_t)std::min(a, b) << 32) | std::max(a, b));
-    }
-    std::sort(keys.begin(), keys.end());
-    if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) return fail(s, DB_EINVAL, "duplicate dynamic bond");
+    db_status st = check_state(s, pos3, pairs, bts, m);
+    if (st != DB_OK) return st;
     HIPCHK(s, hipSetDevice(s->device));
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    db_status st = ensure_cell_capacity(s, pos3);
+    st = ensure_cell_capacity(s, pos3);
     if (st != DB_OK) return st;
     s->step = step;
     return upload_state(s, pos3, vel3, pairs, bts, m);
+}
+
+db_status db_save_checkpoint(db_system* s, void* buf, uint64_t cap, uint64_t* size) {
+    db_status st = ready(s);
+    if (st != DB_OK) return st;
+    if (!size) return fail(s, DB_EINVAL, "size is NULL");
+    HIPCHK(s, hipSetDevice(s->device));
+    const uint32_t n = s->n, nrx = (uint32_t)s->rx.size();
+    const unsigned nb = grid_of(n);
+    LAUNCH(s, k_rows_count, nb, kBlock, s->P, s->D, s->cur_x, s->bsum);
+    LAUNCH(s, k_scan_bsum, 1, 1024, s->bsum, nb);
+    uint32_t m = 0;
+    HIPCHK(s, hipMemcpyAsync(&m, s->bsum + nb, 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *size = ckpt_size(n, nrx, m);
+    if (*size > cap) return fail(s, DB_ETRUNC, "checkpoint of %llu bytes, capacity %llu",
+                                 (unsigned long long)*size, (unsigned long long)cap);
+    if (!buf) return fail(s, DB_EINVAL, "buf is NULL");
+    std::vector<uint32_t> pairs(2 * (size_t)m), bts(m);
+    uint64_t m2 = 0;
+    if (m) {
+        st = db_read_bonds(s, pairs.data(), bts.data(), m, &m2);
+        if (st != DB_OK) return st;
+        if (m2 != m) return fail(s, DB_EDEVICE, "bond count changed during the checkpoint");
+    }
+    std::vector<float4> xh(n), uh(n);
+    std::vector<int32_t> ih(3 * (size_t)n);
+    std::vector<unsigned long long> slots((size_t)3 * kMaxRx * kCtrSlots);
+    HIPCHK(s, hipMemcpyAsync(xh.data(), s->D.x[s->cur_x], n * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(uh.data(), s->D.u, n * sizeof(float4), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(ih.data(), s->D.img, ih.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(slots.data(), s->D.counters, slots.size() * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s->stream));
+    st = check_errors(s);
+    if (st != DB_OK) return st;
+    st = sync_tags(s);
+    if (st != DB_OK) return st;
+    std::vector<uint64_t> ctr(3 * (size_t)nrx, 0);
+    for (size_t c = 0; c < ctr.size(); ++c)
+        for (uint32_t w = 0; w < kCtrSlots; ++w) ctr[c] += slots[c * kCtrSlots + w];
+    std::vector<float> pos(3 * (size_t)n), vel(3 * (size_t)n);
+    std::vector<int32_t> img(3 * (size_t)n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const size_t t = s->tag_h[i];
+        pos[3 * t] = xh[i].x; pos[3 * t + 1] = xh[i].y; pos[3 * t + 2] = xh[i].z;
+        vel[3 * t] = uh[i].x; vel[3 * t + 1] = uh[i].y; vel[3 * t + 2] = uh[i].z;
+        for (uint32_t d = 0; d < 3; ++d) img[3 * t + d] = ih[(size_t)d * n + i];
+    }
+    unsigned char* o = (unsigned char*)buf + kCkptHeader;
+    auto put = [&](const void* p, size_t k) { std::memcpy(o, p, k); o += k; };
+    put(ctr.data(), ctr.size() * 8);
+    put(pos.data(), pos.size() * 4);
+    put(vel.data(), vel.size() * 4);
+    put(img.data(), img.size() * 4);
+    put(pairs.data(), pairs.size() * 4);
+    put(bts.data(), bts.size() * 4);
+    Fnv ph;
+    ph.bytes((const unsigned char*)buf + kCkptHeader, *size - kCkptHeader);
+    unsigned char* h = (unsigned char*)buf;
+    const uint32_t hw[4] = {kCkptMagic, kCkptVersion, n, nrx};
+    const uint64_t hq[4] = {s->step, (uint64_t)m, config_fingerprint(s), ph.h};
+    std::memcpy(h, hw, sizeof hw);
+    std::memcpy(h + sizeof hw, hq, sizeof hq);
+    return DB_OK;
+}
+
+db_status db_load_checkpoint(db_system* s, const void* buf, uint64_t size) {
+    if (!s) return DB_EINVAL;
+    if (s->dead) return fail(s, DB_EDEVICE, "device error earlier on this handle");
+    if (!s->committed) return fail(s, DB_ESTATE, "system not committed");
+    if (!buf) return fail(s, DB_EINVAL, "buf is NULL");
+    if (size < kCkptHeader) return fail(s, DB_EINVAL, "checkpoint shorter than its header");
+    uint32_t hw[4];
+    uint64_t hq[4];
+    std::memcpy(hw, buf, sizeof hw);
+    std::memcpy(hq, (const unsigned char*)buf + sizeof hw, sizeof hq);
+    if (hw[0] != kCkptMagic) return fail(s, DB_EINVAL, "not a checkpoint");
+    if (hw[1] != kCkptVersion) return fail(s, DB_EINVAL, "checkpoint version %u, expected %u", hw[1], kCkptVersion);
+    const uint32_t n = s->n, nrx = (uint32_t)s->rx.size();
+    if (hw[2] != n || hw[3] != nrx)
+        return fail(s, DB_EINVAL, "checkpoint of %u particles and %u reactions, system has %u and %u", hw[2], hw[3], n, nrx);
+    const uint64_t m = hq[1];
+    if (m > (uint64_t)n * kMaxValence || size != ckpt_size(n, nrx, m))
+        return fail(s, DB_EINVAL, "checkpoint size %llu does not match its header", (unsigned long long)size);
+    if (hq[2] != config_fingerprint(s))
+        return fail(s, DB_EINVAL, "checkpoint of a system set up differently (types, bonds, reactions, integrator)");
+    Fnv ph;
+    ph.bytes((const unsigned char*)buf + kCkptHeader, size - kCkptHeader);
+    if (ph.h != hq[3]) return fail(s, DB_EINVAL, "checkpoint payload damaged (hash mismatch)");
+    const unsigned char* c = (const unsigned char*)buf + kCkptHeader;
+    auto take = [&](void* p, size_t k) { std::memcpy(p, c, k); c += k; };
+    std::vector<uint64_t> ctr(3 * (size_t)nrx);
+    std::vector<float> pos(3 * (size_t)n), vel(3 * (size_t)n);
+    std::vector<int32_t> img(3 * (size_t)n);
+    std::vector<uint32_t> pairs(2 * (size_t)m), bts(m);
+    take(ctr.data(), ctr.size() * 8);
+    take(pos.data(), pos.size() * 4);
+    take(vel.data(), vel.size() * 4);
+    take(img.data(), img.size() * 4);
+    take(pairs.data(), pairs.size() * 4);
+    take(bts.data(), bts.size() * 4);
+    db_status st = check_state(s, pos.data(), pairs.data(), bts.data(), m);
+    if (st != DB_OK) return st;
+    HIPCHK(s, hipSetDevice(s->device));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    st = ensure_cell_capacity(s, pos.data());
+    if (st != DB_OK) return st;
+    const uint64_t step_before = s->step;
+    s->step = hq[0];
+    st = upload_state(s, pos.data(), vel.data(), pairs.data(), bts.data(), m, true, img.data());
+    if (st != DB_OK) { s->step = step_before; return st; }
+    // cumulative counters: each total in the first slot of its spread
+    std::vector<unsigned long long> slots((size_t)3 * kMaxRx * kCtrSlots, 0ull);
+    for (size_t k = 0; k < ctr.size(); ++k) slots[k * kCtrSlots] = ctr[k];
+    HIPCHK(s, hipMemcpyAsync(s->D.counters, slots.data(), slots.size() * sizeof(unsigned long long),
+                             hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return DB_OK;
 }
 
 // Before db_commit the read-outs of positions and velocities return the

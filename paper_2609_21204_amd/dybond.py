@@ -95,6 +95,8 @@ _SIGS = {
     "db_batch_autotune": (_I, [_P, _U32, _U32, ctypes.POINTER(BatchPlan), ctypes.POINTER(_U64), _P, _U32]),
     "db_sweep_frozen": (_I, [_P, _U64]),
     "db_set_state": (_I, [_P, _U64, _P, _P, _P, _P, _U64]),
+    "db_save_checkpoint": (_I, [_P, _P, _U64, ctypes.POINTER(_U64)]),
+    "db_load_checkpoint": (_I, [_P, _P, _U64]),
     "db_read_positions": (_I, [_P, _P, _P]),
     "db_read_velocities": (_I, [_P, _P]),
     "db_read_forces": (_I, [_P, _P]),
@@ -365,6 +367,22 @@ def db_set_state(h, step, pos, vel, dyn_pairs=None, dyn_bond_types=None):
     a, ap = _buf(pairs, np.uint32)
     b, bp = _buf(bts, np.uint32)
     _check(h, load().db_set_state(h, step, pp, vp, ap, bp, len(b)))
+
+
+def db_save_checkpoint(h):
+    """The system's checkpoint as bytes (size query, then the copy)."""
+    size = _U64()
+    st = load().db_save_checkpoint(h, None, 0, ctypes.byref(size))
+    if st not in (DB_OK, DB_ETRUNC):
+        _check(h, st)
+    buf = ctypes.create_string_buffer(size.value)
+    _check(h, load().db_save_checkpoint(h, ctypes.cast(buf, _P), size.value, ctypes.byref(size)))
+    return buf.raw[:size.value]
+
+
+def db_load_checkpoint(h, data):
+    buf = ctypes.create_string_buffer(bytes(data), len(data))
+    _check(h, load().db_load_checkpoint(h, ctypes.cast(buf, _P), len(data)))
 
 
 def db_read_positions(h, n, with_images=False):
@@ -657,6 +675,12 @@ class System:
 
     def set_state(self, step, pos, vel, pairs=None, bts=None):
         db_set_state(self.h, step, pos, vel, pairs, bts)
+
+    def save_checkpoint(self):
+        return db_save_checkpoint(self.h)
+
+    def load_checkpoint(self, data):
+        db_load_checkpoint(self.h, data)
 
     @property
     def step_count(self):

@@ -239,6 +239,9 @@ def test_validation_errors_on_host():
         assert _status_of(lambda: db.db_set_particles(s.h, [[0, 0, 0], [1.0, 0, 0]], np.zeros((2, 3)), [0, 2])) == "DB_EINVAL"
         assert _status_of(lambda: db.db_set_type(s.h, 0, 9, 1.0, 1.0, 1.0)) == "DB_EINVAL"
         assert _status_of(lambda: db.db_step(s.h, 1)) == "DB_ESTATE"
+        # checkpoints exist only for committed systems
+        assert _status_of(lambda: db.db_save_checkpoint(s.h)) == "DB_ESTATE"
+        assert _status_of(lambda: db.db_load_checkpoint(s.h, bytes(48))) == "DB_ESTATE"
         # matching schedule: 1..8 grid rounds, LDS finish of at most 256 proposals
         assert _status_of(lambda: db.db_set_matching(s.h, 0, 256)) == "DB_EINVAL"
         assert _status_of(lambda: db.db_set_matching(s.h, 9, 256)) == "DB_EINVAL"
