@@ -164,3 +164,31 @@ def test_batch_mixing_lean_and_full_systems():
     finally:
         for x in plain + batch:
             x.close()
+
+
+@pytest.mark.parametrize("shape", [(4, 0), (4, 4)])
+def test_step_shapes_with_modifiers_and_the_kinetic_temperature(shape):
+    """Four threads per particle (each particle's four threads integrate it
+    together, one coordinate per thread) against the automatic shape of
+    these small systems: the full kernel variant with melting under the
+    kinetic temperature (the step that ends in a sweep sums m v^2) and with
+    tether + slip bonds, and the lean variant under the kinetic temperature;
+    trajectories bit for bit."""
+    cases = [(_small(5, melt=_melt_half_bound()), db.DB_KT_KINETIC),
+             (_small(6, bond=(db.DB_BOND_TETHER, 1.0, 0.5, 0.9, 1.1, 1.5), r_min=0.6, r_max=1.3, slip=2.0),
+              db.DB_KT_SETPOINT),
+             (inputs.small(seed=7), db.DB_KT_KINETIC)]
+    for k, (w, kt) in enumerate(cases):
+        log(f"case step shape {shape} with modifiers, system {k}")
+        ref = db.System.from_workload(w, kt_source=kt)
+        alt = db.System.from_workload(w, kt_source=kt)
+        try:
+            db.db_set_step_shape(alt.h, *shape)
+            assert db.db_get_step_shape(ref.h)[0] != 4
+            ref.step(150)
+            alt.step(150)
+            _assert_same_state(ref, alt, f"system {k}, shape {shape}")
+            assert counters(ref)[0, 1] > 0
+        finally:
+            ref.close()
+            alt.close()
