@@ -99,9 +99,16 @@ __device__ __forceinline__ Force3 force_site(const Params& P, const StepTabs& T,
     for (int q = 0; q < QL; ++q) pj[q] = X[(uint32_t)q < m ? nb[q] : i];
 #pragma unroll
     for (int q = 0; q < QB; ++q) pb[q] = X[bw[q] != kEmpty ? (bw[q] & kIdxMask) : i];
+    // Pairs that need the FP64 evaluation (near the cutoff, across the
+    // boundary) are marked and evaluated after the others: a wave then runs
+    // as many FP64 evaluations as its busiest lane has, instead of one for
+    // every list entry at which any of its lanes needs one.  (Entries from
+    // the 33rd on are evaluated at once.)  The sum is exact, so the order
+    // does not change the force.
+    uint32_t defer = 0u;
 #pragma unroll
     for (int q = 0; q < QL; ++q)
-        if ((uint32_t)q < m) pair_force_tab(P, T, D.err, pi, pj[q], ti, fx, fy, fz);
+        if ((uint32_t)q < m && !pair_force_f32(P, T, D.err, pi, pj[q], ti, fx, fy, fz)) defer |= 1u << q;
     for (uint32_t k0 = QL; k0 < m; k0 += 8) {
         uint32_t nx[8];
         float4 px[8];
@@ -110,8 +117,20 @@ __device__ __forceinline__ Force3 force_site(const Params& P, const StepTabs& T,
 #pragma unroll
         for (int q = 0; q < 8; ++q) px[q] = X[nx[q]];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (k0 + (uint32_t)q < m) pair_force_tab(P, T, D.err, pi, px[q], ti, fx, fy, fz);
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t k = k0 + (uint32_t)q;
+            if (k < m && !pair_force_f32(P, T, D.err, pi, px[q], ti, fx, fy, fz)) {
+                if (k < 32u) defer |= 1u << k;
+                else pair_force_f64(P, T, D.err, pi, px[q], ti, fx, fy, fz);
+            }
+        }
+    }
+    while (defer) {
+        const uint32_t k = (uint32_t)__builtin_ctz(defer);
+        defer &= defer - 1u;
+        const uint32_t j = k >= (uint32_t)QL ? nl[(size_t)k * n + i]
+                                             : (k == 0u ? nb[0] : (k == 1u ? nb[1] : (k == 2u ? nb[2] : nb[3])));
+        pair_force_f64(P, T, D.err, pi, X[j], ti, fx, fy, fz);
     }
     auto bond = [&](uint32_t b, uint32_t w, float4 pw) {
         const uint32_t j = w & kIdxMask;
@@ -191,6 +210,76 @@ __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T
     D.xref[i] = xref_pack(P, pi);
 }
 
+// The same build for the variant that holds the positions in LDS (xs): a
+// cell's member slots then carry only the particle index (4 bytes instead of
+// a 16-byte position record), and each candidate's position is read from
+// LDS, so the build reads a quarter of the bytes from memory.  bin_index_wg
+// fills such a list.
+__device__ __forceinline__ void bin_index_wg(const Params& P, const Dev& D, int lst, uint32_t i, float4 p) {
+    const int c = (cell_coord(p.z, P) * (int)P.nc + cell_coord(p.y, P)) * (int)P.nc + cell_coord(p.x, P);
+    const uint32_t slot = wg_atomic_add(as_global(D.ccount[lst]) + c, 1u);
+    if (slot < P.cellcap) as_global(reinterpret_cast<uint32_t*>(D.cpos[lst]))[cell_slot(P, (uint32_t)c, slot)] = i;
+    else atomicOr(&D.err[0], kErrOverflow);
+}
+
+__device__ __forceinline__ void nl_build_site_lds(const Params& P, const StepTabs& T, const Dev& D, int lst,
+                                                  uint32_t i, float4 pi, const float4* __restrict__ xs) {
+    const uint32_t* __restrict__ cnt = as_global(D.ccount[lst]);
+    const uint32_t* __restrict__ ci = as_global(reinterpret_cast<const uint32_t*>(D.cpos[lst]));
+    uint32_t* __restrict__ nl = as_global(D.nl);
+    const int nc = (int)P.nc;
+    const int cx = cell_coord(pi.x, P), cy = cell_coord(pi.y, P), cz = cell_coord(pi.z, P);
+    const float* rrow = T.rl2 + type_of(pi) * kMaxTypes;
+    const uint32_t cap = P.cellcap;
+    uint32_t m = 0;
+    auto consider = [&](uint32_t j) {
+        if (j == i) return;
+        const float4 q = xs[j];
+        const float dx = mi_delta_f(pi.x, q.x, P), dy = mi_delta_f(pi.y, q.y, P), dz = mi_delta_f(pi.z, q.z, P);
+        if (dx * dx + dy * dy + dz * dz < rrow[type_of(q)]) {
+            if (m < P.nlmax) nl[(size_t)m * P.n + i] = j;
+            ++m;
+        }
+    };
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {                 // z layer oz = g - 1
+        uint32_t cell[9], off[10];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int ox = q % 3 - 1, oy = q / 3 - 1;
+            cell[q] = (uint32_t)((wrapc(cz + g - 1, nc) * nc + wrapc(cy + oy, nc)) * nc + wrapc(cx + ox, nc));
+        }
+        uint32_t cn[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) cn[q] = min(cnt[cell[q]], cap);
+        off[0] = 0u;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) off[q + 1] = off[q] + cn[q];
+        const uint32_t total = off[9];
+        for (uint32_t k0 = 0; k0 < total; k0 += 8) {
+            uint32_t e8[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t idx = min(k0 + (uint32_t)e, total - 1u);
+                uint32_t c = cell[0], o = 0u;
+#pragma unroll
+                for (int q = 1; q < 9; ++q)
+                    if (idx >= off[q]) {
+                        c = cell[q];
+                        o = off[q];
+                    }
+                e8[e] = ci[cell_slot(P, c, idx - o)];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (k0 + (uint32_t)e < total) consider(e8[e]);
+        }
+    }
+    if (m > P.nlmax) atomicOr(&D.err[0], kErrNlist);
+    as_global(D.nl_cnt)[i] = m < P.nlmax ? m : P.nlmax;
+    as_global(D.xref)[i] = xref_pack(P, pi);
+}
+
 // n steps of system blockIdx.x.  Per step, as db_step: forces at x_t + BAOAB
 // (x_{t+1} is binned and the list rebuilt right after a step that moved
 // some particle by more than skin / 2), and the bonding sweep at s = t + 1
@@ -205,8 +294,9 @@ __device__ __forceinline__ void nl_build_site(const Params& P, const StepTabs& T
 // LDS of n float4) after every step, and the force, list and sweep passes
 // gather neighbour and partner positions from there: a thread walks its
 // particles one after another, and each neighbour gather that comes from
-// LDS instead of memory shortens that chain by a memory round trip.  The
-// copy is exact, so both variants give the same result.
+// LDS instead of memory shortens that chain by a memory round trip.  Its
+// cell lists hold indices only (nl_build_site_lds).  The copy is exact, so
+// both variants give the same result.
 template <bool EXT, bool LX>
 __global__ __launch_bounds__(kBatchMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state, uint32_t nsteps) {
@@ -272,9 +362,15 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
             // then read by the build (steps without a build bin nothing)
             for (uint32_t c = tid; c < P.ncell; c += bs) D.ccount[lcur][c] = 0u;
             __syncthreads();
-            for (uint32_t i = tid; i < n; i += bs) bin_particle_wg(P, D, lcur, i, Xn[i]);
-            __syncthreads();
-            for (uint32_t i = tid; i < n; i += bs) nl_build_site(P, T, D, lcur, i, Xn[i]);
+            if constexpr (LX) {
+                for (uint32_t i = tid; i < n; i += bs) bin_index_wg(P, D, lcur, i, Xn[i]);
+                __syncthreads();
+                for (uint32_t i = tid; i < n; i += bs) nl_build_site_lds(P, T, D, lcur, i, Xn[i], xs);
+            } else {
+                for (uint32_t i = tid; i < n; i += bs) bin_particle_wg(P, D, lcur, i, Xn[i]);
+                __syncthreads();
+                for (uint32_t i = tid; i < n; i += bs) nl_build_site(P, T, D, lcur, i, Xn[i]);
+            }
             __syncthreads();
         }
         if (!sweep) continue;

@@ -792,7 +792,9 @@ __device__ __forceinline__ void stage_tabs(const Dev& D, StepTabs& T, uint32_t t
 // 2 (sigma/r)^6 - 1 > 0.12, no cancellation) are evaluated in FP32.  Pairs
 // near the cutoff and pairs across the boundary are screened in FP32 and
 // evaluated in FP64 with the oracle's cutoff test r < 2^(1/6) sigma_ij.
-__device__ __forceinline__ void pair_force_tab(const Params& P, const StepTabs& T, uint32_t* err, float4 pi,
+// pair_force_f32 takes the screen and the FP32 evaluation and returns false
+// for a pair that still needs pair_force_f64; pair_force_tab runs both.
+__device__ __forceinline__ bool pair_force_f32(const Params& P, const StepTabs& T, uint32_t* err, float4 pi,
                                                float4 pj, uint32_t ti, long long& fx, long long& fy,
                                                long long& fz) {
 #pragma clang fp contract(off)
@@ -801,7 +803,7 @@ __device__ __forceinline__ void pair_force_tab(const Params& P, const StepTabs& 
     float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
     if (fabsf(dx) <= P.halfLf && fabsf(dy) <= P.halfLf && fabsf(dz) <= P.halfLf) {
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        if (r2 >= rc2p) return;
+        if (r2 >= rc2p) return true;
         if (r2 < T.rc2_in[pt]) {
             const float ir2 = __builtin_amdgcn_rcpf(r2);
             const float sr2 = T.sig2f[pt] * ir2;
@@ -810,15 +812,22 @@ __device__ __forceinline__ void pair_force_tab(const Params& P, const StepTabs& 
             fx -= to_fix((double)(f * dx), err);
             fy -= to_fix((double)(f * dy), err);
             fz -= to_fix((double)(f * dz), err);
-            return;
+            return true;
         }
     } else {
         dx = mi_delta_f(pi.x, pj.x, P);
         dy = mi_delta_f(pi.y, pj.y, P);
         dz = mi_delta_f(pi.z, pj.z, P);
-        if (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) >= rc2p) return;
+        if (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) >= rc2p) return true;
     }
-    const PairTab& pp = T.pair[pt];
+    return false;
+}
+
+__device__ __forceinline__ void pair_force_f64(const Params& P, const StepTabs& T, uint32_t* err, float4 pi,
+                                               float4 pj, uint32_t ti, long long& fx, long long& fy,
+                                               long long& fz) {
+#pragma clang fp contract(off)
+    const PairTab& pp = T.pair[(int)ti * kMaxTypes + (int)type_of(pj)];
     const double ex = mi_delta(pi.x, pj.x, P.L, P.invL);
     const double ey = mi_delta(pi.y, pj.y, P.L, P.invL);
     const double ez = mi_delta(pi.z, pj.z, P.L, P.invL);
@@ -836,6 +845,12 @@ __device__ __forceinline__ void pair_force_tab(const Params& P, const StepTabs& 
     fx -= to_fix(f * ex, err);
     fy -= to_fix(f * ey, err);
     fz -= to_fix(f * ez, err);
+}
+
+__device__ __forceinline__ void pair_force_tab(const Params& P, const StepTabs& T, uint32_t* err, float4 pi,
+                                               float4 pj, uint32_t ti, long long& fx, long long& fy,
+                                               long long& fz) {
+    if (!pair_force_f32(P, T, err, pi, pj, ti, fx, fy, fz)) pair_force_f64(P, T, err, pi, pj, ti, fx, fy, fz);
 }
 
 // Bond force on site i from partner j (bond type bt), FP64 from the exact
