@@ -121,3 +121,48 @@ def test_checkpoint_rejections_leave_the_state_alone():
             assert e.value.name == "DB_EINVAL" and "set up differently" in str(e.value)
         b.load_checkpoint(ck)
         assert b.save_checkpoint() == ck
+
+
+def test_resume_at_full_size_of_the_timed_gel():
+    """The 200k gel of the benchmark: saved at an unaligned step after 1200
+    steps (a renumbering and list builds behind it), resumed in a fresh
+    system, 130 steps later bit-identical to the unbroken run."""
+    w = inputs.gel(seed=1)
+    log(f"case checkpoint gel n={w.n}")
+    _, c = _split_run(w, 1237, 130)
+    assert c[:, 1].sum() > 0
+
+
+def test_resume_in_another_process(tmp_path):
+    """A checkpoint written to a file and loaded by another process (its own
+    HIP context and allocations) continues exactly as the unbroken run."""
+    import os
+    import subprocess
+    import sys
+
+    w = inputs.telechelic(seed=6)
+    ck_file, out_file = tmp_path / "run.ckpt", tmp_path / "resumed.npz"
+    log("case checkpoint across processes")
+    with db.System.from_workload(w) as a:
+        a.step(101)
+        ck_file.write_bytes(a.save_checkpoint())
+        a.step(99)
+        ref = (a.positions(), a.velocities(), a.bonds(), counters(a))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    child = (
+        "import sys, numpy as np\n"
+        f"sys.path.insert(0, {root!r}); sys.path.insert(0, {os.path.join(root, 'tests')!r})\n"
+        "from paper_2609_21204_amd import dybond as db, inputs\n"
+        "from test_gpu_parity import counters\n"
+        "w = inputs.telechelic(seed=6)\n"
+        "with db.System.from_workload(w) as b:\n"
+        f"    b.load_checkpoint(open({str(ck_file)!r}, 'rb').read())\n"
+        "    b.step(99)\n"
+        f"    np.savez({str(out_file)!r}, pos=b.positions(), vel=b.velocities(), bonds=b.bonds(), ctr=counters(b))\n"
+    )
+    r = subprocess.run([sys.executable, "-c", child], capture_output=True, text=True, timeout=150)
+    assert r.returncode == 0, r.stderr[-2000:]
+    got = np.load(out_file)
+    for name, x, y in zip(("positions", "velocities", "bonds", "counters"), ref,
+                          (got["pos"], got["vel"], got["bonds"], got["ctr"])):
+        assert x.shape == y.shape and np.array_equal(x, y), f"{name} differ after resuming in another process"
