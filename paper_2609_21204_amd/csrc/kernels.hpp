@@ -429,14 +429,14 @@ __device__ __forceinline__ unsigned long long advance_particle(const Params& P, 
 }
 
 constexpr int kTileThreads = 512;
-// The tables of one tile fit 35 KB of LDS, so that four 512-thread
+// The tables of one tile fit 32 KB of LDS, so that four 512-thread
 // workgroups share a CU (twice the tables, 1728 halo cells and 2048 entries,
 // allowed two and made the 200k gel's step 2 % slower).
 constexpr int kTileMaxHalo = 1000;      // halo cells of one tile, (t+2)^3 <= 1000 (t <= 8)
 constexpr int kTileMaxEntries = 1024;   // particles staged in LDS per tile
 constexpr int kTileChunk = (kTileMaxHalo + kTileThreads - 1) / kTileThreads;   // halo cells per thread in the scan
 constexpr int kTileLoads = kTileMaxEntries / kTileThreads;                     // staged entries per thread
-constexpr int kTileMaxCore = 512;       // core particles whose candidates are dealt out evenly
+constexpr int kTileMaxCore = 512;       // core particles whose stencil rows are dealt out as work items
 
 // Workgroups are dealt round-robin to the 8 XCDs.  This remaps the workgroup
 // id so that each XCD gets a contiguous run of work items (particles are kept
@@ -467,17 +467,20 @@ __device__ __forceinline__ void nl_consider(const Params& P, const Dev& D, const
 // its one-cell halo are scanned in LDS, the halo's particles (position +
 // index/type words) are staged in LDS (each thread issues its loads together,
 // locating its entries' cells by binary search over the scanned offsets),
-// and each thread takes one particle of the tile core and visits its 27
-// neighbour cells as 9 contiguous LDS ranges.  Tiles whose halo holds more
-// than kTileMaxEntries particles read the same stencil from global memory.
+// and the stencils of the core particles are scanned as work items of one
+// particle and one row of 3 cells (9 per particle, each a contiguous LDS
+// range) dealt out round robin over the threads.  Tiles with more than
+// kTileMaxCore core particles visit each particle's 27 cells in one thread,
+// and tiles whose halo holds more than kTileMaxEntries particles read the
+// same stencil from global memory.
 // Does nothing unless the rebuild flag `f3` (set by k_step when a particle
 // has moved by more than skin / 2, or by a renumbering) is set; the grid is
 // a few hundred workgroups, so that the launch is cheap when nothing moved
 // that far.  Reads cell list rflag[3] (filled by k_binr) and empties the
 // core cells of the other one, which the next build fills.  Compiled for 8
-// waves per SIMD (56 VGPRs, four workgroups per CU; at 57 VGPRs only three
-// fit): the build's phases are latency-bound, and the fourth workgroup cut
-// its time by 11 % at 4 M and 16 M particles.
+// waves per SIMD (four workgroups per CU; at 57 VGPRs only three fit): the
+// build's phases are latency-bound, and the fourth workgroup cut its time by
+// 11 % at 4 M and 16 M particles.
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_nlist(const Params P, const Dev D, int f3) {
     if (D.rflag[f3] == 0u) return;
     const int lst = (int)D.rflag[3];
@@ -489,7 +492,6 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     __shared__ uint16_t ecell[kTileMaxEntries];    // halo cell of each staged entry
     __shared__ uint16_t core[kTileMaxEntries];     // staged entries that lie in the tile core
     __shared__ uint8_t hshift[kTileMaxHalo];       // periodic image of each halo cell (2 bits per axis)
-    __shared__ uint32_t pstart[kTileMaxCore + 1];  // first candidate of each core particle
     __shared__ uint32_t pcnt[kTileMaxCore];        // neighbours found so far
     __shared__ uint16_t prow0[kTileMaxCore];       // first halo row of its 3 x 3 x 3 stencil
     __shared__ uint32_t ncore;
@@ -628,79 +630,30 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         }
         __syncthreads();
         if (ncore <= (uint32_t)kTileMaxCore) {
-            // candidates of each core particle: its 9 stencil rows of 3
-            // cells; they are numbered consecutively over the core particles
-            // and each thread takes an equal run of them
-            uint32_t sz[2] = {0u, 0u};
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const uint32_t p = 2u * tid + (uint32_t)k;
-                if (p < ncore) {
-                    int ix, iy, iz;
-                    split(ecell[core[p]], ix, iy, iz);
-                    const int hr0 = ((iz - 1) * hy + (iy - 1)) * hx + (ix - 1);
-                    uint32_t c = 0;
-#pragma unroll
-                    for (int r = 0; r < 9; ++r) {
-                        const int hr = hr0 + ((r / 3) * hy + (r % 3)) * hx;
-                        c += hoff[hr + 3] - hoff[hr];
-                    }
-                    prow0[p] = (uint16_t)hr0;
-                    pcnt[p] = 0u;
-                    sz[k] = c;
-                }
+            // work items: (core particle, stencil row), 9 rows of 3 cells per
+            // particle, each a contiguous range of staged entries; items are
+            // dealt out round robin
+            for (uint32_t p = tid; p < ncore; p += kTileThreads) {
+                int ix, iy, iz;
+                split(ecell[core[p]], ix, iy, iz);
+                prow0[p] = (uint16_t)(((iz - 1) * hy + (iy - 1)) * hx + (ix - 1));
+                pcnt[p] = 0u;
             }
-            uint32_t ctot;
-            const uint32_t run0 = block_exclusive_scan(sz[0] + sz[1], &ctot);
-            if (2u * tid < ncore) pstart[2u * tid] = run0;
-            if (2u * tid + 1u < ncore) pstart[2u * tid + 1u] = run0 + sz[0];
-            if (tid == 0) pstart[ncore] = ctot;
             __syncthreads();
-            const uint32_t per = (ctot + kTileThreads - 1) / kTileThreads;
-            uint32_t c = tid * per;
-            const uint32_t cend = min(c + per, ctot);
-            if (c < cend) {
-                uint32_t p = 0;                   // last p with pstart[p] <= c
-#pragma unroll
-                for (uint32_t step = kTileMaxCore / 2; step >= 1; step >>= 1)
-                    if (p + step < ncore && pstart[p + step] <= c) p += step;
-                uint32_t ep = core[p];
-                float4 pi = ent[ep];
-                uint32_t hr0 = prow0[p];
+            for (uint32_t it = tid; it < 9u * ncore; it += kTileThreads) {
+                const uint32_t p = it / 9u, r = it - 9u * p;
+                const uint32_t ep = core[p];
+                const float4 pi = ent[ep];
+                const uint32_t hr = prow0[p] + ((r / 3u) * (uint32_t)hy + (r % 3u)) * (uint32_t)hx;
+                const uint32_t lo = hoff[hr], hi = hoff[hr + 3];
                 const float* rrow = rl2 + slot_type(pi) * kMaxTypes;
-                uint32_t o = c - pstart[p], r = 0, lo = hoff[hr0], hi = hoff[hr0 + 3];
-                while (o >= hi - lo) {
-                    o -= hi - lo;
-                    ++r;
-                    const uint32_t hr = hr0 + ((r / 3) * hy + (r % 3)) * hx;
-                    lo = hoff[hr];
-                    hi = hoff[hr + 3];
-                }
-                uint32_t e2 = lo + o;
-                for (;;) {
-                    if (e2 != ep) {
-                        const float4 q = ent[e2];
-                        const float dx = q.x - pi.x, dy = q.y - pi.y, dz = q.z - pi.z;
-                        if (dx * dx + dy * dy + dz * dz < rrow[slot_type(q)]) {
-                            const uint32_t k = atomicAdd(&pcnt[p], 1u);
-                            if (k < P.nlmax) D.nl[(size_t)k * P.n + slot_index(pi)] = slot_index(q);
-                        }
-                    }
-                    if (++c >= cend) break;
-                    ++e2;
-                    while (e2 >= hi) {            // next non-empty row, next particle
-                        if (++r == 9) {
-                            ++p;
-                            r = 0;
-                            ep = core[p];
-                            pi = ent[ep];
-                            hr0 = prow0[p];
-                            rrow = rl2 + slot_type(pi) * kMaxTypes;
-                        }
-                        const uint32_t hr = hr0 + ((r / 3) * hy + (r % 3)) * hx;
-                        lo = hoff[hr];
-                        hi = hoff[hr + 3];
-                        e2 = lo;
+                for (uint32_t e2 = lo; e2 < hi; ++e2) {
+                    if (e2 == ep) continue;
+                    const float4 q = ent[e2];
+                    const float dx = q.x - pi.x, dy = q.y - pi.y, dz = q.z - pi.z;
+                    if (dx * dx + dy * dy + dz * dz < rrow[slot_type(q)]) {
+                        const uint32_t k = atomicAdd(&pcnt[p], 1u);
+                        if (k < P.nlmax) D.nl[(size_t)k * P.n + slot_index(pi)] = slot_index(q);
                     }
                 }
             }
