@@ -765,3 +765,26 @@ def test_device_readouts_match_host_readouts():
         assert np.array_equal(out2.cpu().numpy(), s.positions())
         with pytest.raises(db.DybondError):
             db.db_read_positions_device(s.h, 0, None)
+
+
+def test_full_replica_set_batched_matches_plain_on_samples():
+    """The benchmark's batch as it is timed: all 1024 replicas of the sweep
+    set (seed 1, sizes 256..8192) in one db_step_batch call under the
+    stored default plan, 130 steps (13 sweeps); 12 replicas spread over the
+    size range, run one by one with db_step, match their batched copies bit
+    for bit."""
+    reps = inputs.replica_set(seed=1, count=1024)
+    order = sorted(range(len(reps)), key=lambda k: reps[k].n)
+    picks = [order[int(round(q * (len(order) - 1) / 11))] for q in range(12)]
+    log("case full replica set: samples " + " ".join(str(reps[k].n) for k in picks))
+    batch = [db.System.from_workload(w) for w in reps]
+    plain = {k: db.System.from_workload(reps[k]) for k in picks}
+    try:
+        db.db_step_batch([b.h for b in batch], 130)
+        for k, p in plain.items():
+            p.step(130)
+            _assert_same_state(p, batch[k], f"replica {k} (n={reps[k].n})")
+        assert sum(int(counters(p)[:, 1].sum()) for p in plain.values()) > 0
+    finally:
+        for x in batch + list(plain.values()):
+            x.close()
