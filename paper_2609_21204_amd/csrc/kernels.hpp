@@ -1001,17 +1001,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     }
 }
 
-// One BAOAB step t -> s = t + 1 with one thread per particle, for short
-// neighbour lists: the thread issues its particle's loads (position,
-// velocity, list position, tag, list length, the first 4 list entries and 4
-// bond words) together, then the 4 neighbour and 4 partner positions
-// together, takes further list entries 4 at a time the same way, and goes
-// on to the integration with its force in registers (no LDS reduction, one
-// barrier).  Same arguments and the same result bit for bit as k_step<TPP>.
+// One BAOAB step t -> s = t + 1 with one thread per particle (the default
+// for large systems): the thread issues its particle's loads (position,
+// velocity, list position, tag, list length, the first 4 list entries and 2
+// bond words) together, then the 4 neighbour and 2 partner positions
+// together, takes further list entries 4 at a time the same way and further
+// bond slots one by one, and goes on to the integration with its force in
+// registers (no LDS reduction, one barrier).  Same arguments and the same
+// result bit for bit as k_step<TPP>.  Compiled for 6 waves per SIMD (78
+// VGPRs, no spill): with 4 bond words up front it took 88 VGPRs and ran 5,
+// 4 % slower at 4 M and 16 M particles; 8 waves spill.
 template <bool EXT = false>
-__global__ __launch_bounds__(256) void k_step1(const Params P, const Dev D, int xin, int sp,
-                                               int f3, int accum_ke) {
-    constexpr int Q = 4, BQ = 4;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_step1(const Params P, const Dev D, int xin, int sp,
+                                                                                       int f3, int accum_ke) {
+    constexpr int Q = 4, BQ = 2;
     __shared__ StepTabs T;
     const uint32_t tid = threadIdx.x;
     const uint32_t i = xcd_block() * 256u + tid;
