@@ -287,9 +287,12 @@ DB_API db_status db_commit(db_system* sys);
  * update and before the forces at the new positions; each sweep forms bonds
  * with P_on = P0_on exp(-U_b(r)/kT) and breaks the bonds present at its
  * start with P0_off (Eq. pon, Eq. probs).  Synchronous: returns when the
- * GPU work is done.  Errors: DB_ESTATE (not committed, invalid state),
- * DB_EDEVICE; DB_EBOND / DB_EOVERFLOW leave the state invalid (DB_ESTATE)
- * until db_set_state. */
+ * GPU work is done.  A system of at most 768 particles advanced by 200 or
+ * more steps in one call, with the automatic launch shape, runs as a batch
+ * of one (db_step_batch): one workgroup takes every step, with the same
+ * result bit for bit.  Errors: DB_ESTATE (not committed, invalid state),
+ * DB_EDEVICE, DB_ENOMEM; DB_EBOND / DB_EOVERFLOW leave the state invalid
+ * (DB_ESTATE) until db_set_state. */
 DB_API db_status db_step(db_system* sys, uint64_t n_steps);
 
 /* Launch plan of a batch (db_step_batch): the systems fall into size

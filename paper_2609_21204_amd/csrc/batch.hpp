@@ -361,6 +361,7 @@ void k_batch(const BatchItem* __restrict__ items, BatchState* __restrict__ state
             // neighbour lists at x_{t+1}: cell list lcur emptied, filled,
             // then read by the build (steps without a build bin nothing)
             for (uint32_t c = tid; c < P.ncell; c += bs) D.ccount[lcur][c] = 0u;
+            if (tid == 0) ++D.rflag[4];       // builds so far, as db_step counts them
             __syncthreads();
             if constexpr (LX) {
                 for (uint32_t i = tid; i < n; i += bs) bin_index_wg(P, D, lcur, i, Xn[i]);

@@ -788,3 +788,31 @@ def test_full_replica_set_batched_matches_plain_on_samples():
     finally:
         for x in batch + list(plain.values()):
             x.close()
+
+
+def test_small_system_one_workgroup_path_matches_grid_kernels():
+    """db_step on a system of at most 768 particles, 200 or more steps per
+    call and the automatic launch shape, runs as a batch of one; the same
+    system under a caller-chosen shape runs the grid kernels: both give the
+    same trajectory bit for bit, through long and short calls, in the lean
+    variant (set point and kinetic temperature) and the full one (melting
+    under the kinetic temperature)."""
+    from test_gpu_modifiers import _melt_half_bound, _small
+    cases = [(inputs.small(seed=12), db.DB_KT_SETPOINT), (inputs.small(seed=13), db.DB_KT_KINETIC),
+             (_small(14, melt=_melt_half_bound()), db.DB_KT_KINETIC)]
+    for k, (w, kt) in enumerate(cases):
+        log(f"case one-workgroup path, system {k} (n={w.n})")
+        one = db.System.from_workload(w, kt_source=kt)
+        grid = db.System.from_workload(w, kt_source=kt)
+        try:
+            db.db_set_step_shape(grid.h, 32, 0)
+            b0 = db.db_read_list_builds(one.h)
+            for n_steps in (300, 7, 233):
+                one.step(n_steps)
+                grid.step(n_steps)
+                _assert_same_state(one, grid, f"system {k} after a call of {n_steps} steps")
+            assert db.db_read_list_builds(one.h) > b0
+            assert counters(one)[0, 1] > 0
+        finally:
+            one.close()
+            grid.close()
