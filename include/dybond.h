@@ -245,9 +245,8 @@ DB_API db_status db_set_matching(db_system* sys, uint32_t grid_rounds, uint32_t 
 
 /* Launch shape of the step kernel and the proposal kernel of the sweep:
  * threads that share one particle (1, 2, 4, 8, 16 or 32, both kernels; 0 =
- * automatic: 4 in the step kernel, or more for small systems so that a
- * launch fills the GPU, and half that in the proposal kernel; from 1.5 M
- * particles on, 1 in the step kernel and 2 in the proposal kernel) and, with 4
+ * automatic: 8 in both below 32 768 particles, 4 in the step kernel and 2
+ * in the proposal kernel up to 1.5 M particles, 1 and 2 from there on) and, with 4
  * threads per particle, how many neighbour-list entries each thread loads
  * before its first gather (1, 2 or 4; 0 = automatic: 1; the next three
  * entries per thread of a longer list are loaded with the first gathers,

@@ -518,22 +518,22 @@ void apply_temperature(db_system* s) {
         }
 }
 
-// threads per particle: 4, or more for small systems so that a launch has
-// at least 2^19 threads
-uint32_t auto_tpp(uint32_t n) {
-    uint32_t t = 4;
-    while (t < 32 && (uint64_t)n * t < 524288ull) t *= 2;
-    return t;
-}
-
-// Threads per particle of the step kernel: auto_tpp, except for large
-// systems, whose data no longer sits in the Infinity Cache: there one thread
-// per particle (k_step1, whose loads for a particle are all in flight
-// together and which needs no LDS reduction) beats four, 2 M particles 3.7 %
-// faster per step, 4 M 6.6 %, 16 M 7.9 %; at 1 M the two are equal and at
-// 200k four threads are 17 % faster.
-constexpr uint32_t kStepOneThreadN = 1500000u;
-uint32_t auto_step_tpp(uint32_t n) { return n >= kStepOneThreadN ? 1u : auto_tpp(n); }
+// Automatic launch shapes (threads per particle) of the step kernel and of
+// the proposal kernel, measured on the gel and the sweep replicas (µs per
+// step, shapes given as step / proposal threads):
+//  - below 32 768 particles 8 / 8: 10 500 particles 13.4 against 14.1 at
+//    4 / 4 and 18.0 at 32 / 16 (the earlier rule of at least 2^19 threads
+//    per launch), 20 000 particles 17.8 against 18.7 and 26.2;
+//  - up to 1.5 M particles 4 / 2: 50 000 particles 21.7 against 22.0 at
+//    8 / 8, 200 000 particles 35.9 against 40.3;
+//  - from 1.5 M particles on 1 / 2: once the state no longer sits in the
+//    Infinity Cache, one thread per particle (k_step1, whose loads for a
+//    particle are all in flight together and which needs no LDS reduction)
+//    beats four: 2 M particles 3.7 % faster per step, 4 M 6.6 %, 16 M 7.9 %
+//    (equal at 1 M).
+constexpr uint32_t kStepEightThreadN = 32768u, kStepOneThreadN = 1500000u;
+uint32_t auto_step_tpp(uint32_t n) { return n >= kStepOneThreadN ? 1u : (n < kStepEightThreadN ? 8u : 4u); }
+uint32_t auto_propose_tpp(uint32_t n) { return n < kStepEightThreadN ? 8u : 2u; }
 
 void fill_params(db_system* s) {
     Params& P = s->P;
@@ -646,7 +646,7 @@ void fill_params(db_system* s) {
     // sites more numerous per pass (13.3 vs 15.9 us per reaction at 200k
     // particles with 2 vs 4 threads, 145 vs 168 us at 4 M)
     P.tpp_step = s->tpp_user ? s->tpp_user : auto_step_tpp(s->n);
-    P.tpp = s->tpp_user ? s->tpp_user : std::max(1u, auto_tpp(s->n) / 2);
+    P.tpp = s->tpp_user ? s->tpp_user : auto_propose_tpp(s->n);
     P.qb_step = P.tpp_step == 4 ? s->qb_user : 0u;
     // build positions are packed to a 21-bit grid (xref_pack): the test takes
     // the grid's half spacing and the FP32 rounding of its decoding off skin / 2
@@ -1416,7 +1416,7 @@ db_status db_set_step_shape(db_system* s, uint32_t tpp, uint32_t list_batch) {
         HIPCHK(s, hipStreamSynchronize(s->stream));
         destroy_graphs(s);
         s->P.tpp_step = tpp ? tpp : auto_step_tpp(s->n);
-        s->P.tpp = tpp ? tpp : std::max(1u, auto_tpp(s->n) / 2);
+        s->P.tpp = tpp ? tpp : auto_propose_tpp(s->n);
         s->P.qb_step = s->P.tpp_step == 4 ? list_batch : 0u;
     }
     return DB_OK;

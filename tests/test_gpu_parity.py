@@ -675,7 +675,7 @@ def test_batch_with_the_smallest_systems():
                 x.close()
 
 
-@pytest.mark.parametrize("shape", [(1, 0), (2, 0), (4, 1), (4, 2), (8, 0)])
+@pytest.mark.parametrize("shape", [(1, 0), (2, 0), (4, 1), (4, 2), (16, 0), (32, 0)])
 def test_step_shape_does_not_change_results(shape):
     """Any launch shape of the step and proposal kernels (threads per
     particle, list entries loaded up front) gives the same trajectory bit for
