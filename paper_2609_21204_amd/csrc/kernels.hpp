@@ -261,23 +261,44 @@ __device__ __forceinline__ Force3 force_on(const Params& P, const Dev& D, const 
     return fix_to_force(D, fx, fy, fz);
 }
 
-// Insert particle i (position p) into cell list `lst`.
-__device__ __forceinline__ void bin_particle(const Params& P, const Dev& D, int lst, uint32_t i, float4 p) {
-    const int c = (cell_coord(p.z, P) * (int)P.nc + cell_coord(p.y, P)) * (int)P.nc + cell_coord(p.x, P);
-    const uint32_t slot = atomicAdd(&D.ccount[lst][c], 1u);
-    if (slot < P.cellcap)
-        D.cpos[lst][cell_slot(P, (uint32_t)c, slot)] = make_float4(p.x, p.y, p.z, __uint_as_float(i | (type_of(p) << 24)));
-    else atomicOr(&D.err[0], kErrOverflow);
-}
-
 __global__ void k_clear_counts(const Params P, const Dev D, int lst) {
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell; c += gridDim.x * blockDim.x)
         D.ccount[lst][c] = 0u;
 }
 
+// Insert one wave's particles (lanes with `valid`) into cell list `lst`,
+// with one counter atomic per run of consecutive lanes in the same cell:
+// particles are numbered in cell order, so a wave's 64 lanes fall into a
+// few such runs, and same-address atomics are taken one at a time.  Each
+// lane's slot is the run's base plus its place in the run.  All 64 lanes
+// must call this together.
+__device__ __forceinline__ void bin_wave(const Params& P, const Dev& D, int lst, uint32_t i, bool valid,
+                                         float4 p) {
+    const int c = valid ? (cell_coord(p.z, P) * (int)P.nc + cell_coord(p.y, P)) * (int)P.nc + cell_coord(p.x, P)
+                        : -1;
+    const uint32_t lane = __lane_id();
+    const int cprev = __shfl_up(c, 1u, 64);
+    const bool head = lane == 0u || c != cprev;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = (2ull << lane) - 1ull;         // lanes 0..lane (all for lane 63)
+    const uint32_t h = 63u - (uint32_t)__clzll((long long)(heads & upto));   // this lane's run head
+    const unsigned long long above = heads & ~upto;
+    const uint32_t next = above ? (uint32_t)__ffsll((long long)above) - 1u : 64u;
+    uint32_t base = 0;
+    if (head && valid) base = atomicAdd(&D.ccount[lst][c], next - lane);
+    base = __shfl(base, (int)h, 64);
+    if (valid) {
+        const uint32_t slot = base + (lane - h);
+        if (slot < P.cellcap)
+            D.cpos[lst][cell_slot(P, (uint32_t)c, slot)] = make_float4(p.x, p.y, p.z, __uint_as_float(i | (type_of(p) << 24)));
+        else atomicOr(&D.err[0], kErrOverflow);
+    }
+}
+
 __global__ void k_bin(const Params P, const Dev D, int xin, int lst) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P.n) bin_particle(P, D, lst, i, D.x[xin][i]);
+    const bool valid = i < P.n;
+    bin_wave(P, D, lst, i, valid, valid ? D.x[xin][i] : make_float4(0.f, 0.f, 0.f, 0.f));
 }
 
 // Cell lists: lists 0 and 1 take turns holding the positions of the latest
@@ -293,7 +314,8 @@ constexpr int kSortList = 2;
 __global__ void k_binr(const Params P, const Dev D, int xin, int f3) {
     if (D.rflag[f3] == 0u) return;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P.n) bin_particle(P, D, (int)D.rflag[3], i, D.x[xin][i]);
+    const bool valid = i < P.n;
+    bin_wave(P, D, (int)D.rflag[3], i, valid, valid ? D.x[xin][i] : make_float4(0.f, 0.f, 0.f, 0.f));
 }
 
 // Forces (and per-particle energies) at the current positions into f4[off + i].
