@@ -641,10 +641,11 @@ void fill_params(db_system* s) {
             const double rl = need > 0.0 ? need + skin : 0.0;
             P.rl2[a * kMaxTypes + b] = (float)(rl * rl * (1.0 + 1e-4));
         }
-    // the proposal kernel takes half the step kernel's threads per site by
-    // default: its scan is shorter (4 list entries up front) and its listed
-    // sites more numerous per pass (13.3 vs 15.9 us per reaction at 200k
-    // particles with 2 vs 4 threads, 145 vs 168 us at 4 M)
+    // from 32 768 particles on, the proposal kernel takes 2 threads per site
+    // by default: its scan is shorter (4 list entries up front) and its
+    // listed sites more numerous per pass (13.3 vs 15.9 us per reaction at
+    // 200k particles with 2 vs 4 threads, 145 vs 168 us at 4 M); below, 8
+    // like the step kernel (auto_propose_tpp)
     P.tpp_step = s->tpp_user ? s->tpp_user : auto_step_tpp(s->n);
     P.tpp = s->tpp_user ? s->tpp_user : auto_propose_tpp(s->n);
     P.qb_step = P.tpp_step == 4 ? s->qb_user : 0u;
