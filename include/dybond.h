@@ -287,9 +287,10 @@ DB_API db_status db_commit(db_system* sys);
  * with P_on = P0_on exp(-U_b(r)/kT) and breaks the bonds present at its
  * start with P0_off (Eq. pon, Eq. probs).  Synchronous: returns when the
  * GPU work is done.  A system of at most 768 particles advanced by 200 or
- * more steps in one call, with the automatic launch shape, runs as a batch
- * of one (db_step_batch): one workgroup takes every step, with the same
- * result bit for bit.  Errors: DB_ESTATE (not committed, invalid state),
+ * more steps in one call, with the automatic launch shape, can run as a
+ * batch of one (db_step_batch: one workgroup takes every step) instead of
+ * the grid kernels, with the same result bit for bit: the first such call
+ * times 100 steps on each and later calls keep the faster.  Errors: DB_ESTATE (not committed, invalid state),
  * DB_EDEVICE, DB_ENOMEM; DB_EBOND / DB_EOVERFLOW leave the state invalid
  * (DB_ESTATE) until db_set_state. */
 DB_API db_status db_step(db_system* sys, uint64_t n_steps);

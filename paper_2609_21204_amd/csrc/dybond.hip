@@ -118,6 +118,9 @@ struct db_system {
     bool tags_dirty = false;               // device tag/rtag changed since the host mirrors were read
     bool sort_enabled = true;              // renumber particles in cell order (every kSortPeriod steps)
     uint64_t sort_due = 0;                 // step from which the next renumbering is due
+    int path_pick = 0;                     // long calls on a small system: 0 not measured, 1 one workgroup, 2 grid
+    bool path_pending = false;             // a measurement of the two paths awaits the end of the call
+    hipEvent_t path_ev[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -1009,26 +1012,81 @@ db_status prepare_graphs(db_system* s) {
 db_status run_batch(db_system* const* systems, uint32_t count, uint64_t nsteps, const db_batch_plan& plan,
                     float* ms);
 
-// Small systems advanced by many steps in one call run as a batch of one
+// Small systems advanced by many steps in one call can run as a batch of one
 // (one 1024-thread workgroup runs every step, barriers in place of kernel
-// launches; bitwise the same trajectory): a 512-particle step is then ~10
-// instead of ~14 us, where the grid kernels are bound by their launches.
-// Above ~850 particles one CU is slower than the whole GPU; below 200 steps
-// per call the batch's per-call set-up is not repaid.  Not taken with a
+// launches; bitwise the same trajectory).  Which is faster depends on the
+// system, not only on its size: a 512-particle dimer gas at density 0.1
+// takes 9.5 us per step that way against 12.5 us on the grid kernels, but
+// sweep replicas of 257 to 684 particles at densities 0.08 to 0.39 take
+// 12.8 to 18.8 us against 12.0 to 14.3 us.  So the first call of at least
+// 2 kPathTrial steps on such a system runs kPathTrial steps on each path
+// between events, and the end of that call keeps the faster path for every
+// later call (path_pick).  kPathTrial stays below the shortest span graph
+// (120 steps), so the grid's part replays only graphs captured before the
+// first event (prepare_graphs; spans are captured when first used, and a
+// capture inside the timed part would leave the GPU idle and count against
+// the grid).  Above kOneGroupMaxN particles one CU is slower than
+// the whole GPU (sweep replicas of 800 to 1030 particles: 15.6 to 19.3 us
+// against 12.4 to 14.5); below kOneGroupMinSteps steps per call the batch's
+// per-call set-up is not repaid.  Neither path is measured or taken with a
 // caller-chosen launch shape, with graphs off or with kernel timing on.
 constexpr uint32_t kOneGroupMaxN = 768;
 constexpr uint64_t kOneGroupMinSteps = 200;
+constexpr uint64_t kPathTrial = 100;
+static_assert(kPathTrial < 120, "the grid's timed part must not need a span graph");
+
+db_status run_one_group(db_system* s, uint64_t nsteps) {
+    db_batch_plan plan{};
+    plan.n_classes = 1;
+    plan.n_max[0] = 0xFFFFFFFFu;
+    plan.threads[0] = (uint32_t)kBatchMaxThreads;
+    db_system* one[1] = {s};
+    return run_batch(one, 1, nsteps, plan, nullptr);
+}
+
+db_status run_grid(db_system* s, uint64_t nsteps);
 
 db_status run_steps(db_system* s, uint64_t nsteps) {
-    if (s->use_graphs && !s->timing.on && s->tpp_user == 0 && s->n <= kOneGroupMaxN &&
-        nsteps >= kOneGroupMinSteps) {
-        db_batch_plan plan{};
-        plan.n_classes = 1;
-        plan.n_max[0] = 0xFFFFFFFFu;
-        plan.threads[0] = (uint32_t)kBatchMaxThreads;
-        db_system* one[1] = {s};
-        return run_batch(one, 1, nsteps, plan, nullptr);
+    const bool small = s->use_graphs && !s->timing.on && s->tpp_user == 0 && s->n <= kOneGroupMaxN &&
+                       nsteps >= kOneGroupMinSteps;
+    if (!small || s->path_pick == 2) return run_grid(s, nsteps);
+    if (s->path_pick == 0 && !s->path_pending && nsteps >= 2 * kPathTrial) {
+        // the grid's graphs are captured before the first event, so that
+        // their set-up is not timed
+        for (auto& e : s->path_ev)
+            if (!e) HIPCHK(s, hipEventCreate(&e));
+        if (s->graphs.empty()) {
+            const db_status st = prepare_graphs(s);
+            if (st != DB_OK) return st;
+        }
+        HIPCHK(s, hipEventRecord(s->path_ev[0], s->stream));
+        db_status st = run_grid(s, kPathTrial);
+        if (st != DB_OK) return st;
+        HIPCHK(s, hipEventRecord(s->path_ev[1], s->stream));
+        st = run_one_group(s, kPathTrial);
+        if (st != DB_OK) return st;
+        HIPCHK(s, hipEventRecord(s->path_ev[2], s->stream));
+        s->path_pending = true;
+        nsteps -= 2 * kPathTrial;
     }
+    if (nsteps == 0) return DB_OK;
+    return nsteps >= kOneGroupMinSteps ? run_one_group(s, nsteps) : run_grid(s, nsteps);
+}
+
+// After a call that measured both paths has synchronised: keep the faster.
+void settle_path(db_system* s) {
+    if (!s->path_pending) return;
+    s->path_pending = false;
+    float grid_ms = 0.f, one_ms = 0.f;
+    if (hipEventElapsedTime(&grid_ms, s->path_ev[0], s->path_ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&one_ms, s->path_ev[1], s->path_ev[2]) != hipSuccess) {
+        (void)hipGetLastError();           // measured again by a later call
+        return;
+    }
+    s->path_pick = one_ms <= grid_ms ? 1 : 2;
+}
+
+db_status run_grid(db_system* s, uint64_t nsteps) {
     const uint64_t span = graph_span(s), per = graph_period(s);
     const bool graphs = s->use_graphs && !s->timing.on;
     if (graphs && s->graphs.empty()) {
@@ -1213,6 +1271,8 @@ void db_destroy(db_system* s) {
         for (auto e : s->timing.pool) (void)hipEventDestroy(e);
         if (s->ev_out) (void)hipEventDestroy(s->ev_out);
         if (s->ev_back) (void)hipEventDestroy(s->ev_back);
+        for (auto e : s->path_ev)
+            if (e) (void)hipEventDestroy(e);
         if (s->err_h) (void)hipHostFree(s->err_h);
         for (void* p : s->allocs) (void)hipFree(p);
         if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
@@ -1595,7 +1655,9 @@ db_status db_step(db_system* s, uint64_t nsteps) {
     HIPCHK(s, hipSetDevice(s->device));
     st = run_steps(s, nsteps);
     if (st != DB_OK) return st;
-    return check_errors(s);
+    st = check_errors(s);
+    if (st == DB_OK) settle_path(s);
+    return st;
 }
 
 }  // extern "C"

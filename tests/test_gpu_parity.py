@@ -796,7 +796,10 @@ def test_small_system_one_workgroup_path_matches_grid_kernels():
     system under a caller-chosen shape runs the grid kernels: both give the
     same trajectory bit for bit, through long and short calls, in the lean
     variant (set point and kinetic temperature) and the full one (melting
-    under the kinetic temperature)."""
+    under the kinetic temperature).  The first call (300 steps) times 100
+    steps on each path (grid kernels, then a batch of one) and ends with 100
+    on the grid kernels; the later calls of 200 or more steps take the path
+    that measured faster."""
     from test_gpu_modifiers import _melt_half_bound, _small
     cases = [(inputs.small(seed=12), db.DB_KT_SETPOINT), (inputs.small(seed=13), db.DB_KT_KINETIC),
              (_small(14, melt=_melt_half_bound()), db.DB_KT_KINETIC)]
@@ -807,7 +810,7 @@ def test_small_system_one_workgroup_path_matches_grid_kernels():
         try:
             db.db_set_step_shape(grid.h, 32, 0)
             b0 = db.db_read_list_builds(one.h)
-            for n_steps in (300, 7, 233):
+            for n_steps in (300, 7, 233, 450, 260):
                 one.step(n_steps)
                 grid.step(n_steps)
                 _assert_same_state(one, grid, f"system {k} after a call of {n_steps} steps")
